@@ -1,0 +1,284 @@
+"""Float64 CPU oracle for the EA Heisenberg spin-glass sweep -- TEST INFRASTRUCTURE.
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. It wraps ``hsg_oracle.c`` (plain serial C,
+float64, built with ``-O2 -ffp-contract=off`` and no fast-math) through ctypes,
+with the same call names as the HIP library so that the tests can drive both
+identically. It shares no code with the HIP path.
+
+Functions and what pins them (details in the tests):
+
+* ``philox``            -- rocRAND's independent Philox4x32-10 (host build);
+* ``frame``             -- orthonormality and handedness;
+* ``hb_draw``           -- von Mises-Fisher moments (Langevin function), the CDF;
+* ``or_reflect``        -- Eq. (3) invariants: |s'| = 1, s'.h = s.h, involution;
+* ``energy``            -- explicit bond list on L = 4, ferro / Neel ground states;
+* ``Oracle.sweep``      -- single spin in a field, open 1D chain, OR energy
+                           conservation, infinite temperature, site-order
+                           independence of a half-sweep;
+* ``Oracle.pt_exchange``-- acceptance frequency against min(1, e^Delta);
+* ``Oracle.measure_overlap`` -- q^2 = 1 for identical aligned copies, O(3)
+                           invariance, trace identity.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+STORAGE_MODES = {"f32": 0, "f16": 1, "bf16": 2, "qangle": 3}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (serial, float64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+class Cfg(C.Structure):
+    _fields_ = [("L", C.c_int32), ("n_samples", C.c_int32), ("n_copies", C.c_int32),
+                ("n_temps", C.c_int32), ("n_hb", C.c_int32), ("n_or", C.c_int32),
+                ("pt_every", C.c_int32), ("sample_uid_base", C.c_uint32),
+                ("seed", C.c_uint64)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(_LIB)
+        P = C.POINTER
+        u32p, dp, i32p, i64p, u64p = (P(C.c_uint32), P(C.c_double), P(C.c_int32),
+                                       P(C.c_int64), P(C.c_uint64))
+        L.hsgo_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.hsgo_u24.argtypes = [C.c_uint32]
+        L.hsgo_u24.restype = C.c_double
+        L.hsgo_u53.argtypes = [C.c_uint32, C.c_uint32]
+        L.hsgo_u53.restype = C.c_double
+        L.hsgo_frame.argtypes = [dp, dp, dp]
+        L.hsgo_hb_draw.argtypes = [dp, C.c_double, C.c_uint32, C.c_uint32, dp]
+        L.hsgo_or_reflect.argtypes = [dp, dp, dp]
+        L.hsgo_energy.argtypes = [C.c_int, dp, dp, dp]
+        L.hsgo_energy.restype = C.c_double
+        L.hsgo_hb_words.argtypes = [P(Cfg), C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                                    C.c_uint32, C.c_int64, u32p]
+        L.hsgo_half_sweep.argtypes = [P(Cfg), dp, dp, dp, i32p, dp, C.c_int, C.c_int, C.c_int,
+                                      C.c_uint32, i64p]
+        L.hsgo_pt_pass.argtypes = [P(Cfg), dp, i32p, dp, C.c_uint32, C.c_uint32, u64p]
+        L.hsgo_energies.argtypes = [P(Cfg), dp, dp, dp, dp]
+        L.hsgo_sweep.argtypes = [P(Cfg), dp, dp, dp, i32p, dp, dp, u64p, C.c_int, u64p]
+        L.hsgo_overlap.argtypes = [P(Cfg), dp, i32p, dp]
+        L.hsgo_set_storage_mode.argtypes = [C.c_int]
+        L.hsgo_store_roundtrip.argtypes = [C.c_int, dp]
+        L.hsgo_round_f16.argtypes = [C.c_double]
+        L.hsgo_round_f16.restype = C.c_double
+        L.hsgo_round_bf16.argtypes = [C.c_double]
+        L.hsgo_round_bf16.restype = C.c_double
+        L.hsgo_hb_draw_many.argtypes = [dp, C.c_double, u32p, C.c_int64, dp]
+        _lib = L
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+# ---------------------------------------------------------------- primitives
+def philox(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().hsgo_philox4x32_10(_p(c, C.c_uint32), _p(k, C.c_uint32), _p(out, C.c_uint32))
+    return out
+
+
+def u24(x: int) -> float:
+    return lib().hsgo_u24(int(x))
+
+
+def u53(a: int, b: int) -> float:
+    return lib().hsgo_u53(int(a), int(b))
+
+
+def frame(n):
+    n = np.ascontiguousarray(n, dtype=np.float64)
+    e1 = np.zeros(3)
+    e2 = np.zeros(3)
+    lib().hsgo_frame(_p(n, C.c_double), _p(e1, C.c_double), _p(e2, C.c_double))
+    return e1, e2
+
+
+def hb_draw(h, beta: float, x0: int, x1: int) -> np.ndarray:
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.zeros(3)
+    lib().hsgo_hb_draw(_p(h, C.c_double), float(beta), int(x0), int(x1), _p(out, C.c_double))
+    return out
+
+
+def hb_draw_many(h, beta: float, n: int, key=(0x1234567, 0x89ABCDE)) -> np.ndarray:
+    """n heat-bath draws about a fixed field, Philox blocks (q, 0, 0, 0) under key."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros((n, 3))
+    lib().hsgo_hb_draw_many(_p(h, C.c_double), float(beta), _p(k, C.c_uint32), int(n),
+                            _p(out, C.c_double))
+    return out
+
+
+def or_reflect(s, h) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    out = np.zeros(3)
+    lib().hsgo_or_reflect(_p(s, C.c_double), _p(h, C.c_double), _p(out, C.c_double))
+    return out
+
+
+def energy(L: int, J, H, s) -> float:
+    """Eq. (1) for one replica; J [3][N], H [3][N] or None, s [3][N]."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    Hp = None
+    if H is not None:
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        Hp = _p(H, C.c_double)
+    return lib().hsgo_energy(int(L), _p(J, C.c_double), Hp, _p(s, C.c_double))
+
+
+def round_f16(v: float) -> float:
+    return lib().hsgo_round_f16(float(v))
+
+
+def round_bf16(v: float) -> float:
+    return lib().hsgo_round_bf16(float(v))
+
+
+def store_roundtrip(mode: str, s) -> np.ndarray:
+    s = np.array(s, dtype=np.float64)
+    lib().hsgo_store_roundtrip(STORAGE_MODES[mode], _p(s, C.c_double))
+    return s
+
+
+# ---------------------------------------------------------------- group model
+class Oracle:
+    """Serial float64 model of one lattice-size group; mirrors the C-ABI calls.
+
+    ``spins`` has the canonical layout [d][o][slot][3][N] in float64;
+    ``slot_at_temp`` is [d][o][k] int32; ``E`` holds the energy of each slot after
+    the last sweep, [d][o][slot].
+    """
+
+    def __init__(self, L, n_samples, n_copies, temps, J, H, spins0, *, seed, n_hb=1, n_or=4,
+                 pt_every=1, sample_uid_base=0, storage="f32"):
+        self.cfg = Cfg(L=L, n_samples=n_samples, n_copies=n_copies, n_temps=len(temps),
+                       n_hb=n_hb, n_or=n_or, pt_every=pt_every,
+                       sample_uid_base=sample_uid_base, seed=seed)
+        self.L = L
+        self.N = L ** 3
+        self.temps = np.asarray(temps, dtype=np.float64)
+        self.beta = np.ascontiguousarray(1.0 / self.temps)
+        self.J = np.ascontiguousarray(J, dtype=np.float64).reshape(n_samples, 3, self.N)
+        self.H = None if H is None else np.ascontiguousarray(H, dtype=np.float64).reshape(
+            n_samples, 3, self.N)
+        self.spins = np.ascontiguousarray(spins0, dtype=np.float64).reshape(
+            n_samples, n_copies, len(temps), 3, self.N).copy()
+        self.storage = storage
+        if STORAGE_MODES[storage] != 0:
+            self._apply_storage_to_all()
+        T = len(temps)
+        self.slot_at_temp = np.ascontiguousarray(
+            np.broadcast_to(np.arange(T, dtype=np.int32), (n_samples, n_copies, T))).copy()
+        self.E = np.zeros((n_samples, n_copies, T), dtype=np.float64)
+        self.accepts = np.zeros((n_samples, n_copies, max(T - 1, 1)), dtype=np.uint64)
+        self.t = 0
+        self.pt_calls = 0
+
+    @classmethod
+    def from_group(cls, g, *, seed, n_hb=1, n_or=4, pt_every=1, storage="f32"):
+        return cls(g.L, g.n_samples, g.n_copies, g.temps, g.J, g.H, g.spins0, seed=seed,
+                   n_hb=n_hb, n_or=n_or, pt_every=pt_every, sample_uid_base=g.sample_uid_base,
+                   storage=storage)
+
+    def _apply_storage_to_all(self):
+        mode = STORAGE_MODES[self.storage]
+        flat = np.moveaxis(self.spins, 3, -1).reshape(-1, 3).copy()
+        for r in range(flat.shape[0]):
+            row = np.ascontiguousarray(flat[r])
+            lib().hsgo_store_roundtrip(mode, _p(row, C.c_double))
+            flat[r] = row
+        self.spins = np.ascontiguousarray(
+            np.moveaxis(flat.reshape(self.spins.shape[:3] + (self.N, 3)), -1, 3))
+
+    def _args(self):
+        Hp = None if self.H is None else _p(self.H, C.c_double)
+        return _p(self.J, C.c_double), Hp
+
+    def sweep(self, n_sweeps: int = 1) -> None:
+        lib().hsgo_set_storage_mode(STORAGE_MODES[self.storage])
+        t = np.array([self.t], dtype=np.uint64)
+        Jp, Hp = self._args()
+        rc = lib().hsgo_sweep(C.byref(self.cfg), Jp, Hp, _p(self.spins, C.c_double),
+                              _p(self.slot_at_temp, C.c_int32), _p(self.beta, C.c_double),
+                              _p(self.E, C.c_double), _p(t, C.c_uint64), int(n_sweeps),
+                              _p(self.accepts, C.c_uint64))
+        lib().hsgo_set_storage_mode(0)
+        if rc != 0:
+            raise RuntimeError("oracle sweep failed: temperature map is not a permutation")
+        self.t = int(t[0])
+
+    def half_sweep(self, kind: int, parity: int, rep: int = 0, order=None) -> None:
+        lib().hsgo_set_storage_mode(STORAGE_MODES[self.storage])
+        Jp, Hp = self._args()
+        op = None
+        if order is not None:
+            order = np.ascontiguousarray(order, dtype=np.int64)
+            op = _p(order, C.c_int64)
+        rc = lib().hsgo_half_sweep(C.byref(self.cfg), Jp, Hp, _p(self.spins, C.c_double),
+                                   _p(self.slot_at_temp, C.c_int32), _p(self.beta, C.c_double),
+                                   int(kind), int(rep), int(parity), self.t & 0xFFFFFFFF, op)
+        lib().hsgo_set_storage_mode(0)
+        if rc != 0:
+            raise RuntimeError("oracle half-sweep failed")
+
+    def compute_energies(self) -> np.ndarray:
+        Jp, Hp = self._args()
+        E = np.zeros_like(self.E)
+        lib().hsgo_energies(C.byref(self.cfg), Jp, Hp, _p(self.spins, C.c_double),
+                            _p(E, C.c_double))
+        return E
+
+    def measure_energy(self) -> np.ndarray:
+        return self.compute_energies()
+
+    def pt_exchange(self, energies=None) -> None:
+        """Standalone tempering pass (purpose 2, counter = number of standalone calls)."""
+        E = np.ascontiguousarray(self.E if energies is None else energies, dtype=np.float64)
+        lib().hsgo_pt_pass(C.byref(self.cfg), _p(E, C.c_double),
+                           _p(self.slot_at_temp, C.c_int32), _p(self.beta, C.c_double),
+                           self.pt_calls & 0xFFFFFFFF, 2, _p(self.accepts, C.c_uint64))
+        self.pt_calls += 1
+
+    def measure_overlap(self) -> np.ndarray:
+        q = np.zeros((self.cfg.n_samples, self.cfg.n_temps, 10), dtype=np.float64)
+        lib().hsgo_overlap(C.byref(self.cfg), _p(self.spins, C.c_double),
+                           _p(self.slot_at_temp, C.c_int32), _p(q, C.c_double))
+        return q
+
+    def hb_words(self, d, o, slot, rep, parity, i):
+        w = np.zeros(2, dtype=np.uint32)
+        lib().hsgo_hb_words(C.byref(self.cfg), d, o, slot, rep, parity, self.t & 0xFFFFFFFF,
+                            int(i), _p(w, C.c_uint32))
+        return w
