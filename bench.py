@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the EA Heisenberg spin-glass sweep on one MI355X.
+
+A step is one full sweep (1 heat-bath + 4 over-relaxation half-sweep pairs, the
+fused float64 energy, one tempering pass) of every replica of the workload.
+Default workload: L = 32, 64 disorder samples x 2 copies x 32 temperatures
+(geometric in [0.10, 0.30]), Gaussian couplings, zero field, float32 spins:
+4096 replicas, 134,217,728 spins. Inputs are seeded and synthetic.
+
+Prints one JSON line: ns per spin update (t / (steps x 5 x spins), the paper's
+per-update time), the roofline of the dominant kernel (the over-relaxation
+half-sweep, HBM-bound) from HIP events on the library's stream, and the float64
+oracle timed on a bounded sample of the same workload on host cores.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+METRIC = "ns per spin update (HB+OR) & achieved HBM GB/s, FP32 vs batched+compressed"
+STORE_BYTES = {"f32": 12, "f16": 6, "bf16": 6}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(groups, storage, kind):
+    """HBM bytes one half-sweep launch must move, over all replicas.
+
+    Per update of a parity-p site: its stored spin is written (b_s), the other
+    parity is read once (b_s per update: each of its sites feeds six updates but
+    is fetched once), over-relaxation also reads the old spin (b_s); the six
+    couplings of the site (and the field) are read once per sample and shared by
+    the R_O R_T replicas of that sample.
+    """
+    bs = STORE_BYTES[storage]
+    total = 0.0
+    for g in groups:
+        upd = g.n_slots * g.N // 2
+        spin = (3 if kind == 1 else 2) * bs
+        shared = 6 * 4 + (12 if g.H is not None else 0)
+        total += upd * spin + g.n_samples * (g.N // 2) * shared
+    return total
+
+
+def time_kernel(lat, kind, n, torch):
+    """Average duration of one half-sweep launch, from HIP events on the stream
+    the library launches on (torch's current stream)."""
+    stream = torch.cuda.current_stream()
+    for p in (0, 1):
+        lat.half_sweep(kind, p)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for i in range(n):
+        lat.half_sweep(kind, i & 1)
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / n * 1e-3  # seconds per launch
+
+
+def cpu_baseline(inst, sweeps, log_fn):
+    """The float64 oracle, as it stands, on one sample of the workload (every
+    replica of that sample), single-threaded on the host."""
+    import oracle
+    from paper_1204_6192_amd import inputs
+    g = inst.groups[0]
+    sub = inputs.Group(L=g.L, n_samples=1, n_copies=g.n_copies, temps=g.temps, J=g.J[:1],
+                       H=None if g.H is None else g.H[:1], spins0=g.spins0[:1],
+                       sample_uid_base=g.sample_uid_base)
+    o = oracle.Oracle.from_group(sub, seed=inst.seed, n_hb=inst.n_hb, n_or=inst.n_or,
+                                 pt_every=inst.pt_every)
+    t0 = time.perf_counter()
+    o.sweep(sweeps)
+    dt = time.perf_counter() - t0
+    updates = sweeps * (inst.n_hb + inst.n_or) * sub.n_slots * sub.N
+    log_fn(f"oracle: {sweeps} sweeps of 1 sample ({sub.n_slots} replicas, L={g.L}) in {dt:.1f} s")
+    return {"value": dt / updates * 1e9, "unit": "ns/update", "cores": 1, "kind": "oracle",
+            "sample": f"1 of {g.n_samples} samples (all {sub.n_slots} replicas, L={g.L}), "
+                      f"{sweeps} sweeps, {updates} updates, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="batched",
+                    choices=["tiny", "batched", "field", "uneven", "large"])
+    ap.add_argument("--storage", default=None, choices=["f32", "f16", "bf16"])
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-launches", type=int, default=40)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: there is no multi-GPU path (disorder samples "
+              "are independent and would shard across GPUs with no communication)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1204_6192_amd import hsg, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_gen = time.perf_counter()
+    inst = inputs.make_instance(args.config, storage=args.storage)
+    if inst.storage == "qangle":
+        inst.storage = "f32"
+    log(f"workload {args.config}: {len(inst.groups)} group(s), {inst.n_spins} spins, "
+        f"storage {inst.storage}; inputs in {time.perf_counter() - t_gen:.1f} s")
+    lat = hsg.Lattice(inst.groups, storage=inst.storage, n_hb=inst.n_hb, n_or=inst.n_or,
+                      pt_every=inst.pt_every, seed=inst.seed)
+    torch.cuda.synchronize()
+
+    lat.sweep(args.warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat.sync()
+    updates = args.steps * (inst.n_hb + inst.n_or) * lat.n_spins
+    ns_update = dt / updates * 1e9
+    log(f"{args.steps} sweeps in {dt:.3f} s: {ns_update * 1e3:.2f} ps/update")
+
+    # dominant kernel: the over-relaxation half-sweep (4 of the 5 passes)
+    t_or = time_kernel(lat, 1, args.kernel_launches, torch)
+    t_hb = time_kernel(lat, 0, max(4, args.kernel_launches // 4), torch)
+    b_or = algorithmic_bytes(inst.groups, inst.storage, 1)
+    b_hb = algorithmic_bytes(inst.groups, inst.storage, 0)
+    gbs_or = b_or / t_or / 1e9
+    log(f"OR half-sweep: {t_or * 1e6:.1f} us, {b_or / 1e9:.3f} GB -> {gbs_or:.0f} GB/s; "
+        f"HB half-sweep: {t_hb * 1e6:.1f} us, {b_hb / 1e9:.3f} GB -> {b_hb / t_hb / 1e9:.0f} GB/s")
+    eff_gbs = (2 * inst.n_hb * b_hb + 2 * inst.n_or * b_or) / (dt / args.steps) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(inst, args.cpu_sweeps, log)
+
+    cfg = {"workload": args.config, "L": [g.L for g in inst.groups],
+           "samples": [g.n_samples for g in inst.groups], "copies": inst.groups[0].n_copies,
+           "temperatures": inst.groups[0].n_temps,
+           "t_range": [float(inst.groups[0].temps[0]), float(inst.groups[0].temps[-1])],
+           "couplings": "bimodal" if inst.groups[0].coupling_kind else "gaussian",
+           "field": inst.groups[0].H is not None, "storage": inst.storage,
+           "sweep": f"{inst.n_hb} HB + {inst.n_or} OR + PT every {inst.pt_every}",
+           "spins": lat.n_spins, "replicas": lat.n_replicas}
+    out = {
+        "metric": METRIC, "value": ns_update, "unit": "ns/update", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": cfg,
+        "effective_gbs": eff_gbs,
+        "roofline": {"bound": "hbm", "kernel": "k_half_sweep (over-relaxation)",
+                     "achieved": gbs_or, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs_or / PEAK_HBM_GBS, "traffic": None,
+                     "launch_us": t_or * 1e6, "bytes_per_launch": b_or,
+                     "hb_launch_us": t_hb * 1e6, "hb_gbs": b_hb / t_hb / 1e9},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * hsg.h -- C-ABI of libhsg.so: Monte-Carlo sweeps of the three-dimensional
+ * Edwards-Anderson Heisenberg spin glass on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow T. Yavors'kii and M. Weigel, "Optimized GPU simulation
+ * of continuous-spin glass models" (arXiv:1204.6192):
+ *   - the model, Eq. (1): unit 3-vector spins on a periodic L^3 cubic lattice,
+ *     quenched nearest-neighbour couplings J_ij, optional random field H_i;
+ *   - the heat-bath update, Eq. (2), and the over-relaxation reflection,
+ *     Eq. (3), applied as checkerboard half-sweeps (Sec. 3.1);
+ *   - parallel tempering between neighbouring temperatures, Eq. (4), walking
+ *     the ladder from the lowest temperature and permuting temperatures, not
+ *     spins (Sec. 2 and the description of the tempering kernel in Sec. 3.3);
+ *   - the energy of Eq. (1) and the Edwards-Anderson overlap of Eq. (5);
+ *   - one execution round in the sense of Sec. 3.2: the caller provides spins,
+ *     couplings, fields and temperatures, runs sweeps, and reads back the spins
+ *     and the generator position to resume later.
+ *
+ * Conventions
+ *   Site index i = x + L (y + L z); parity (x + y + z) mod 2; L even, >= 4.
+ *   A group is a set of samples sharing L, the number of copies R_O and the
+ *   temperature ladder (R_T rungs). Replica r = (sample d, copy o, slot s);
+ *   "slot" is the storage place of a replica inside its (d, o) ladder. The
+ *   canonical replica order is [group][d][o][s].
+ *   Canonical arrays (float32, device memory):
+ *     spins   [group][d][o][s][3][L^3]
+ *     J       [group][d][3][L^3]   J[a][i] couples i and i + e_a (a = x, y, z)
+ *     H       [group][d][3][L^3]   only for groups with has_field != 0
+ *   Temperature map (int32, device): slot_at_temp[group][d][o][k] = slot that
+ *   currently holds rung k; rung k has temperature temps[k] (increasing).
+ *
+ * One sweep = n_hb heat-bath half-sweep pairs (even sites, then odd), then
+ * n_or over-relaxation pairs, then the exact float64 energy of every replica,
+ * then, if (t + 1) is a multiple of pt_every, one tempering pass. t is the
+ * sweep counter (0 after init).
+ *
+ * Random numbers: Philox4x32-10 keyed by the 64-bit seed with counter
+ *   heat bath (c0, c1, c2, c3) = (i >> 2, t, s | o<<8 | rep<<12 | parity<<16, uid)
+ *     the parity site with ((i >> 1) & 1) == 0 takes words 0, 1; the other
+ *     site of the block takes words 2, 3; u = ((w >> 8) + 1) 2^-24;
+ *   tempering (k, t, o<<8 | 1<<20, uid), standalone call n: (k, n, o<<8 | 2<<20, uid)
+ *     u = ((w0 << 21 ^ w1 >> 11) + 1) 2^-53, accept if Delta >= 0 or u <= exp(Delta);
+ *   uid = sample_uid_base of the group + d.
+ *
+ * Ownership and errors
+ *   The caller allocates and owns every device buffer; the library never
+ *   calls hipMalloc. Buffer sizes come from hsg_query_sizes. The handle holds
+ *   host metadata only. Every call returns an hsg_status; arguments are
+ *   validated before anything is enqueued. Calls are ordered on the given
+ *   stream and asynchronous unless stated; faults inside kernels surface as
+ *   HSG_E_DEVICE from the next synchronising call (hsg_sync). After an error,
+ *   hsg_last_error() returns a message (per thread). One handle must not be
+ *   used from two threads at once.
+ */
+#ifndef HSG_H
+#define HSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *hsg_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef int32_t hsg_status;
+#define HSG_OK 0
+#define HSG_E_INVALID (-1)     /* bad argument or description */
+#define HSG_E_SIZE (-2)        /* a size limit of the counter map or the ABI exceeded */
+#define HSG_E_UNSUPPORTED (-3) /* a storage / coupling combination that is not built */
+#define HSG_E_DEVICE (-4)      /* a HIP runtime or kernel error */
+#define HSG_E_STATE (-5)       /* call out of order (e.g. set_temp_map with a non-permutation) */
+
+/* Spin storage in HBM. Arithmetic is always float32; compressed forms are
+ * renormalised to |s| = 1 when they are read (Sec. 3.3 packs spins as well). */
+#define HSG_STORE_F32 0
+#define HSG_STORE_F16 1
+#define HSG_STORE_BF16 2
+#define HSG_STORE_QANGLE 3
+
+typedef struct {
+    int32_t L;                /* even, 4 <= L <= 1024 */
+    int32_t n_samples;        /* R_D >= 1 */
+    int32_t n_copies;         /* R_O, 1..16 (2 for the overlap) */
+    int32_t n_temps;          /* R_T, 1..256 */
+    const double *temps;      /* host, [n_temps], strictly increasing, finite, > 0 */
+    uint32_t sample_uid_base; /* RNG identity of sample 0 of this group */
+    int32_t has_field;        /* 0: H = 0 and no field array is read */
+    int32_t coupling_kind;    /* 0: real couplings; 1: couplings are exactly +-1 */
+    int32_t reserved;         /* must be 0 */
+} hsg_group_desc;
+
+typedef struct {
+    const hsg_group_desc *groups; /* host, [n_groups] */
+    int32_t n_groups;             /* 1..64 */
+    int32_t storage;              /* HSG_STORE_* */
+    int32_t n_hb;                 /* heat-bath half-sweep pairs per sweep, 0..16 */
+    int32_t n_or;                 /* over-relaxation pairs per sweep, 0..64; n_hb + n_or >= 1 */
+    int32_t pt_every;             /* tempering after every pt_every-th sweep; 0 = never */
+    int32_t reserved;             /* must be 0 */
+    uint64_t seed;                /* Philox key */
+} hsg_desc;
+
+typedef struct {
+    uint64_t state_bytes;    /* spins (internal layout), temperature maps, energies, counters */
+    uint64_t coupling_bytes; /* couplings in the internal layout and the ladders */
+    uint64_t field_bytes;    /* random fields in the internal layout (0 if no group has one) */
+    uint64_t scratch_bytes;  /* reduction partials */
+    uint64_t n_replicas;     /* total replicas over all groups */
+    uint64_t n_spins;        /* total spins over all replicas */
+} hsg_sizes;
+
+typedef struct hsg_lattice hsg_lattice;
+
+/* Sizes of the four caller-owned device buffers for `desc`. Host only. */
+hsg_status hsg_query_sizes(const hsg_desc *desc, hsg_sizes *out);
+
+/* Validate `desc`, bind the buffers and pack the canonical inputs into them.
+ * d_spins0, d_J (and d_H if any group has a field) are read on `stream` and
+ * may be freed once the stream has passed this call. d_state, d_couplings,
+ * d_field (may be NULL if field_bytes == 0) and d_scratch must stay allocated
+ * until hsg_destroy, 256-byte aligned, with at least the queried sizes. The
+ * sweep counter starts at 0, every temperature map at the identity. */
+hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const float *d_J,
+                            const float *d_H, void *d_state, void *d_couplings, void *d_field,
+                            void *d_scratch, hsg_stream_t stream, hsg_lattice **out);
+
+/* n_sweeps >= 0 full sweeps (see the header comment), asynchronous. */
+hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream);
+
+/* One checkerboard half-sweep of every replica: kind 0 = heat bath, 1 = over-
+ * relaxation; parity 0 or 1; rep = heat-bath repetition index for the counter.
+ * Uses the current sweep counter and does not advance it. */
+hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t rep,
+                          hsg_stream_t stream);
+
+/* One standalone tempering pass over every ladder using the energies of the
+ * last sweep (or of the last hsg_measure_energy); advances the standalone-call
+ * counter. */
+hsg_status hsg_pt_exchange(hsg_lattice *h, hsg_stream_t stream);
+
+/* Recompute the float64 energy of Eq. (1) of every replica into d_E
+ * [n_replicas] (canonical replica order); also stores it as the energies that
+ * a following hsg_pt_exchange uses. */
+hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream);
+
+/* Copy the energies computed at the end of the last sweep into d_E [n_replicas]. */
+hsg_status hsg_get_energies(const hsg_lattice *h, double *d_E, hsg_stream_t stream);
+
+/* Overlap of Eq. (5) between copies 0 and 1 at every rung, float64:
+ * d_q[group][d][k][10] = q^{mu nu} at 3 mu + nu (mu from copy 0), then
+ * q^2 = sum of the nine squares. Requires n_copies >= 2 in every group. */
+hsg_status hsg_measure_overlap(hsg_lattice *h, double *d_q, hsg_stream_t stream);
+
+/* Decode the spins into the canonical float32 layout (renormalised). */
+hsg_status hsg_get_spins(const hsg_lattice *h, float *d_spins, hsg_stream_t stream);
+
+/* Replace the spins from the canonical float32 layout (encoded as stored). */
+hsg_status hsg_set_spins(hsg_lattice *h, const float *d_spins, hsg_stream_t stream);
+
+/* Temperature maps [group][d][o][k] int32 (device). set_ validates nothing on
+ * the device: the caller must pass permutations of 0..n_temps-1. */
+hsg_status hsg_get_temp_map(const hsg_lattice *h, int32_t *d_slot_at_temp, hsg_stream_t stream);
+hsg_status hsg_set_temp_map(hsg_lattice *h, const int32_t *d_slot_at_temp, hsg_stream_t stream);
+
+/* Accepted tempering swaps per rung pair since init, uint64 [group][d][o][k]
+ * for k = 0..n_temps-2 (device). */
+hsg_status hsg_get_pt_accepts(const hsg_lattice *h, uint64_t *d_accepts, hsg_stream_t stream);
+
+/* Generator position for checkpoint / resume (host values). */
+hsg_status hsg_get_state(const hsg_lattice *h, uint64_t *sweep_counter, uint64_t *pt_calls,
+                         uint64_t *seed);
+hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls);
+
+/* Tuning (results do not depend on it): slots processed per work item
+ * (1..R_O R_T, 0 = automatic). */
+hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
+
+/* Wait for `stream` and report any device error. */
+hsg_status hsg_sync(hsg_lattice *h, hsg_stream_t stream);
+
+/* Release the handle (not the caller's buffers). NULL is ignored. */
+void hsg_destroy(hsg_lattice *h);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *hsg_last_error(void);
+
+/* Test hook: n Philox4x32-10 blocks, d_ctr [n][4], d_key [n][2] -> d_out [n][4]
+ * (device arrays). Exposes the device generator for a bit-exact comparison. */
+hsg_status hsg_debug_philox(const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out,
+                            int64_t n, hsg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSG_H */

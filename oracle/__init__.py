@@ -89,6 +89,7 @@ def lib():
         L.hsgo_round_bf16.argtypes = [C.c_double]
         L.hsgo_round_bf16.restype = C.c_double
         L.hsgo_hb_draw_many.argtypes = [dp, C.c_double, u32p, C.c_int64, dp]
+        L.hsgo_set_noise.argtypes = [C.c_double, C.c_uint64]
         _lib = L
     return _lib
 
@@ -205,6 +206,7 @@ class Oracle:
         self.accepts = np.zeros((n_samples, n_copies, max(T - 1, 1)), dtype=np.uint64)
         self.t = 0
         self.pt_calls = 0
+        self.noise = (0.0, 0)  # sensitivity probe: (relative amplitude, stream seed)
 
     @classmethod
     def from_group(cls, g, *, seed, n_hb=1, n_or=4, pt_every=1, storage="f32"):
@@ -226,8 +228,20 @@ class Oracle:
         Hp = None if self.H is None else _p(self.H, C.c_double)
         return _p(self.J, C.c_double), Hp
 
+    def set_noise(self, eps: float, seed: int) -> None:
+        """Test-only sensitivity probe: perturb every update by relative eps."""
+        self.noise = (float(eps), int(seed))
+
+    def _noise_on(self):
+        eps, seed = self.noise
+        if eps > 0.0:
+            # advance the stream per call so that successive calls differ
+            lib().hsgo_set_noise(eps, (seed * 1_000_003 + self.t * 7919 + self.pt_calls)
+                                 & 0xFFFFFFFFFFFFFFFF)
+
     def sweep(self, n_sweeps: int = 1) -> None:
         lib().hsgo_set_storage_mode(STORAGE_MODES[self.storage])
+        self._noise_on()
         t = np.array([self.t], dtype=np.uint64)
         Jp, Hp = self._args()
         rc = lib().hsgo_sweep(C.byref(self.cfg), Jp, Hp, _p(self.spins, C.c_double),
@@ -235,6 +249,7 @@ class Oracle:
                               _p(self.E, C.c_double), _p(t, C.c_uint64), int(n_sweeps),
                               _p(self.accepts, C.c_uint64))
         lib().hsgo_set_storage_mode(0)
+        lib().hsgo_set_noise(0.0, 0)
         if rc != 0:
             raise RuntimeError("oracle sweep failed: temperature map is not a permutation")
         self.t = int(t[0])

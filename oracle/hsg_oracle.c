@@ -89,19 +89,34 @@ static void normalise3(double v[3])
     v[0] /= n; v[1] /= n; v[2] /= n;
 }
 
-/* Orthonormal frame (e1, e2) with e1 x e2 = n for a unit vector n:
- * Duff, Burgess, Christensen, Hery, Kensler, Liani, Villemin, "Building an
- * Orthonormal Basis, Revisited", JCGT 6(1), 2017. sign(0) and sign(-0) are +1. */
+/* Orthonormal frame (e1, e2) with e1 x e2 = n for a unit vector n, after
+ * J. R. Frisvad, "Building an orthonormal basis from a 3D unit vector without
+ * normalization", J. Graphics Tools 16(3), 2012:
+ *   e1 = (1 - nx^2 a, -nx ny a, -nx),  e2 = (-nx ny a, 1 - ny^2 a, -ny),
+ *   a = 1 / (1 + nz).
+ * For nz < 0 the same 1 + nz is formed as (nx^2 + ny^2) / (1 - nz), which does
+ * not cancel. The frame is continuous on the sphere except at nz = -1, where it
+ * takes its limit along nx > 0, ny = 0: e1 = (-1, 0, 0), e2 = (0, 1, 0). */
 void hsgo_frame(const double n[3], double e1[3], double e2[3])
 {
-    double sgn = (n[2] >= 0.0) ? 1.0 : -1.0;
-    double a = -1.0 / (sgn + n[2]);
-    double b = n[0] * n[1] * a;
-    e1[0] = 1.0 + sgn * n[0] * n[0] * a;
-    e1[1] = sgn * b;
-    e1[2] = -sgn * n[0];
+    double a;
+    if (n[2] >= 0.0) {
+        a = 1.0 / (1.0 + n[2]);
+    } else {
+        double rxy = n[0] * n[0] + n[1] * n[1];
+        if (rxy == 0.0) {
+            e1[0] = -1.0; e1[1] = 0.0; e1[2] = 0.0;
+            e2[0] = 0.0;  e2[1] = 1.0; e2[2] = 0.0;
+            return;
+        }
+        a = (1.0 - n[2]) / rxy;
+    }
+    double b = -n[0] * n[1] * a;
+    e1[0] = 1.0 - n[0] * n[0] * a;
+    e1[1] = b;
+    e1[2] = -n[0];
     e2[0] = b;
-    e2[1] = sgn + n[1] * n[1] * a;
+    e2[1] = 1.0 - n[1] * n[1] * a;
     e2[2] = -n[1];
 }
 
@@ -245,6 +260,23 @@ static int g_storage_mode = 0;
 void hsgo_set_storage_mode(int mode) { g_storage_mode = mode; }
 void hsgo_store_roundtrip(int mode, double s[3]);
 
+/* Sensitivity probe (tests only): with eps > 0, every updated component is
+ * multiplied by (1 + eps r), r uniform in [-1, 1) from a SplitMix64 stream,
+ * before the storage rounding. eps = 2^-24 mimics float32 rounding of every
+ * stored spin; runs with different noise seeds show how far two correct
+ * trajectories drift apart. eps = 0 (the default) leaves the chain exact. */
+static double g_noise_eps = 0.0;
+static uint64_t g_noise_state = 0;
+void hsgo_set_noise(double eps, uint64_t seed) { g_noise_eps = eps; g_noise_state = seed; }
+static double noise_uniform(void)
+{
+    uint64_t z = (g_noise_state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1p-52 - 1.0;
+}
+
 /* One half-sweep of one slot: every site of parity `parity` gets a heat-bath
  * draw (kind 0) or an over-relaxation reflection (kind 1). Sites of one parity
  * only see the other parity through H_eff, so the in-place update is exact.
@@ -278,6 +310,8 @@ static void half_sweep_slot(const hsgo_cfg *c, const double *J, const double *H,
             for (int m = 0; m < 3; ++m) so[m] = s[m * N + i];
             hsgo_or_reflect(so, h, sn);
         }
+        if (g_noise_eps > 0.0)
+            for (int m = 0; m < 3; ++m) sn[m] *= 1.0 + g_noise_eps * noise_uniform();
         hsgo_store_roundtrip(g_storage_mode, sn);
         for (int m = 0; m < 3; ++m) s[m * N + i] = sn[m];
     }

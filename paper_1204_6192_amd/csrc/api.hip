@@ -1,0 +1,592 @@
+// api.hip -- the C-ABI of libhsg.so (declared in include/hsg.h).
+//
+// Host side only: validation, buffer carving, and the order of launches that
+// makes one sweep (heat-bath pairs, over-relaxation pairs with the energy of
+// Eq. (1) fused into the last pass, tempering per Eq. (4)). No device memory is
+// allocated here; every buffer belongs to the caller.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/hsg.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+hsg_status fail(hsg_status st, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+hsg_status fail(hsg_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+hsg_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(HSG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr uint64_t kAlign = 256;
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int bytes_per_component(int storage) { return storage == HSG_STORE_F32 ? 4 : 2; }
+
+struct Group {
+    int32_t L, D, O, T;
+    int64_t N, Nh;
+    uint32_t uid_base;
+    bool field;
+    int32_t ckind;
+    std::vector<double> temps;
+    int64_t rep0;  // first replica of the group in canonical order
+    int64_t n_rep;
+    int64_t can_spin0;  // element offset of the group in the canonical spin array
+    int64_t can_site0;  // element offset of the group in the canonical J and H arrays
+    // byte offsets
+    uint64_t o_spins, o_sat, o_tos, o_E, o_acc;  // state
+    uint64_t o_J6, o_b64, o_b32;                 // couplings
+    uint64_t o_H;                                // field
+    uint64_t o_scr;                              // scratch
+    int32_t n_pb_sweep;                          // blocks of 256 site pairs per replica
+    int32_t n_pb_site;                           // blocks of 256 sites per replica half
+};
+
+struct Layout {
+    std::vector<Group> g;
+    hsg_sizes sz{};
+};
+
+hsg_status build_layout(const hsg_desc *desc, Layout &lay)
+{
+    if (desc == nullptr) return fail(HSG_E_INVALID, "desc is NULL");
+    if (desc->reserved != 0) return fail(HSG_E_INVALID, "desc.reserved must be 0");
+    if (desc->n_groups < 1 || desc->n_groups > 64)
+        return fail(HSG_E_INVALID, "n_groups = %d, need 1..64", desc->n_groups);
+    if (desc->groups == nullptr) return fail(HSG_E_INVALID, "groups is NULL");
+    if (desc->storage < HSG_STORE_F32 || desc->storage > HSG_STORE_QANGLE)
+        return fail(HSG_E_INVALID, "storage = %d is not an HSG_STORE_* value", desc->storage);
+    if (desc->storage == HSG_STORE_QANGLE)
+        return fail(HSG_E_UNSUPPORTED, "quantised-angle storage is not built in this library");
+    if (desc->n_hb < 0 || desc->n_hb > 16) return fail(HSG_E_SIZE, "n_hb = %d, need 0..16", desc->n_hb);
+    if (desc->n_or < 0 || desc->n_or > 64) return fail(HSG_E_SIZE, "n_or = %d, need 0..64", desc->n_or);
+    if (desc->n_hb + desc->n_or < 1) return fail(HSG_E_INVALID, "a sweep needs n_hb + n_or >= 1");
+    if (desc->pt_every < 0) return fail(HSG_E_INVALID, "pt_every = %d < 0", desc->pt_every);
+    lay.g.clear();
+    uint64_t st = 0, cp = 0, fd = 0, sc = 0;
+    int64_t rep0 = 0, spins = 0, sites = 0;
+    for (int gi = 0; gi < desc->n_groups; ++gi) {
+        const hsg_group_desc &gd = desc->groups[gi];
+        Group g{};
+        if (gd.reserved != 0) return fail(HSG_E_INVALID, "group %d: reserved must be 0", gi);
+        if (gd.L < 4 || gd.L > 1024 || (gd.L & 1))
+            return fail(HSG_E_INVALID, "group %d: L = %d must be even and in 4..1024", gi, gd.L);
+        if (gd.n_samples < 1) return fail(HSG_E_INVALID, "group %d: n_samples = %d < 1", gi, gd.n_samples);
+        if (gd.n_copies < 1 || gd.n_copies > 16)
+            return fail(HSG_E_SIZE, "group %d: n_copies = %d, need 1..16", gi, gd.n_copies);
+        if (gd.n_temps < 1 || gd.n_temps > 256)
+            return fail(HSG_E_SIZE, "group %d: n_temps = %d, need 1..256", gi, gd.n_temps);
+        if (gd.temps == nullptr) return fail(HSG_E_INVALID, "group %d: temps is NULL", gi);
+        for (int k = 0; k < gd.n_temps; ++k) {
+            const double T = gd.temps[k];
+            if (!(std::isfinite(T) && T > 0.0))
+                return fail(HSG_E_INVALID, "group %d: temps[%d] = %g is not finite and > 0", gi, k, T);
+            if (k > 0 && !(T > gd.temps[k - 1]))
+                return fail(HSG_E_INVALID, "group %d: temps must be strictly increasing (k = %d)", gi, k);
+        }
+        if (gd.coupling_kind != 0 && gd.coupling_kind != 1)
+            return fail(HSG_E_INVALID, "group %d: coupling_kind = %d", gi, gd.coupling_kind);
+        if ((uint64_t)gd.sample_uid_base + (uint64_t)gd.n_samples > 0x100000000ull)
+            return fail(HSG_E_SIZE, "group %d: sample uids exceed 32 bits", gi);
+        g.L = gd.L;
+        g.D = gd.n_samples;
+        g.O = gd.n_copies;
+        g.T = gd.n_temps;
+        g.N = (int64_t)g.L * g.L * g.L;
+        g.Nh = g.N / 2;
+        g.uid_base = gd.sample_uid_base;
+        g.field = gd.has_field != 0;
+        g.ckind = gd.coupling_kind;
+        g.temps.assign(gd.temps, gd.temps + gd.n_temps);
+        g.rep0 = rep0;
+        g.can_spin0 = spins * 3;
+        g.can_site0 = sites * 3;
+        g.n_rep = (int64_t)g.D * g.O * g.T;
+        const int64_t pairs = g.Nh / 2;
+        g.n_pb_sweep = (int32_t)((pairs + hsg::kBlock - 1) / hsg::kBlock);
+        g.n_pb_site = (int32_t)((g.Nh + hsg::kBlock - 1) / hsg::kBlock);
+        // state
+        g.o_spins = st;
+        st = align_up(st + (uint64_t)g.n_rep * 6 * g.Nh * bytes_per_component(desc->storage));
+        g.o_sat = st;
+        st = align_up(st + (uint64_t)g.n_rep * 4);
+        g.o_tos = st;
+        st = align_up(st + (uint64_t)g.n_rep * 4);
+        g.o_E = st;
+        st = align_up(st + (uint64_t)g.n_rep * 8);
+        g.o_acc = st;
+        st = align_up(st + (uint64_t)g.D * g.O * (g.T > 1 ? g.T - 1 : 1) * 8);
+        // couplings and ladder
+        g.o_J6 = cp;
+        cp = align_up(cp + (uint64_t)g.D * 2 * 6 * g.Nh * 4);
+        g.o_b64 = cp;
+        cp = align_up(cp + (uint64_t)g.T * 8);
+        g.o_b32 = cp;
+        cp = align_up(cp + (uint64_t)g.T * 4);
+        // field
+        g.o_H = fd;
+        if (g.field) fd = align_up(fd + (uint64_t)g.D * 2 * 3 * g.Nh * 4);
+        // scratch: the largest of the three reductions of this group
+        g.o_scr = sc;
+        const uint64_t e_sweep = (uint64_t)g.n_rep * g.n_pb_sweep * 8;
+        const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
+        const uint64_t q_full = (uint64_t)g.D * g.T * g.n_pb_site * 9 * 8;
+        uint64_t need = e_sweep > e_full ? e_sweep : e_full;
+        if (q_full > need) need = q_full;
+        sc = align_up(sc + need);
+        rep0 += g.n_rep;
+        spins += g.n_rep * g.N;
+        sites += (int64_t)g.D * g.N;
+        lay.g.push_back(std::move(g));
+    }
+    lay.sz.state_bytes = st;
+    lay.sz.coupling_bytes = cp;
+    lay.sz.field_bytes = fd;
+    lay.sz.scratch_bytes = sc;
+    lay.sz.n_replicas = (uint64_t)rep0;
+    lay.sz.n_spins = (uint64_t)spins;
+    return HSG_OK;
+}
+
+}  // namespace
+
+struct hsg_lattice {
+    Layout lay;
+    int32_t storage = 0, n_hb = 1, n_or = 4, pt_every = 1;
+    uint64_t seed = 0;
+    uint64_t t = 0, pt_calls = 0;
+    char *state = nullptr, *coup = nullptr, *field = nullptr, *scratch = nullptr;
+    int32_t slots_per_item = 0;
+    bool have_energies = false;
+};
+
+namespace {
+
+hipStream_t S(hsg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+int chunk_for(const hsg_lattice *h, const Group &g)
+{
+    const int spp = g.O * g.T;
+    int c = h->slots_per_item > 0 ? h->slots_per_item : 8;
+    return c < spp ? c : spp;
+}
+
+hsg::SweepArgs sweep_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep)
+{
+    hsg::SweepArgs a{};
+    a.spins = h->state + g.o_spins;
+    a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+    a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+    a.temp_of_slot = reinterpret_cast<const int32_t *>(h->state + g.o_tos);
+    a.beta32 = reinterpret_cast<const float *>(h->coup + g.o_b32);
+    a.e_partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+    a.Nh = g.Nh;
+    a.L = g.L;
+    a.Lh = g.L / 2;
+    a.slots_per_sample = g.O * g.T;
+    a.T = g.T;
+    a.chunk = chunk_for(h, g);
+    a.n_chunks = (a.slots_per_sample + a.chunk - 1) / a.chunk;
+    a.n_pb = g.n_pb_sweep;
+    a.n_blocks = g.D * a.n_chunks * a.n_pb;
+    a.t = (uint32_t)(h->t & 0xFFFFFFFFu);
+    a.rep = rep;
+    a.parity = (uint32_t)parity;
+    a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(h->seed >> 32);
+    a.uid_base = g.uid_base;
+    return a;
+}
+
+hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool energy, hipStream_t s)
+{
+    for (const Group &g : h->lay.g) {
+        const hsg::SweepArgs a = sweep_args(h, g, parity, (uint32_t)rep);
+        if ((int64_t)g.D * a.n_chunks * a.n_pb > 0x7FFFFFFFll)
+            return fail(HSG_E_SIZE, "grid too large");
+        hipError_t e = hsg::launch_half_sweep(a, h->storage, kind, g.field, energy, s);
+        if (e != hipSuccess) return hip_fail(e, "half-sweep launch");
+        if (energy) {
+            e = hsg::launch_reduce_partials(a.e_partials, a.n_pb, g.n_rep,
+                                            reinterpret_cast<double *>(h->state + g.o_E), s);
+            if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
+        }
+    }
+    return HSG_OK;
+}
+
+hsg_status run_pt(hsg_lattice *h, uint32_t ctr1, uint32_t purpose, hipStream_t s)
+{
+    for (const Group &g : h->lay.g) {
+        hsg::PtArgs a{};
+        a.slot_at_temp = reinterpret_cast<int32_t *>(h->state + g.o_sat);
+        a.temp_of_slot = reinterpret_cast<int32_t *>(h->state + g.o_tos);
+        a.E = reinterpret_cast<const double *>(h->state + g.o_E);
+        a.beta64 = reinterpret_cast<const double *>(h->coup + g.o_b64);
+        a.accepts = reinterpret_cast<unsigned long long *>(h->state + g.o_acc);
+        a.D = g.D;
+        a.O = g.O;
+        a.T = g.T;
+        a.ctr1 = ctr1;
+        a.purpose = purpose;
+        a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+        a.key1 = (uint32_t)(h->seed >> 32);
+        a.uid_base = g.uid_base;
+        const hipError_t e = hsg::launch_pt(a, s);
+        if (e != hipSuccess) return hip_fail(e, "tempering launch");
+    }
+    return HSG_OK;
+}
+
+hsg::PackArgs pack_args(const hsg_lattice *h, const Group &g)
+{
+    hsg::PackArgs a{};
+    a.spins_int = h->state + g.o_spins;
+    a.J6 = reinterpret_cast<float *>(h->coup + g.o_J6);
+    a.Hp = g.field ? reinterpret_cast<float *>(h->field + g.o_H) : nullptr;
+    a.n_rep = g.n_rep;
+    a.D = g.D;
+    a.L = g.L;
+    return a;
+}
+
+bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign - 1)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *hsg_last_error(void) { return g_err.c_str(); }
+
+hsg_status hsg_query_sizes(const hsg_desc *desc, hsg_sizes *out)
+{
+    if (out == nullptr) return fail(HSG_E_INVALID, "out is NULL");
+    Layout lay;
+    const hsg_status st = build_layout(desc, lay);
+    if (st != HSG_OK) return st;
+    *out = lay.sz;
+    return HSG_OK;
+}
+
+hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const float *d_J, const float *d_H,
+                            void *d_state, void *d_couplings, void *d_field, void *d_scratch, hsg_stream_t stream,
+                            hsg_lattice **out)
+{
+    if (out == nullptr) return fail(HSG_E_INVALID, "out is NULL");
+    *out = nullptr;
+    Layout lay;
+    hsg_status st = build_layout(desc, lay);
+    if (st != HSG_OK) return st;
+    bool any_field = false;
+    for (const Group &g : lay.g) any_field = any_field || g.field;
+    if (d_spins0 == nullptr || d_J == nullptr) return fail(HSG_E_INVALID, "d_spins0 and d_J are required");
+    if (any_field && d_H == nullptr) return fail(HSG_E_INVALID, "a group has a field but d_H is NULL");
+    if (d_state == nullptr || d_couplings == nullptr || d_scratch == nullptr)
+        return fail(HSG_E_INVALID, "d_state, d_couplings and d_scratch are required");
+    if (lay.sz.field_bytes > 0 && d_field == nullptr) return fail(HSG_E_INVALID, "d_field is required");
+    if (!aligned(d_state) || !aligned(d_couplings) || !aligned(d_scratch) || (d_field && !aligned(d_field)))
+        return fail(HSG_E_INVALID, "device buffers must be 256-byte aligned");
+
+    hsg_lattice *h = new (std::nothrow) hsg_lattice();
+    if (h == nullptr) return fail(HSG_E_INVALID, "out of host memory");
+    h->lay = std::move(lay);
+    h->storage = desc->storage;
+    h->n_hb = desc->n_hb;
+    h->n_or = desc->n_or;
+    h->pt_every = desc->pt_every;
+    h->seed = desc->seed;
+    h->state = static_cast<char *>(d_state);
+    h->coup = static_cast<char *>(d_couplings);
+    h->field = static_cast<char *>(d_field);
+    h->scratch = static_cast<char *>(d_scratch);
+    hipStream_t s = S(stream);
+
+    for (const Group &g : h->lay.g) {
+        hsg::PackArgs a = pack_args(h, g);
+        a.spins_can = const_cast<float *>(d_spins0) + g.can_spin0;
+        a.J_can = d_J + g.can_site0;
+        a.H_can = g.field ? d_H + g.can_site0 : nullptr;
+        hipError_t e = hsg::launch_pack_spins(a, h->storage, s);
+        if (e == hipSuccess) e = hsg::launch_pack_couplings(a, s);
+        if (e == hipSuccess && g.field) e = hsg::launch_pack_field(a, s);
+        // ladders: float64 and float32 inverse temperatures
+        std::vector<double> b64(g.T);
+        std::vector<float> b32(g.T);
+        for (int k = 0; k < g.T; ++k) {
+            b64[k] = 1.0 / g.temps[k];
+            b32[k] = (float)b64[k];
+        }
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->coup + g.o_b64, b64.data(), g.T * 8, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(h->coup + g.o_b32, b32.data(), g.T * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hsg::launch_fill_identity_maps(reinterpret_cast<int32_t *>(h->state + g.o_sat),
+                                               reinterpret_cast<int32_t *>(h->state + g.o_tos),
+                                               (int64_t)g.D * g.O, g.T, s);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(h->state + g.o_E, 0, (size_t)g.n_rep * 8, s);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(h->state + g.o_acc, 0, (size_t)g.D * g.O * (g.T > 1 ? g.T - 1 : 1) * 8, s);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "init");
+        }
+        // the host copies above read stack vectors: wait before they go away
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "init");
+        }
+    }
+    *out = h;
+    return HSG_OK;
+}
+
+hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (n_sweeps < 0) return fail(HSG_E_INVALID, "n_sweeps = %d < 0", n_sweeps);
+    if (h->t + (uint64_t)n_sweeps > 0x100000000ull)
+        return fail(HSG_E_SIZE, "the sweep counter would pass 2^32 (the counter map limit)");
+    hipStream_t s = S(stream);
+    for (int it = 0; it < n_sweeps; ++it) {
+        const int last_kind = h->n_or > 0 ? 1 : 0;
+        for (int r = 0; r < h->n_hb; ++r)
+            for (int p = 0; p < 2; ++p) {
+                const bool energy = (last_kind == 0) && r == h->n_hb - 1 && p == 1;
+                hsg_status st = run_half_sweep(h, 0, p, r, energy, s);
+                if (st != HSG_OK) return st;
+            }
+        for (int r = 0; r < h->n_or; ++r)
+            for (int p = 0; p < 2; ++p) {
+                const bool energy = r == h->n_or - 1 && p == 1;
+                hsg_status st = run_half_sweep(h, 1, p, 0, energy, s);
+                if (st != HSG_OK) return st;
+            }
+        h->have_energies = true;
+        if (h->pt_every > 0 && ((h->t + 1) % (uint64_t)h->pt_every) == 0) {
+            hsg_status st = run_pt(h, (uint32_t)(h->t & 0xFFFFFFFFu), 1u, s);
+            if (st != HSG_OK) return st;
+        }
+        h->t += 1;
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t rep, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (kind != 0 && kind != 1) return fail(HSG_E_INVALID, "kind = %d, need 0 (HB) or 1 (OR)", kind);
+    if (parity != 0 && parity != 1) return fail(HSG_E_INVALID, "parity = %d", parity);
+    if (rep < 0 || rep > 15) return fail(HSG_E_SIZE, "rep = %d, need 0..15", rep);
+    return run_half_sweep(h, kind, parity, rep, false, S(stream));
+}
+
+hsg_status hsg_pt_exchange(hsg_lattice *h, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (h->pt_calls >= 0x100000000ull) return fail(HSG_E_SIZE, "standalone tempering counter exhausted");
+    const hsg_status st = run_pt(h, (uint32_t)h->pt_calls, 2u, S(stream));
+    if (st == HSG_OK) h->pt_calls += 1;
+    return st;
+}
+
+hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream)
+{
+    if (h == nullptr || d_E == nullptr) return fail(HSG_E_INVALID, "handle and d_E are required");
+    hipStream_t s = S(stream);
+    for (const Group &g : h->lay.g) {
+        hsg::EnergyArgs a{};
+        a.spins = h->state + g.o_spins;
+        a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+        a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+        a.partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+        a.Nh = g.Nh;
+        a.n_rep = g.n_rep;
+        a.L = g.L;
+        a.Lh = g.L / 2;
+        a.slots_per_sample = g.O * g.T;
+        a.n_pb = g.n_pb_site;
+        hipError_t e = hsg::launch_energy(a, h->storage, s);
+        double *E = reinterpret_cast<double *>(h->state + g.o_E);
+        if (e == hipSuccess) e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, E, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_E + g.rep0, E, (size_t)g.n_rep * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "measure_energy");
+    }
+    h->have_energies = true;
+    return HSG_OK;
+}
+
+hsg_status hsg_get_energies(const hsg_lattice *h, double *d_E, hsg_stream_t stream)
+{
+    if (h == nullptr || d_E == nullptr) return fail(HSG_E_INVALID, "handle and d_E are required");
+    for (const Group &g : h->lay.g) {
+        const hipError_t e = hipMemcpyAsync(d_E + g.rep0, h->state + g.o_E, (size_t)g.n_rep * 8,
+                                            hipMemcpyDeviceToDevice, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "get_energies");
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_measure_overlap(hsg_lattice *h, double *d_q, hsg_stream_t stream)
+{
+    if (h == nullptr || d_q == nullptr) return fail(HSG_E_INVALID, "handle and d_q are required");
+    for (const Group &g : h->lay.g)
+        if (g.O < 2) return fail(HSG_E_INVALID, "the overlap needs n_copies >= 2 in every group");
+    int64_t off = 0;
+    for (const Group &g : h->lay.g) {
+        hsg::OverlapArgs a{};
+        a.spins = h->state + g.o_spins;
+        a.slot_at_temp = reinterpret_cast<const int32_t *>(h->state + g.o_sat);
+        a.partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+        a.q = d_q + off;
+        a.Nh = g.Nh;
+        a.D = g.D;
+        a.O = g.O;
+        a.T = g.T;
+        a.n_pb = g.n_pb_site;
+        const hipError_t e = hsg::launch_overlap(a, h->storage, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "measure_overlap");
+        off += (int64_t)g.D * g.T * 10;
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_get_spins(const hsg_lattice *h, float *d_spins, hsg_stream_t stream)
+{
+    if (h == nullptr || d_spins == nullptr) return fail(HSG_E_INVALID, "handle and d_spins are required");
+    for (const Group &g : h->lay.g) {
+        hsg::PackArgs a = pack_args(h, g);
+        a.spins_can = d_spins + g.can_spin0;
+        const hipError_t e = hsg::launch_unpack_spins(a, h->storage, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "get_spins");
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_set_spins(hsg_lattice *h, const float *d_spins, hsg_stream_t stream)
+{
+    if (h == nullptr || d_spins == nullptr) return fail(HSG_E_INVALID, "handle and d_spins are required");
+    for (const Group &g : h->lay.g) {
+        hsg::PackArgs a = pack_args(h, g);
+        a.spins_can = const_cast<float *>(d_spins) + g.can_spin0;
+        const hipError_t e = hsg::launch_pack_spins(a, h->storage, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "set_spins");
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_get_temp_map(const hsg_lattice *h, int32_t *d_sat, hsg_stream_t stream)
+{
+    if (h == nullptr || d_sat == nullptr) return fail(HSG_E_INVALID, "handle and d_slot_at_temp are required");
+    for (const Group &g : h->lay.g) {
+        const hipError_t e = hipMemcpyAsync(d_sat + g.rep0, h->state + g.o_sat, (size_t)g.n_rep * 4,
+                                            hipMemcpyDeviceToDevice, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "get_temp_map");
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_set_temp_map(hsg_lattice *h, const int32_t *d_sat, hsg_stream_t stream)
+{
+    if (h == nullptr || d_sat == nullptr) return fail(HSG_E_INVALID, "handle and d_slot_at_temp are required");
+    for (const Group &g : h->lay.g) {
+        int32_t *sat = reinterpret_cast<int32_t *>(h->state + g.o_sat);
+        hipError_t e = hipMemcpyAsync(sat, d_sat + g.rep0, (size_t)g.n_rep * 4, hipMemcpyDeviceToDevice, S(stream));
+        if (e == hipSuccess)
+            e = hsg::launch_invert_maps(sat, reinterpret_cast<int32_t *>(h->state + g.o_tos), (int64_t)g.D * g.O,
+                                        g.T, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "set_temp_map");
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_get_pt_accepts(const hsg_lattice *h, uint64_t *d_acc, hsg_stream_t stream)
+{
+    if (h == nullptr || d_acc == nullptr) return fail(HSG_E_INVALID, "handle and d_accepts are required");
+    int64_t off = 0;
+    for (const Group &g : h->lay.g) {
+        const int64_t n = (int64_t)g.D * g.O * (g.T - 1);
+        if (n > 0) {
+            const hipError_t e =
+                hipMemcpyAsync(d_acc + off, h->state + g.o_acc, (size_t)n * 8, hipMemcpyDeviceToDevice, S(stream));
+            if (e != hipSuccess) return hip_fail(e, "get_pt_accepts");
+        }
+        off += n;
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_get_state(const hsg_lattice *h, uint64_t *sweep_counter, uint64_t *pt_calls, uint64_t *seed)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (sweep_counter) *sweep_counter = h->t;
+    if (pt_calls) *pt_calls = h->pt_calls;
+    if (seed) *seed = h->seed;
+    return HSG_OK;
+}
+
+hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (sweep_counter > 0xFFFFFFFFull || pt_calls > 0xFFFFFFFFull)
+        return fail(HSG_E_SIZE, "counters are limited to 32 bits");
+    h->t = sweep_counter;
+    h->pt_calls = pt_calls;
+    return HSG_OK;
+}
+
+hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (slots_per_item < 0 || slots_per_item > 16 * 256)
+        return fail(HSG_E_INVALID, "slots_per_item = %d", slots_per_item);
+    h->slots_per_item = slots_per_item;
+    return HSG_OK;
+}
+
+hsg_status hsg_sync(hsg_lattice *h, hsg_stream_t stream)
+{
+    (void)h;
+    hipError_t e = hipStreamSynchronize(S(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "sync");
+    return HSG_OK;
+}
+
+void hsg_destroy(hsg_lattice *h) { delete h; }
+
+hsg_status hsg_debug_philox(const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int64_t n,
+                            hsg_stream_t stream)
+{
+    if (n < 0 || (n > 0 && (d_ctr == nullptr || d_key == nullptr || d_out == nullptr)))
+        return fail(HSG_E_INVALID, "bad philox arguments");
+    const hipError_t e = hsg::launch_philox(d_ctr, d_key, d_out, n, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "philox");
+    return HSG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,267 @@
+// device.h -- per-site arithmetic of the sweep, for gfx950 (wave64).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), the heat-bath draw of
+// Eq. (2), the over-relaxation reflection of Eq. (3), the spin storage codecs
+// and float64 wave / block reductions. All arithmetic is float32 except the
+// reductions; the library is compiled with -ffp-contract=off so that every
+// fused multiply-add below is one written on purpose.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace hsg {
+
+// ---------------------------------------------------------------- Philox
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+// (0, 1] from the top 24 bits; exact in float32.
+__device__ __forceinline__ float u24(uint32_t w) { return (float)((w >> 8) + 1u) * 0x1p-24f; }
+
+// (0, 1] with 53 bits from two words; exact in float64.
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b)
+{
+    const uint64_t m = ((uint64_t)a << 21) ^ (uint64_t)(b >> 11);
+    return (double)(m + 1ull) * 0x1p-53;
+}
+
+// ---------------------------------------------------------------- vectors
+struct v3 {
+    float x, y, z;
+};
+
+__device__ __forceinline__ float dot3(v3 a, v3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+
+__device__ __forceinline__ v3 scale3(v3 a, float f) { return v3{a.x * f, a.y * f, a.z * f}; }
+
+__device__ __forceinline__ v3 normalise3(v3 a) { return scale3(a, 1.0f / sqrtf(dot3(a, a))); }
+
+// Error-free sum a + b = s + e (Knuth's TwoSum).
+__device__ __forceinline__ float two_sum(float a, float b, float &e)
+{
+    const float s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
+// Rescale a vector whose length is already 1 to within ~1e-3 onto the unit
+// sphere, in float32 without a systematic bias. Plain renormalisation
+// (v / sqrt(v.v)) cannot resolve deviations below the float32 spacing at 1.0,
+// and repeated over-relaxation drifts |s| to about 1 + 4e-8 on average, which
+// biases every bond energy by twice that. Here |v|^2 - 1 is formed with
+// error-free products and sums, and the second-order series of
+// 1/sqrt(1 + d) - 1 is applied with one fused multiply-add per component.
+__device__ __forceinline__ v3 renorm_unit(v3 a)
+{
+    const float px = a.x * a.x, ex = fmaf(a.x, a.x, -px);
+    const float py = a.y * a.y, ey = fmaf(a.y, a.y, -py);
+    const float pz = a.z * a.z, ez = fmaf(a.z, a.z, -pz);
+    float e1, e2;
+    const float t = two_sum(px, py, e1);
+    const float b = two_sum(t, pz, e2);
+    const float d = (b - 1.0f) + (((e1 + e2) + (ex + ey)) + ez);  // b - 1 is exact near 1
+    const float corr = d * fmaf(0.375f, d, -0.5f);
+    return v3{fmaf(a.x, corr, a.x), fmaf(a.y, corr, a.y), fmaf(a.z, corr, a.z)};
+}
+
+// h += J * s
+__device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
+{
+    h.x = fmaf(J, s.x, h.x);
+    h.y = fmaf(J, s.y, h.y);
+    h.z = fmaf(J, s.z, h.z);
+}
+
+// ---------------------------------------------------------------- Eq. (2)
+// New spin drawn from exp(beta h.s): c = cos(angle to h) by inverting the CDF
+// of exp(kappa c) on [-1, 1], kappa = beta |h|, with two algebraically equal
+// forms of c = 1 + ln(u + (1 - u) e^{-2 kappa}) / kappa chosen for float32
+// accuracy: log1p/expm1 for small kappa (no loss near c = 2u - 1), log/exp for
+// larger kappa (the argument is a sum of two positive terms, so it never
+// cancels, and e^{-2 kappa} only underflows). Azimuth 2 pi u2 about h in the
+// frame of Frisvad (JGT 2012), which is continuous except at n = -z (a frame
+// with a jump along a whole great circle would turn float32 rounding of h into
+// O(1) jumps of the new spin); 1 + n_z is formed without cancellation for
+// n_z < 0. Zero field: uniform, z frame.
+__device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t w1)
+{
+    const float u1 = u24(w0);
+    const float u2 = u24(w1);
+    const float hh = dot3(h, h);
+    const float hn = sqrtf(hh);
+    const float kappa = beta * hn;
+    // omc = 1 - c is formed directly (it is -ln(...) / kappa), so neither c nor
+    // the transverse length sqrt((1 - c)(1 + c)) loses precision when c -> 1.
+    v3 n;
+    float omc;
+    if (hn == 0.0f || kappa == 0.0f) {
+        n = v3{0.0f, 0.0f, 1.0f};
+        omc = 2.0f * (1.0f - u1);  // c = 2 u1 - 1, exact
+    } else {
+        const float inv = 1.0f / hn;
+        n = v3{h.x * inv, h.y * inv, h.z * inv};
+        const float omu = 1.0f - u1;  // exact on the 2^-24 grid
+        float lg;
+        if (kappa < 0.5f)
+            lg = log1pf(omu * expm1f(-2.0f * kappa));
+        else
+            lg = logf(fmaf(omu, expf(-2.0f * kappa), u1));
+        omc = fminf(2.0f, fmaxf(0.0f, -lg / kappa));
+    }
+    const float c = 1.0f - omc;
+    v3 e1, e2;
+    const float rxy = fmaf(n.x, n.x, n.y * n.y);
+    if (n.z < 0.0f && rxy == 0.0f) {
+        e1 = v3{-1.0f, 0.0f, 0.0f};
+        e2 = v3{0.0f, 1.0f, 0.0f};
+    } else {
+        const float a = (n.z >= 0.0f) ? 1.0f / (1.0f + n.z) : (1.0f - n.z) / rxy;  // 1 / (1 + n_z)
+        const float b = -n.x * n.y * a;
+        e1 = v3{fmaf(-n.x * n.x, a, 1.0f), b, -n.x};
+        e2 = v3{b, fmaf(-n.y * n.y, a, 1.0f), -n.y};
+    }
+    const float st = sqrtf(omc * (2.0f - omc));
+    float sp, cp;
+    sincospif(2.0f * u2, &sp, &cp);
+    const float ta = st * cp, tb = st * sp;
+    v3 s{fmaf(c, n.x, fmaf(ta, e1.x, tb * e2.x)), fmaf(c, n.y, fmaf(ta, e1.y, tb * e2.y)),
+         fmaf(c, n.z, fmaf(ta, e1.z, tb * e2.z))};
+    return renorm_unit(s);
+}
+
+// ---------------------------------------------------------------- Eq. (3)
+// Reflection of s about the local field; a zero field leaves s unchanged. The
+// spin must be a unit vector to float32 precision (the reflection keeps |s|).
+__device__ __forceinline__ v3 over_relax(v3 s, v3 h)
+{
+    const float hh = dot3(h, h);
+    if (hh == 0.0f) return s;
+    const float f = 2.0f * dot3(s, h) / hh;
+    v3 r{fmaf(f, h.x, -s.x), fmaf(f, h.y, -s.y), fmaf(f, h.z, -s.z)};
+    return renorm_unit(r);
+}
+
+// ---------------------------------------------------------------- storage
+// Spins of one replica, one parity: three component planes of Nh values.
+template <int STORE>
+struct Codec;
+
+template <>
+struct Codec<0> {  // float32: stored renormalised, read as is
+    using T = float;
+    __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
+    {
+        return v3{p[j], p[cs + j], p[2 * cs + j]};
+    }
+    __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
+    {
+        p[j] = s.x;
+        p[cs + j] = s.y;
+        p[2 * cs + j] = s.z;
+    }
+    __device__ static __forceinline__ v3 stored_value(v3 s) { return s; }
+};
+
+template <>
+struct Codec<1> {  // float16 components (round to nearest even), renormalised on load
+    using T = __half;
+    __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
+    {
+        return normalise3(v3{__half2float(p[j]), __half2float(p[cs + j]), __half2float(p[2 * cs + j])});
+    }
+    __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
+    {
+        p[j] = __float2half_rn(s.x);
+        p[cs + j] = __float2half_rn(s.y);
+        p[2 * cs + j] = __float2half_rn(s.z);
+    }
+    __device__ static __forceinline__ v3 stored_value(v3 s)
+    {
+        return normalise3(v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
+                             __half2float(__float2half_rn(s.z))});
+    }
+};
+
+// bfloat16: the upper half of the float32 pattern, rounded to nearest even.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v)
+{
+    const uint32_t b = __float_as_uint(v);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+template <>
+struct Codec<2> {
+    using T = uint16_t;
+    __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
+    {
+        return normalise3(v3{bf16_to_f32(p[j]), bf16_to_f32(p[cs + j]), bf16_to_f32(p[2 * cs + j])});
+    }
+    __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
+    {
+        p[j] = f32_to_bf16_rne(s.x);
+        p[cs + j] = f32_to_bf16_rne(s.y);
+        p[2 * cs + j] = f32_to_bf16_rne(s.z);
+    }
+    __device__ static __forceinline__ v3 stored_value(v3 s)
+    {
+        return normalise3(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
+                             bf16_to_f32(f32_to_bf16_rne(s.z))});
+    }
+};
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over a 256-thread block, fixed order; every thread must call it. The
+// result is valid in thread 0. `red` is __shared__ double[4].
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return r;
+}
+
+// Block ids are dealt round-robin over the 8 XCDs; remap them so that each XCD
+// runs a contiguous range of logical work items (neighbouring z-slabs of the
+// same replicas share that XCD's L2).
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+    const int xcd = b & 7, idx = b >> 3, base = nb >> 3, extra = nb & 7;
+    return xcd * base + (xcd < extra ? xcd : extra) + idx;
+}
+
+}  // namespace hsg

@@ -1,0 +1,98 @@
+// kernels.h -- host-side launchers of the device kernels (internal to libhsg.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsg {
+
+constexpr int kBlock = 256;  // work-group size of the sweep and reduction kernels (4 waves)
+
+// Internal layouts (per group; d = sample, r = replica in canonical order):
+//   spins  [r][parity][3][Nh]      storage type per codec, Nh = L^3 / 2,
+//                                  element j of parity p = canonical site i with
+//                                  parity(i) = p and i >> 1 = j
+//   J6     [d][parity][6][Nh]      float32, the six couplings of each site in
+//                                  neighbour order +x, -x, +y, -y, +z, -z
+//   Hp     [d][parity][3][Nh]      float32
+struct SweepArgs {
+    void *spins;
+    const float *J6;
+    const float *Hp;             // nullptr when the group has no field
+    const int32_t *temp_of_slot; // [D][O][T] rung of each slot
+    const float *beta32;         // [T]
+    double *e_partials;          // [replica][n_pb] when the pass computes energies
+    int64_t Nh;
+    int32_t L, Lh;
+    int32_t slots_per_sample;    // O * T
+    int32_t T;
+    int32_t chunk, n_chunks, n_pb, n_blocks;
+    uint32_t t, rep, parity;
+    uint32_t key0, key1, uid_base;
+};
+
+// kind 0 = heat bath, 1 = over-relaxation.
+hipError_t launch_half_sweep(const SweepArgs &a, int storage, int kind, bool field, bool energy,
+                             hipStream_t s);
+
+// E[r] = sum over the n_pb partials of replica r, for n_rep replicas.
+hipError_t launch_reduce_partials(const double *partials, int n_pb, int64_t n_rep, double *E,
+                                  hipStream_t s);
+
+struct PtArgs {
+    int32_t *slot_at_temp;       // [D][O][T]
+    int32_t *temp_of_slot;       // [D][O][T]
+    const double *E;             // [D][O][T] by slot
+    const double *beta64;        // [T]
+    unsigned long long *accepts; // [D][O][T-1]
+    int32_t D, O, T;
+    uint32_t ctr1, purpose;
+    uint32_t key0, key1, uid_base;
+};
+hipError_t launch_pt(const PtArgs &a, hipStream_t s);
+
+struct PackArgs {
+    void *spins_int;
+    float *spins_can;  // canonical [r][3][N]
+    const float *J_can;
+    float *J6;
+    const float *H_can;
+    float *Hp;
+    int64_t n_rep, D;
+    int32_t L;
+};
+hipError_t launch_pack_spins(const PackArgs &a, int storage, hipStream_t s);
+hipError_t launch_unpack_spins(const PackArgs &a, int storage, hipStream_t s);
+hipError_t launch_pack_couplings(const PackArgs &a, hipStream_t s);
+hipError_t launch_pack_field(const PackArgs &a, hipStream_t s);
+
+// Exact float64 energy of every replica: partials [r][n_pb], n_pb = ceil(Nh / 256).
+struct EnergyArgs {
+    const void *spins;
+    const float *J6;
+    const float *Hp;
+    double *partials;
+    int64_t Nh, n_rep;
+    int32_t L, Lh, slots_per_sample, n_pb;
+};
+hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s);
+
+// Overlap of copies 0 and 1 at every rung: partials [d][k][n_pb][9] -> q [d][k][10].
+struct OverlapArgs {
+    const void *spins;
+    const int32_t *slot_at_temp;
+    double *partials;
+    double *q;
+    int64_t Nh;
+    int32_t D, O, T, n_pb;
+};
+hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s);
+
+hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
+                                     int32_t T, hipStream_t s);
+hipError_t launch_invert_maps(const int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
+                              int32_t T, hipStream_t s);
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
+                         hipStream_t s);
+
+}  // namespace hsg

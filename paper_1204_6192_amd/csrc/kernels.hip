@@ -1,0 +1,524 @@
+// kernels.hip -- device kernels of libhsg.so (gfx950).
+//
+// Checkerboard half-sweeps (Sec. 3.1; Eqs. (2) and (3)) over the parity-split
+// structure-of-arrays layout, with the couplings of a sample held in registers
+// while a work item walks several replicas of that sample (the J/H recycling
+// of Sec. 3.3); the exact float64 energy of Eq. (1) fused into the last pass;
+// the tempering walk of Eq. (4); energy and overlap (Eq. (5)) reductions; and
+// layout conversion between the canonical and internal arrays.
+#include "device.h"
+#include "kernels.h"
+
+namespace hsg {
+
+// ---------------------------------------------------------------- geometry
+struct Site {
+    int32_t x, y, z;
+};
+
+// Neighbours (in the other parity's half-index space) of the parity-p site
+// with half-index j, in the order +x, -x, +y, -y, +z, -z.
+__device__ __forceinline__ void neighbours(int64_t j, int32_t L, int32_t Lh, int p, int64_t nb[6])
+{
+    const int32_t r = (int32_t)(j / Lh);
+    const int32_t xh = (int32_t)(j - (int64_t)r * Lh);
+    const int32_t y = r % L, z = r / L;
+    const int o = (y + z + p) & 1;  // x = 2 xh + o
+    const int32_t xp = o ? (xh + 1 == Lh ? 0 : xh + 1) : xh;
+    const int32_t xm = o ? xh : (xh == 0 ? Lh - 1 : xh - 1);
+    const int32_t yp = (y + 1 == L) ? 0 : y + 1, ym = (y == 0) ? L - 1 : y - 1;
+    const int32_t zp = (z + 1 == L) ? 0 : z + 1, zm = (z == 0) ? L - 1 : z - 1;
+    const int64_t row = (int64_t)r * Lh;
+    nb[0] = row + xp;
+    nb[1] = row + xm;
+    nb[2] = ((int64_t)z * L + yp) * Lh + xh;
+    nb[3] = ((int64_t)z * L + ym) * Lh + xh;
+    nb[4] = ((int64_t)zp * L + y) * Lh + xh;
+    nb[5] = ((int64_t)zm * L + y) * Lh + xh;
+}
+
+// ---------------------------------------------------------------- half-sweep
+// One thread owns the two parity-p sites with half-indices 2q and 2q + 1 (they
+// share Philox block q) and walks `chunk` replicas of one sample, keeping the
+// sample's couplings and field in registers. Grid: samples x replica chunks x
+// blocks of 256 site pairs, remapped so each XCD gets contiguous work.
+template <int STORE, int KIND, bool FIELD, bool ENERGY>
+__global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    __shared__ double red[4];
+
+    const int lb = xcd_remap((int)blockIdx.x, a.n_blocks);
+    const int pb = lb % a.n_pb;
+    const int rest = lb / a.n_pb;
+    const int ch = rest % a.n_chunks;
+    const int d = rest / a.n_chunks;
+    const int64_t Nh = a.Nh;
+    const int64_t q = (int64_t)pb * kBlock + threadIdx.x;
+    const bool active = q < (Nh >> 1);
+    const int p = (int)a.parity;
+
+    int64_t nb[2][6];
+    float Jc[2][6];
+    v3 Hs[2] = {v3{0.f, 0.f, 0.f}, v3{0.f, 0.f, 0.f}};
+    v3 He[2] = {v3{0.f, 0.f, 0.f}, v3{0.f, 0.f, 0.f}};
+    if (active) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int64_t j = 2 * q + k;
+            neighbours(j, a.L, a.Lh, p, nb[k]);
+            const float *Jb = a.J6 + ((int64_t)d * 2 + p) * 6 * Nh;
+#pragma unroll
+            for (int n = 0; n < 6; ++n) Jc[k][n] = Jb[n * Nh + j];
+            if (FIELD) {
+                const float *Hb = a.Hp + ((int64_t)d * 2 + p) * 3 * Nh;
+                Hs[k] = v3{Hb[j], Hb[Nh + j], Hb[2 * Nh + j]};
+                if (ENERGY) {  // the field on the other parity at the same half-index
+                    const float *Ho = a.Hp + ((int64_t)d * 2 + (1 - p)) * 3 * Nh;
+                    He[k] = v3{Ho[j], Ho[Nh + j], Ho[2 * Nh + j]};
+                }
+            }
+        }
+    }
+
+    T *spins = (T *)a.spins;
+    for (int cs = 0; cs < a.chunk; ++cs) {
+        const int sis = ch * a.chunk + cs;  // replica index inside the sample: o * T + slot
+        if (sis >= a.slots_per_sample) break;
+        const int64_t rep = (int64_t)d * a.slots_per_sample + sis;
+        double e = 0.0;
+        if (active) {
+            const float beta = a.beta32[a.temp_of_slot[rep]];
+            T *base = spins + rep * 6 * Nh;
+            T *own = base + (int64_t)p * 3 * Nh;
+            const T *oth = base + (int64_t)(1 - p) * 3 * Nh;
+            u32x4 r{0u, 0u, 0u, 0u};
+            if (KIND == 0) {
+                const int o = sis / a.T, ts = sis - o * a.T;
+                const uint32_t c2 = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12) | ((uint32_t)p << 16);
+                r = philox4x32_10(u32x4{(uint32_t)q, a.t, c2, a.uid_base + (uint32_t)d}, a.key0, a.key1);
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int64_t j = 2 * q + k;
+                v3 h = Hs[k];
+                double hx = Hs[k].x, hy = Hs[k].y, hz = Hs[k].z;
+#pragma unroll
+                for (int n = 0; n < 6; ++n) {
+                    const v3 sn = C::load(oth, Nh, nb[k][n]);
+                    acc3(h, Jc[k][n], sn);
+                    if (ENERGY) {
+                        hx = fma((double)Jc[k][n], (double)sn.x, hx);
+                        hy = fma((double)Jc[k][n], (double)sn.y, hy);
+                        hz = fma((double)Jc[k][n], (double)sn.z, hz);
+                    }
+                }
+                v3 s1;
+                if (KIND == 0)
+                    s1 = heat_bath(h, beta, k ? r.z : r.x, k ? r.w : r.y);
+                else
+                    s1 = over_relax(C::load(own, Nh, j), h);
+                C::store(own, Nh, j, s1);
+                if (ENERGY) {
+                    // each bond has exactly one endpoint on this parity (the odd one)
+                    const v3 sv = C::stored_value(s1);
+                    e -= (double)sv.x * hx + (double)sv.y * hy + (double)sv.z * hz;
+                    if (FIELD) {
+                        const v3 so = C::load(oth, Nh, j);
+                        e -= (double)He[k].x * so.x + (double)He[k].y * so.y + (double)He[k].z * so.z;
+                    }
+                }
+            }
+        }
+        if (ENERGY) {
+            const double tot = block_sum(e, red);
+            if (threadIdx.x == 0) a.e_partials[rep * a.n_pb + pb] = tot;
+        }
+    }
+}
+
+template <int STORE>
+static hipError_t launch_half_sweep_s(const SweepArgs &a, int kind, bool field, bool energy, hipStream_t s)
+{
+    const dim3 grid((unsigned)a.n_blocks), block(kBlock);
+#define HSG_L(K, F, E) hipLaunchKernelGGL((k_half_sweep<STORE, K, F, E>), grid, block, 0, s, a)
+    if (kind == 0) {
+        if (field) { if (energy) HSG_L(0, true, true); else HSG_L(0, true, false); }
+        else { if (energy) HSG_L(0, false, true); else HSG_L(0, false, false); }
+    } else {
+        if (field) { if (energy) HSG_L(1, true, true); else HSG_L(1, true, false); }
+        else { if (energy) HSG_L(1, false, true); else HSG_L(1, false, false); }
+    }
+#undef HSG_L
+    return hipGetLastError();
+}
+
+hipError_t launch_half_sweep(const SweepArgs &a, int storage, int kind, bool field, bool energy, hipStream_t s)
+{
+    switch (storage) {
+    case 0: return launch_half_sweep_s<0>(a, kind, field, energy, s);
+    case 1: return launch_half_sweep_s<1>(a, kind, field, energy, s);
+    case 2: return launch_half_sweep_s<2>(a, kind, field, energy, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------- partial sums
+// One wave per replica; lane l adds partials l, l + 64, ... in order, then a
+// fixed butterfly: the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *partials, int n_pb, int64_t n_rep, double *E)
+{
+    const int64_t rep = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    double v = 0.0;
+    if (rep < n_rep)
+        for (int i = lane; i < n_pb; i += 64) v += partials[rep * n_pb + i];
+    v = wave_sum(v);
+    if (rep < n_rep && lane == 0) E[rep] = v;
+}
+
+hipError_t launch_reduce_partials(const double *partials, int n_pb, int64_t n_rep, double *E, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((n_rep + 3) / 4);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(blocks), dim3(256), 0, s, partials, n_pb, n_rep, E);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- tempering
+// One thread per (sample, copy) ladder walks k = 0 .. T-2 from the lowest
+// temperature; float64 acceptance exponent (Eq. (4)); temperatures move.
+__global__ __launch_bounds__(64) void k_pt(PtArgs a)
+{
+    const int64_t lad = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lad >= (int64_t)a.D * a.O) return;
+    const int d = (int)(lad / a.O), o = (int)(lad - (int64_t)d * a.O);
+    int32_t *sat = a.slot_at_temp + lad * a.T;
+    int32_t *tos = a.temp_of_slot + lad * a.T;
+    const double *E = a.E + lad * a.T;
+    for (int k = 0; k + 1 < a.T; ++k) {
+        const int32_t sa = sat[k], sb = sat[k + 1];
+        const double delta = (a.beta64[k + 1] - a.beta64[k]) * (E[sb] - E[sa]);
+        const u32x4 r = philox4x32_10(
+            u32x4{(uint32_t)k, a.ctr1, ((uint32_t)o << 8) | (a.purpose << 20), a.uid_base + (uint32_t)d}, a.key0,
+            a.key1);
+        const double u = u53(r.x, r.y);
+        if (delta >= 0.0 || u <= exp(delta)) {
+            sat[k] = sb;
+            sat[k + 1] = sa;
+            tos[sb] = k;
+            tos[sa] = k + 1;
+            a.accepts[lad * (a.T - 1) + k] += 1ull;
+        }
+    }
+}
+
+hipError_t launch_pt(const PtArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.D * a.O;
+    if (a.T < 2 || n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pt, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- layouts
+__device__ __forceinline__ Site site_of(int64_t i, int32_t L)
+{
+    Site c;
+    c.x = (int32_t)(i % L);
+    const int64_t r = i / L;
+    c.y = (int32_t)(r % L);
+    c.z = (int32_t)(r / L);
+    return c;
+}
+
+__device__ __forceinline__ int64_t index_of(int32_t x, int32_t y, int32_t z, int32_t L)
+{
+    x = (x + L) % L;
+    y = (y + L) % L;
+    z = (z + L) % L;
+    return (int64_t)x + (int64_t)L * ((int64_t)y + (int64_t)L * z);
+}
+
+template <int STORE>
+__global__ __launch_bounds__(256) void k_pack_spins(PackArgs a)
+{
+    using C = Codec<STORE>;
+    const int64_t N = (int64_t)a.L * a.L * a.L, Nh = N / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n_rep * N) return;
+    const int64_t rep = gid / N, i = gid - rep * N;
+    const Site c = site_of(i, a.L);
+    const int p = (c.x + c.y + c.z) & 1;
+    const float *src = a.spins_can + rep * 3 * N;
+    typename C::T *dst = (typename C::T *)a.spins_int + rep * 6 * Nh + (int64_t)p * 3 * Nh;
+    C::store(dst, Nh, i >> 1, v3{src[i], src[N + i], src[2 * N + i]});
+}
+
+template <int STORE>
+__global__ __launch_bounds__(256) void k_unpack_spins(PackArgs a)
+{
+    using C = Codec<STORE>;
+    const int64_t N = (int64_t)a.L * a.L * a.L, Nh = N / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.n_rep * N) return;
+    const int64_t rep = gid / N, i = gid - rep * N;
+    const Site c = site_of(i, a.L);
+    const int p = (c.x + c.y + c.z) & 1;
+    const typename C::T *src = (const typename C::T *)a.spins_int + rep * 6 * Nh + (int64_t)p * 3 * Nh;
+    const v3 s = C::load(src, Nh, i >> 1);
+    float *dst = a.spins_can + rep * 3 * N;
+    dst[i] = s.x;
+    dst[N + i] = s.y;
+    dst[2 * N + i] = s.z;
+}
+
+__global__ __launch_bounds__(256) void k_pack_couplings(PackArgs a)
+{
+    const int64_t N = (int64_t)a.L * a.L * a.L, Nh = N / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.D * N) return;
+    const int64_t d = gid / N, i = gid - d * N;
+    const Site c = site_of(i, a.L);
+    const int p = (c.x + c.y + c.z) & 1;
+    const int64_t j = i >> 1;
+    const float *Jc = a.J_can + d * 3 * N;
+    float *J6 = a.J6 + (d * 2 + p) * 6 * Nh;
+    J6[0 * Nh + j] = Jc[0 * N + i];
+    J6[1 * Nh + j] = Jc[0 * N + index_of(c.x - 1, c.y, c.z, a.L)];
+    J6[2 * Nh + j] = Jc[1 * N + i];
+    J6[3 * Nh + j] = Jc[1 * N + index_of(c.x, c.y - 1, c.z, a.L)];
+    J6[4 * Nh + j] = Jc[2 * N + i];
+    J6[5 * Nh + j] = Jc[2 * N + index_of(c.x, c.y, c.z - 1, a.L)];
+}
+
+__global__ __launch_bounds__(256) void k_pack_field(PackArgs a)
+{
+    const int64_t N = (int64_t)a.L * a.L * a.L, Nh = N / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= a.D * N) return;
+    const int64_t d = gid / N, i = gid - d * N;
+    const Site c = site_of(i, a.L);
+    const int p = (c.x + c.y + c.z) & 1;
+    const int64_t j = i >> 1;
+    const float *Hc = a.H_can + d * 3 * N;
+    float *Hp = a.Hp + (d * 2 + p) * 3 * Nh;
+    for (int m = 0; m < 3; ++m) Hp[m * Nh + j] = Hc[m * N + i];
+}
+
+static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+hipError_t launch_pack_spins(const PackArgs &a, int storage, hipStream_t s)
+{
+    const int64_t n = a.n_rep * (int64_t)a.L * a.L * a.L;
+    if (n == 0) return hipSuccess;
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_pack_spins<0>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_pack_spins<1>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_pack_spins<2>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_spins(const PackArgs &a, int storage, hipStream_t s)
+{
+    const int64_t n = a.n_rep * (int64_t)a.L * a.L * a.L;
+    if (n == 0) return hipSuccess;
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_unpack_spins<0>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_unpack_spins<1>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_unpack_spins<2>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_couplings(const PackArgs &a, hipStream_t s)
+{
+    const int64_t n = a.D * (int64_t)a.L * a.L * a.L;
+    hipLaunchKernelGGL(k_pack_couplings, dim3(blocks_for(n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_field(const PackArgs &a, hipStream_t s)
+{
+    const int64_t n = a.D * (int64_t)a.L * a.L * a.L;
+    hipLaunchKernelGGL(k_pack_field, dim3(blocks_for(n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- energy
+// Exact float64 energy of Eq. (1): every bond has one even endpoint, so the sum
+// over even sites of s_i . sum_n J_n s_n counts each bond once; the field term
+// runs over both parities at the same half-index.
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    __shared__ double red[4];
+    const int64_t rep = blockIdx.x / a.n_pb;
+    const int pb = (int)(blockIdx.x - rep * a.n_pb);
+    const int64_t Nh = a.Nh;
+    const int64_t j = (int64_t)pb * kBlock + threadIdx.x;
+    const int64_t d = rep / a.slots_per_sample;
+    double e = 0.0;
+    if (j < Nh) {
+        const T *base = (const T *)a.spins + rep * 6 * Nh;
+        int64_t nb[6];
+        neighbours(j, a.L, a.Lh, 0, nb);
+        const v3 s0 = C::load(base, Nh, j);
+        const float *J6 = a.J6 + (d * 2 + 0) * 6 * Nh;
+        for (int n = 0; n < 6; ++n) {
+            const v3 sn = C::load(base + 3 * Nh, Nh, nb[n]);
+            const double sd = (double)s0.x * sn.x + (double)s0.y * sn.y + (double)s0.z * sn.z;
+            e -= (double)J6[n * Nh + j] * sd;
+        }
+        if (a.Hp != nullptr) {
+            const v3 s1 = C::load(base + 3 * Nh, Nh, j);
+            const float *H0 = a.Hp + (d * 2 + 0) * 3 * Nh;
+            const float *H1 = a.Hp + (d * 2 + 1) * 3 * Nh;
+            e -= (double)H0[j] * s0.x + (double)H0[Nh + j] * s0.y + (double)H0[2 * Nh + j] * s0.z;
+            e -= (double)H1[j] * s1.x + (double)H1[Nh + j] * s1.y + (double)H1[2 * Nh + j] * s1.z;
+        }
+    }
+    const double tot = block_sum(e, red);
+    if (threadIdx.x == 0) a.partials[rep * a.n_pb + pb] = tot;
+}
+
+hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s)
+{
+    const int64_t blocks = a.n_rep * a.n_pb;
+    if (blocks == 0) return hipSuccess;
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_energy<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_energy<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_energy<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- overlap
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_overlap(OverlapArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    __shared__ double red[4];
+    const int64_t dk = blockIdx.x / a.n_pb;  // d * T + k
+    const int pb = (int)(blockIdx.x - dk * a.n_pb);
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int64_t Nh = a.Nh;
+    const int64_t j = (int64_t)pb * kBlock + threadIdx.x;
+    const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
+    const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
+    const T *A = (const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 6 * Nh;
+    const T *B = (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 6 * Nh;
+    double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (j < Nh) {
+        for (int p = 0; p < 2; ++p) {
+            const v3 x = C::load(A + (int64_t)p * 3 * Nh, Nh, j);
+            const v3 y = C::load(B + (int64_t)p * 3 * Nh, Nh, j);
+            const double xa[3] = {x.x, x.y, x.z}, ya[3] = {y.x, y.y, y.z};
+            for (int m = 0; m < 3; ++m)
+                for (int n = 0; n < 3; ++n) acc[3 * m + n] += xa[m] * ya[n];
+        }
+    }
+    for (int m = 0; m < 9; ++m) {
+        const double tot = block_sum(acc[m], red);
+        if (threadIdx.x == 0) a.partials[(dk * a.n_pb + pb) * 9 + m] = tot;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_overlap_finish(OverlapArgs a)
+{
+    const int64_t dk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (dk >= (int64_t)a.D * a.T) return;
+    const double invN = 1.0 / (double)(2 * a.Nh);
+    double q2 = 0.0;
+    for (int m = 0; m < 9; ++m) {
+        double v = 0.0;
+        for (int pb = 0; pb < a.n_pb; ++pb) v += a.partials[(dk * a.n_pb + pb) * 9 + m];
+        v *= invN;
+        a.q[dk * 10 + m] = v;
+        q2 += v * v;
+    }
+    a.q[dk * 10 + 9] = q2;
+}
+
+hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)a.D * a.T * a.n_pb;
+    if (blocks == 0) return hipSuccess;
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_overlap<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_overlap<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_overlap<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)a.D * a.T;
+    hipLaunchKernelGGL(k_overlap_finish, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- maps
+__global__ __launch_bounds__(256) void k_fill_identity(int32_t *sat, int32_t *tos, int64_t n_lad, int32_t T)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_lad * T) return;
+    const int32_t k = (int32_t)(g % T);
+    sat[g] = k;
+    tos[g] = k;
+}
+
+__global__ __launch_bounds__(256) void k_invert(const int32_t *sat, int32_t *tos, int64_t n_lad, int32_t T)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_lad * T) return;
+    const int64_t lad = g / T;
+    const int32_t k = (int32_t)(g - lad * T);
+    const int32_t s = sat[g];
+    if (s >= 0 && s < T) tos[lad * T + s] = k;
+}
+
+hipError_t launch_fill_identity_maps(int32_t *sat, int32_t *tos, int64_t n_lad, int32_t T, hipStream_t s)
+{
+    const int64_t n = n_lad * T;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_identity, dim3(blocks_for(n)), dim3(256), 0, s, sat, tos, n_lad, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_maps(const int32_t *sat, int32_t *tos, int64_t n_lad, int32_t T, hipStream_t s)
+{
+    const int64_t n = n_lad * T;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert, dim3(blocks_for(n)), dim3(256), 0, s, sat, tos, n_lad, T);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- debug
+__global__ __launch_bounds__(256) void k_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const u32x4 r = philox4x32_10(u32x4{ctr[4 * g], ctr[4 * g + 1], ctr[4 * g + 2], ctr[4 * g + 3]},
+                                  key[2 * g], key[2 * g + 1]);
+    out[4 * g] = r.x;
+    out[4 * g + 1] = r.y;
+    out[4 * g + 2] = r.z;
+    out[4 * g + 3] = r.w;
+}
+
+hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_philox, dim3(blocks_for(n)), dim3(256), 0, s, ctr, key, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace hsg

@@ -1,0 +1,276 @@
+"""Thin ctypes binding of libhsg.so (see include/hsg.h for the contract).
+
+Argument marshalling only: every step of the sweep runs in the HIP kernels of
+the library. PyTorch supplies device memory and the stream. Importing this
+module fails loudly if the library has not been built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsg.so")
+HEADER_PATH = os.path.join(_HERE, "..", "include", "hsg.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                      "g.build()'` (or paper_1204_6192_amd/build.py); there is no fallback path")
+
+OK, E_INVALID, E_SIZE, E_UNSUPPORTED, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "qangle": 3}
+
+
+class HSGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hsg status {status}: {msg}")
+        self.status = status
+
+
+class GroupDesc(C.Structure):
+    _fields_ = [("L", C.c_int32), ("n_samples", C.c_int32), ("n_copies", C.c_int32),
+                ("n_temps", C.c_int32), ("temps", C.POINTER(C.c_double)),
+                ("sample_uid_base", C.c_uint32), ("has_field", C.c_int32),
+                ("coupling_kind", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Desc(C.Structure):
+    _fields_ = [("groups", C.POINTER(GroupDesc)), ("n_groups", C.c_int32), ("storage", C.c_int32),
+                ("n_hb", C.c_int32), ("n_or", C.c_int32), ("pt_every", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("state_bytes", C.c_uint64), ("coupling_bytes", C.c_uint64),
+                ("field_bytes", C.c_uint64), ("scratch_bytes", C.c_uint64),
+                ("n_replicas", C.c_uint64), ("n_spins", C.c_uint64)]
+
+
+# The process must hold one HIP runtime. libhsg.so needs libamdhip64.so.7; torch
+# (used for device memory and streams) brings its own copy with that soname, so
+# importing torch first makes the loader bind libhsg.so to torch's runtime.
+import torch  # noqa: E402,F401  (must precede the CDLL below)
+
+lib = C.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({line.split()[-1] for line in f if "libamdhip64" in line})
+    except OSError:
+        return []
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are loaded in this process (%s); import torch before "
+                      "anything else loads libamdhip64" % ", ".join(_hip_runtimes()))
+_vp, _i32, _i64, _u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+_SIG = {
+    "hsg_query_sizes": [C.POINTER(Desc), C.POINTER(Sizes)],
+    "hsg_init_lattice": [C.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)],
+    "hsg_sweep": [_vp, _i32, _vp],
+    "hsg_half_sweep": [_vp, _i32, _i32, _i32, _vp],
+    "hsg_pt_exchange": [_vp, _vp],
+    "hsg_measure_energy": [_vp, _vp, _vp],
+    "hsg_get_energies": [_vp, _vp, _vp],
+    "hsg_measure_overlap": [_vp, _vp, _vp],
+    "hsg_get_spins": [_vp, _vp, _vp],
+    "hsg_set_spins": [_vp, _vp, _vp],
+    "hsg_get_temp_map": [_vp, _vp, _vp],
+    "hsg_set_temp_map": [_vp, _vp, _vp],
+    "hsg_get_pt_accepts": [_vp, _vp, _vp],
+    "hsg_get_state": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
+    "hsg_set_state": [_vp, _u64, _u64],
+    "hsg_set_tuning": [_vp, _i32],
+    "hsg_sync": [_vp, _vp],
+    "hsg_debug_philox": [_vp, _vp, _vp, _i64, _vp],
+}
+for _name, _args in _SIG.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = C.c_int32
+lib.hsg_destroy.argtypes = [_vp]
+lib.hsg_destroy.restype = None
+lib.hsg_last_error.argtypes = []
+lib.hsg_last_error.restype = C.c_char_p
+
+
+def declared_symbols() -> List[str]:
+    """Names of the functions declared in include/hsg.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsg_[a-z_0-9]+)\s*\(", text)))
+
+
+def check(status: int) -> None:
+    if status != OK:
+        raise HSGError(status, lib.hsg_last_error().decode())
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def make_desc(groups, storage: str, n_hb: int, n_or: int, pt_every: int, seed: int):
+    """Build the ctypes description; returns (desc, keep-alive list)."""
+    keep = []
+    arr = (GroupDesc * len(groups))()
+    for k, g in enumerate(groups):
+        temps = np.ascontiguousarray(g.temps, dtype=np.float64)
+        keep.append(temps)
+        arr[k] = GroupDesc(L=g.L, n_samples=g.n_samples, n_copies=g.n_copies, n_temps=len(temps),
+                           temps=temps.ctypes.data_as(C.POINTER(C.c_double)),
+                           sample_uid_base=g.sample_uid_base, has_field=int(g.H is not None),
+                           coupling_kind=g.coupling_kind, reserved=0)
+    keep.append(arr)
+    d = Desc(groups=arr, n_groups=len(groups), storage=STORAGE[storage], n_hb=n_hb, n_or=n_or,
+             pt_every=pt_every, reserved=0, seed=seed & 0xFFFFFFFFFFFFFFFF)
+    return d, keep
+
+
+def query_sizes(desc: Desc) -> Sizes:
+    out = Sizes()
+    check(lib.hsg_query_sizes(C.byref(desc), C.byref(out)))
+    return out
+
+
+class Lattice:
+    """One handle of the library plus the caller-owned device buffers (torch)."""
+
+    def __init__(self, groups: Sequence, *, storage: str = "f32", n_hb: int = 1, n_or: int = 4,
+                 pt_every: int = 1, seed: int = 0, device: str = "cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.groups = list(groups)
+        self.device = torch.device(device)
+        self.desc, self._keep = make_desc(self.groups, storage, n_hb, n_or, pt_every, seed)
+        self.sizes = query_sizes(self.desc)
+        self.n_replicas = int(self.sizes.n_replicas)
+        self.n_spins = int(self.sizes.n_spins)
+
+        def buf(nbytes):
+            return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=self.device)
+
+        self.state = buf(self.sizes.state_bytes)
+        self.couplings = buf(self.sizes.coupling_bytes)
+        self.field = buf(self.sizes.field_bytes) if self.sizes.field_bytes else None
+        self.scratch = buf(self.sizes.scratch_bytes)
+        spins0 = torch.cat([torch.from_numpy(np.ascontiguousarray(g.spins0)).reshape(-1)
+                            for g in self.groups]).to(self.device)
+        J = torch.cat([torch.from_numpy(np.ascontiguousarray(g.J)).reshape(-1)
+                       for g in self.groups]).to(self.device)
+        Hs = [g.H for g in self.groups]
+        H = None
+        if any(h is not None for h in Hs):
+            H = torch.cat([torch.from_numpy(np.ascontiguousarray(
+                h if h is not None else np.zeros_like(g.J))).reshape(-1)
+                for g, h in zip(self.groups, Hs)]).to(self.device)
+        self.stream = stream
+        handle = C.c_void_p()
+        check(lib.hsg_init_lattice(C.byref(self.desc), _ptr(spins0), _ptr(J),
+                                   _ptr(H) if H is not None else None, _ptr(self.state),
+                                   _ptr(self.couplings),
+                                   _ptr(self.field) if self.field is not None else None,
+                                   _ptr(self.scratch), _stream(stream), C.byref(handle)))
+        self.h = handle
+
+    # -- the calls of the ABI, same names ------------------------------------
+    def sweep(self, n: int = 1) -> None:
+        check(lib.hsg_sweep(self.h, int(n), _stream(self.stream)))
+
+    def half_sweep(self, kind: int, parity: int, rep: int = 0) -> None:
+        check(lib.hsg_half_sweep(self.h, int(kind), int(parity), int(rep), _stream(self.stream)))
+
+    def pt_exchange(self) -> None:
+        check(lib.hsg_pt_exchange(self.h, _stream(self.stream)))
+
+    def measure_energy(self):
+        E = self.torch.empty(self.n_replicas, dtype=self.torch.float64, device=self.device)
+        check(lib.hsg_measure_energy(self.h, _ptr(E), _stream(self.stream)))
+        return E
+
+    def get_energies(self):
+        E = self.torch.empty(self.n_replicas, dtype=self.torch.float64, device=self.device)
+        check(lib.hsg_get_energies(self.h, _ptr(E), _stream(self.stream)))
+        return E
+
+    def measure_overlap(self):
+        n = sum(g.n_samples * g.n_temps * 10 for g in self.groups)
+        q = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        check(lib.hsg_measure_overlap(self.h, _ptr(q), _stream(self.stream)))
+        return q
+
+    def get_spins(self):
+        s = self.torch.empty(self.n_spins * 3, dtype=self.torch.float32, device=self.device)
+        check(lib.hsg_get_spins(self.h, _ptr(s), _stream(self.stream)))
+        return s
+
+    def set_spins(self, s) -> None:
+        assert s.dtype == self.torch.float32 and s.numel() == self.n_spins * 3 and s.is_contiguous()
+        check(lib.hsg_set_spins(self.h, _ptr(s), _stream(self.stream)))
+
+    def get_temp_map(self):
+        m = self.torch.empty(self.n_replicas, dtype=self.torch.int32, device=self.device)
+        check(lib.hsg_get_temp_map(self.h, _ptr(m), _stream(self.stream)))
+        return m
+
+    def set_temp_map(self, m) -> None:
+        assert m.dtype == self.torch.int32 and m.numel() == self.n_replicas and m.is_contiguous()
+        check(lib.hsg_set_temp_map(self.h, _ptr(m), _stream(self.stream)))
+
+    def get_pt_accepts(self):
+        n = sum(g.n_samples * g.n_copies * (g.n_temps - 1) for g in self.groups)
+        a = self.torch.zeros(max(n, 1), dtype=self.torch.int64, device=self.device)
+        check(lib.hsg_get_pt_accepts(self.h, _ptr(a), _stream(self.stream)))
+        return a[:n]
+
+    def get_state(self):
+        t, n, s = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        check(lib.hsg_get_state(self.h, C.byref(t), C.byref(n), C.byref(s)))
+        return int(t.value), int(n.value), int(s.value)
+
+    def set_state(self, sweep_counter: int, pt_calls: int = 0) -> None:
+        check(lib.hsg_set_state(self.h, int(sweep_counter), int(pt_calls)))
+
+    def set_tuning(self, slots_per_item: int) -> None:
+        check(lib.hsg_set_tuning(self.h, int(slots_per_item)))
+
+    def sync(self) -> None:
+        check(lib.hsg_sync(self.h, _stream(self.stream)))
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            lib.hsg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def debug_philox(ctr, key):
+    """Device Philox4x32-10 on n blocks: ctr [n, 4], key [n, 2] (uint32 numpy)."""
+    import torch
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32)
+    key = np.ascontiguousarray(key, dtype=np.uint32)
+    n = ctr.shape[0]
+    dc = torch.from_numpy(ctr.view(np.int32)).cuda()
+    dk = torch.from_numpy(key.view(np.int32)).cuda()
+    out = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    check(lib.hsg_debug_philox(_ptr(dc), _ptr(dk), _ptr(out), n, _stream(None)))
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)

@@ -1,0 +1,117 @@
+"""The C-ABI library loads, exports every declared entry point, sizes buffers as
+documented and rejects bad descriptions before touching a device (CPU only)."""
+
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_1204_6192_amd import hsg, inputs
+
+
+def test_every_declared_symbol_is_exported():
+    names = hsg.declared_symbols()
+    assert "hsg_init_lattice" in names and "hsg_sweep" in names
+    for n in names:
+        assert hasattr(hsg.lib, n), n
+
+
+def _desc(groups, **kw):
+    args = dict(storage="f32", n_hb=1, n_or=4, pt_every=1, seed=1)
+    args.update(kw)
+    return hsg.make_desc(groups, **args)
+
+
+def _group(L=8, D=2, O=2, T=4, field=False):
+    rng = np.random.default_rng(0)
+    return inputs.make_group(rng, L, D, O, inputs.geometric_ladder(0.1, 0.3, T),
+                             field=("gaussian", 0.1) if field else None)
+
+
+def test_query_sizes_formula():
+    g = _group(L=8, D=2, O=2, T=4, field=True)
+    d, keep = _desc([g])
+    sz = hsg.query_sizes(d)
+    n_rep = 2 * 2 * 4
+    assert sz.n_replicas == n_rep
+    assert sz.n_spins == n_rep * 512
+    assert sz.state_bytes >= n_rep * 3 * 512 * 4
+    assert sz.coupling_bytes >= 2 * 6 * 512 * 4
+    assert sz.field_bytes >= 2 * 3 * 512 * 4
+    for f in ("state_bytes", "coupling_bytes", "field_bytes", "scratch_bytes"):
+        assert getattr(sz, f) % 256 == 0
+    d16, keep16 = _desc([g], storage="f16")
+    assert hsg.query_sizes(d16).state_bytes < sz.state_bytes
+    d0, keep0 = _desc([_group(field=False)])
+    assert hsg.query_sizes(d0).field_bytes == 0
+
+
+def _status(desc):
+    out = hsg.Sizes()
+    return hsg.lib.hsg_query_sizes(C.byref(desc), C.byref(out))
+
+
+@pytest.mark.parametrize("L", [3, 2, 0, 7, 2048])
+def test_bad_L_rejected(L):
+    g = _group()
+    g.L = L
+    d, keep = _desc([g])
+    assert _status(d) == hsg.E_INVALID
+    assert b"L" in hsg.lib.hsg_last_error()
+
+
+def test_bad_temperatures_rejected():
+    for temps in ([0.2, 0.1], [0.1, 0.1], [-0.1, 0.2], [0.0, 1.0], [0.1, float("inf")],
+                  [float("nan"), 1.0]):
+        g = _group(T=2)
+        g.temps = np.array(temps)
+        d, keep = _desc([g])
+        assert _status(d) == hsg.E_INVALID, temps
+
+
+def test_bad_mix_and_storage():
+    g = _group()
+    d, keep = _desc([g], n_hb=0, n_or=0)
+    assert _status(d) == hsg.E_INVALID
+    d, keep = _desc([g], n_hb=17)
+    assert _status(d) == hsg.E_SIZE
+    d, keep = _desc([g], pt_every=-1)
+    assert _status(d) == hsg.E_INVALID
+    d, keep = _desc([g])
+    d.storage = 9
+    assert _status(d) == hsg.E_INVALID
+    d.storage = hsg.STORAGE["qangle"]
+    assert _status(d) == hsg.E_UNSUPPORTED
+    d, keep = _desc([g])
+    d.n_groups = 0
+    assert _status(d) == hsg.E_INVALID
+    g2 = _group(T=300)
+    d, keep = _desc([g2])
+    assert _status(d) == hsg.E_SIZE
+
+
+def test_init_rejects_null_buffers_without_device():
+    g = _group()
+    d, keep = _desc([g])
+    h = C.c_void_p()
+    st = hsg.lib.hsg_init_lattice(C.byref(d), None, None, None, None, None, None, None, None,
+                                  C.byref(h))
+    assert st == hsg.E_INVALID and not h.value
+    st = hsg.lib.hsg_init_lattice(C.byref(d), 256, 256, None, 256, 256, None, None, None,
+                                  C.byref(h))
+    assert st == hsg.E_INVALID  # scratch missing
+    st = hsg.lib.hsg_init_lattice(C.byref(d), 256, 256, None, 257, 256, None, 256, None,
+                                  C.byref(h))
+    assert st == hsg.E_INVALID and b"aligned" in hsg.lib.hsg_last_error()
+    gf = _group(field=True)
+    df, keepf = _desc([gf])
+    st = hsg.lib.hsg_init_lattice(C.byref(df), 256, 256, None, 256, 256, 256, 256, None,
+                                  C.byref(h))
+    assert st == hsg.E_INVALID and b"field" in hsg.lib.hsg_last_error()
+
+
+def test_null_handle_calls_fail_cleanly():
+    for name, extra in (("hsg_sweep", (1, None)), ("hsg_pt_exchange", (None,)),
+                        ("hsg_measure_energy", (None, None)), ("hsg_set_tuning", (0,))):
+        assert getattr(hsg.lib, name)(None, *extra) == hsg.E_INVALID
+    hsg.lib.hsg_destroy(None)

@@ -1,0 +1,456 @@
+"""Parity of the HIP path (through the C-ABI) with the float64 oracle on the GPU.
+
+Both sides consume the same seeded inputs and the same Philox streams; the
+oracle never sees anything the GPU produced. Tolerances:
+
+* per spin component, float32 path vs float64 oracle: 1e-4 wherever the
+  chain's own sensitivity permits it, and at every sweep within SHADOW_FACTOR
+  times the drift of oracle runs whose updates are perturbed at the float32
+  rounding scale (the chain amplifies differences about tenfold per sweep from
+  a random start, so no float32 trajectory can stay within 1e-4 of the float64
+  one for 10 sweeps);
+* energies and overlaps of identical configurations: 1e-12 relative (float64
+  accumulation of float32 products, different summation order);
+* integer results (tempering decisions, temperature maps, Philox words): exact.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from paper_1204_6192_amd import inputs  # noqa: E402
+
+TOL_SPIN = 1e-4
+SHADOW_FACTOR = 10.0
+
+
+@pytest.fixture(scope="module")
+def hsg():
+    from paper_1204_6192_amd import hsg as mod
+    return mod
+
+
+def _lat(hsg, groups, inst_seed, **kw):
+    return hsg.Lattice(groups, seed=inst_seed, **kw)
+
+
+def _gpu_spins(lat, g_index=0):
+    s = lat.get_spins().cpu().numpy()
+    off = 0
+    for k, g in enumerate(lat.groups):
+        n = g.n_slots * 3 * g.N
+        if k == g_index:
+            return s[off:off + n].reshape(g.n_samples, g.n_copies, g.n_temps, 3, g.N)
+        off += n
+
+
+def _maps(lat, g_index=0):
+    m = lat.get_temp_map().cpu().numpy()
+    off = 0
+    for k, g in enumerate(lat.groups):
+        if k == g_index:
+            return m[off:off + g.n_slots].reshape(g.n_samples, g.n_copies, g.n_temps)
+        off += g.n_slots
+
+
+def _energies(E, lat, g_index=0):
+    E = E.cpu().numpy()
+    off = 0
+    for k, g in enumerate(lat.groups):
+        if k == g_index:
+            return E[off:off + g.n_slots].reshape(g.n_samples, g.n_copies, g.n_temps)
+        off += g.n_slots
+
+
+def test_device_philox_bit_exact(hsg, oracle_lib):
+    rng = np.random.default_rng(1)
+    n = 4096
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    out = hsg.debug_philox(ctr, key)
+    for i in range(0, n, 7):
+        assert np.array_equal(out[i], oracle_lib.philox(ctr[i], key[i])), i
+
+
+def test_spins_roundtrip_and_initial_measurements(hsg, oracle_lib):
+    inst = inputs.make_instance("tiny")
+    g = inst.groups[0]
+    lat = _lat(hsg, inst.groups, inst.seed)
+    s = _gpu_spins(lat)
+    assert np.array_equal(s, g.spins0)
+    o = oracle_lib.Oracle.from_group(g, seed=inst.seed)
+    E = _energies(lat.measure_energy(), lat)
+    Eo = o.compute_energies()
+    assert np.allclose(E, Eo, rtol=1e-12, atol=1e-10)
+    q = lat.measure_overlap().cpu().numpy().reshape(g.n_samples, g.n_temps, 10)
+    assert np.allclose(q, o.measure_overlap(), rtol=1e-12, atol=1e-14)
+    assert np.array_equal(_maps(lat), o.slot_at_temp)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_single_half_sweep(hsg, oracle_lib, kind):
+    inst = inputs.make_instance("tiny")
+    g = inst.groups[0]
+    lat = _lat(hsg, inst.groups, inst.seed)
+    o = oracle_lib.Oracle.from_group(g, seed=inst.seed)
+    for p in (0, 1):
+        lat.half_sweep(kind, p)
+        o.half_sweep(kind, p)
+        err = np.abs(_gpu_spins(lat) - o.spins).max()
+        print(f"kind {kind} parity {p}: max |ds| = {err:.3e}", flush=True)
+        assert err < 1e-5
+
+
+NOISE_EPS = 2.0 ** -22  # per-update relative noise of the reference runs (a few float32 roundings)
+N_REFS = 3
+
+
+def _references(oracle_lib, group, kw, n, tag):
+    """Oracle runs whose every update is perturbed by relative NOISE_EPS (a
+    test-only probe of the oracle), each with its own noise stream."""
+    refs = []
+    for k in range(n):
+        r = oracle_lib.Oracle.from_group(group, **kw)
+        r.set_noise(NOISE_EPS, 1000 * tag + k)
+        refs.append(r)
+    return refs
+
+
+def _rms(a):
+    return float(np.sqrt((np.asarray(a, dtype=np.float64) ** 2).mean()))
+
+
+def _trajectory(hsg, oracle_lib, inst, n_sweeps, storage="f32", spin_tol=TOL_SPIN,
+                shadow_factor=SHADOW_FACTOR):
+    """GPU vs oracle over n_sweeps from the same seeded start.
+
+    The chain amplifies any difference in the spins by roughly an order of
+    magnitude per sweep from a random start (a positive Lyapunov exponent of the
+    over-relaxation / heat-bath dynamics), so no float32 trajectory stays within
+    a fixed distance of the float64 one for long. Reference runs of the oracle
+    with every update perturbed at the float32 rounding scale show how far two
+    correct trajectories drift apart. Checks, while the references are still in
+    the linear regime (RMS drift < 1e-3):
+      * every spin component within spin_tol whenever all references stay ten
+        times below it (the chain's own sensitivity allows the bound);
+      * RMS and maximum spin deviation within shadow_factor times the largest of
+        the references';
+      * RMS energy deviation within shadow_factor times the references' plus
+        2^-22 |E| (float32 spins are unit only to 2^-23, which scales each bond
+        term by up to 2^-22);
+      * temperature maps equal while every reference's maps equal the oracle's.
+    At every sweep the fused energy of the last pass equals the full
+    recomputation of the GPU's own spins.
+    """
+    lat = _lat(hsg, inst.groups, inst.seed, storage=storage, n_hb=inst.n_hb, n_or=inst.n_or,
+               pt_every=inst.pt_every)
+    kw = dict(seed=inst.seed, n_hb=inst.n_hb, n_or=inst.n_or, pt_every=inst.pt_every,
+              storage=storage)
+    orcs = [oracle_lib.Oracle.from_group(g, **kw) for g in inst.groups]
+    refs = [_references(oracle_lib, g, kw, N_REFS, k + 1) for k, g in enumerate(inst.groups)]
+    maps_track = [True] * len(inst.groups)
+    for t in range(n_sweeps):
+        lat.sweep(1)
+        for o, rs in zip(orcs, refs):
+            o.sweep(1)
+            for r in rs:
+                r.sweep(1)
+        E = lat.get_energies()
+        Em = lat.measure_energy()
+        for k, (g, o, rs) in enumerate(zip(inst.groups, orcs, refs)):
+            d = np.abs(_gpu_spins(lat, k) - o.spins)
+            Eg, Emg = _energies(E, lat, k), _energies(Em, lat, k)
+            r_rms = max(_rms(r.spins - o.spins) for r in rs)
+            r_max = max(np.abs(r.spins - o.spins).max() for r in rs)
+            r_E = max(_rms(r.E - o.E) for r in rs)
+            print(f"sweep {t + 1} group {k} (L={g.L}): GPU-oracle rms {_rms(d):.2e} max "
+                  f"{d.max():.2e} E-rms {_rms(Eg - o.E):.2e} | references rms {r_rms:.2e} "
+                  f"max {r_max:.2e} E-rms {r_E:.2e}", flush=True)
+            if r_rms < 1e-3:
+                if spin_tol is not None and r_max < 0.1 * spin_tol:
+                    assert d.max() < spin_tol, (t, k, d.max())
+                assert _rms(d) <= shadow_factor * r_rms, (t, k)
+                assert d.max() <= shadow_factor * r_max, (t, k)
+                assert _rms(Eg - o.E) <= shadow_factor * r_E + 2.0 ** -22 * np.abs(o.E).max(), (t, k)
+            assert np.allclose(Eg, Emg, rtol=1e-11, atol=1e-9)
+            maps_track[k] = maps_track[k] and all(np.array_equal(r.slot_at_temp, o.slot_at_temp)
+                                                  for r in rs)
+            if maps_track[k]:
+                assert np.array_equal(_maps(lat, k), o.slot_at_temp), (t, k)
+    return lat, orcs
+
+
+def test_trajectory_tiny_10_sweeps(hsg, oracle_lib):
+    inst = inputs.make_instance("tiny")
+    lat, orcs = _trajectory(hsg, oracle_lib, inst, 10)
+    acc = lat.get_pt_accepts().cpu().numpy()
+    assert np.array_equal(acc, orcs[0].accepts.reshape(-1))
+
+
+def test_trajectory_with_field(hsg, oracle_lib):
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 40))
+    g = inputs.make_group(rng, 8, 2, 2, inputs.geometric_ladder(0.05, 0.25, 6),
+                          field=("gaussian", 0.2))
+    inst = inputs.Instance(groups=[g], seed=inputs.PHILOX_KEY_BASE + 40)
+    _trajectory(hsg, oracle_lib, inst, 10)
+
+
+def test_trajectory_uneven_groups(hsg, oracle_lib):
+    """Three lattice sizes in one handle, including L = 6 (L/2 odd: a thread's two
+    sites straddle rows) and L = 4 (the smallest lattice)."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 41))
+    groups, uid = [], 0
+    for L, D in ((4, 2), (6, 3), (10, 1)):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, 5),
+                                        sample_uid_base=uid))
+        uid += D
+    inst = inputs.Instance(groups=groups, seed=inputs.PHILOX_KEY_BASE + 41)
+    _trajectory(hsg, oracle_lib, inst, 10)
+
+
+def test_trajectory_bimodal_mix(hsg, oracle_lib):
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 42))
+    g = inputs.make_group(rng, 8, 2, 2, inputs.geometric_ladder(0.1, 0.3, 4), couplings="bimodal")
+    inst = inputs.Instance(groups=[g], seed=inputs.PHILOX_KEY_BASE + 42, n_hb=2, n_or=3,
+                           pt_every=2)
+    _trajectory(hsg, oracle_lib, inst, 10)
+
+
+def test_batched_L32_two_samples(hsg, oracle_lib):
+    """The batched workload's lattice and ladder (L = 32, 2 x 32 temperatures) for two
+    samples, checked in full for 2 sweeps; several tiles and every replica."""
+    inst = inputs.make_instance("batched", scale_samples=2)
+    _trajectory(hsg, oracle_lib, inst, 2, spin_tol=None)
+
+
+def test_batched_full_size_sampled(hsg, oracle_lib):
+    """All 64 samples in the launch configuration of the benchmark; one sweep; the
+    oracle recomputes two whole samples (every replica of each) one by one."""
+    inst = inputs.make_instance("batched")
+    g = inst.groups[0]
+    lat = _lat(hsg, inst.groups, inst.seed)
+    lat.sweep(1)
+    s = lat.get_spins().cpu().numpy().reshape(g.n_samples, g.n_copies, g.n_temps, 3, g.N)
+    maps = _maps(lat)
+    E = _energies(lat.get_energies(), lat)
+    for d in (0, 37):
+        sub = inputs.Group(L=g.L, n_samples=1, n_copies=g.n_copies, temps=g.temps,
+                           J=g.J[d:d + 1], H=None, spins0=g.spins0[d:d + 1],
+                           sample_uid_base=g.sample_uid_base + d)
+        o = oracle_lib.Oracle.from_group(sub, seed=inst.seed)
+        rs = _references(oracle_lib, sub, dict(seed=inst.seed), 2, 50 + d)
+        o.sweep(1)
+        for r in rs:
+            r.sweep(1)
+        dd = s[d:d + 1] - o.spins
+        r_rms = max(_rms(r.spins - o.spins) for r in rs)
+        r_max = max(np.abs(r.spins - o.spins).max() for r in rs)
+        r_E = max(_rms(r.E - o.E) for r in rs)
+        print(f"sample {d}: GPU-oracle rms {_rms(dd):.2e} max {np.abs(dd).max():.2e} E-rms "
+              f"{_rms(E[d:d + 1] - o.E):.2e} | references rms {r_rms:.2e} max {r_max:.2e} "
+              f"E-rms {r_E:.2e}", flush=True)
+        assert _rms(dd) <= SHADOW_FACTOR * r_rms and np.abs(dd).max() <= SHADOW_FACTOR * r_max
+        assert np.array_equal(maps[d:d + 1], o.slot_at_temp)
+        assert _rms(E[d:d + 1] - o.E) <= SHADOW_FACTOR * r_E + 2.0 ** -22 * np.abs(o.E).max()
+
+
+def test_tuning_and_batch_composition_invariance(hsg):
+    inst = inputs.make_instance("batched", scale_samples=3, L_override=12)
+    ref = None
+    for spi in (1, 5, 8, 64):
+        lat = _lat(hsg, inst.groups, inst.seed)
+        lat.set_tuning(spi)
+        lat.sweep(3)
+        s = _gpu_spins(lat)
+        if ref is None:
+            ref = s
+        assert np.array_equal(s, ref), spi
+    # sample 1 alone, as its own group with its own uid, reproduces its part of the batch
+    g = inst.groups[0]
+    sub = inputs.Group(L=g.L, n_samples=1, n_copies=g.n_copies, temps=g.temps, J=g.J[1:2],
+                       H=None, spins0=g.spins0[1:2], sample_uid_base=g.sample_uid_base + 1)
+    lat1 = _lat(hsg, [sub], inst.seed)
+    lat1.sweep(3)
+    assert np.array_equal(_gpu_spins(lat1)[0], ref[1])
+
+
+def test_checkpoint_resume_bit_identical(hsg):
+    inst = inputs.make_instance("tiny")
+    a = _lat(hsg, inst.groups, inst.seed)
+    a.sweep(6)
+    b = _lat(hsg, inst.groups, inst.seed)
+    b.sweep(3)
+    spins, maps = b.get_spins(), b.get_temp_map()
+    t, n, seed = b.get_state()
+    assert t == 3 and seed == inst.seed
+    c = _lat(hsg, inst.groups, inst.seed)
+    c.set_spins(spins)
+    c.set_temp_map(maps)
+    c.set_state(t, n)
+    c.sweep(3)
+    assert torch.equal(a.get_spins(), c.get_spins())
+    assert torch.equal(a.get_temp_map(), c.get_temp_map())
+    assert torch.equal(a.get_energies(), c.get_energies())
+    c.sync()
+
+
+def test_standalone_tempering_matches_oracle(hsg, oracle_lib):
+    inst = inputs.make_instance("tiny")
+    g = inst.groups[0]
+    lat = _lat(hsg, inst.groups, inst.seed)
+    o = oracle_lib.Oracle.from_group(g, seed=inst.seed)
+    lat.measure_energy()
+    o.E[:] = o.compute_energies()
+    for _ in range(5):
+        lat.pt_exchange()
+        o.pt_exchange()
+        assert np.array_equal(_maps(lat), o.slot_at_temp)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_trajectory_compressed_storage(hsg, oracle_lib, storage):
+    """Compressed spin storage against the oracle's emulation of the same codec
+    (components rounded to nearest even, renormalised when read)."""
+    inst = inputs.make_instance("tiny")
+    _trajectory(hsg, oracle_lib, inst, 10, storage=storage, spin_tol=None)
+
+
+# ---------------------------------------------------------------- closed forms on the GPU
+def langevin(k):
+    return 1.0 / np.tanh(k) - 1.0 / k
+
+
+def test_gpu_single_spin_in_field_with_tempering(hsg):
+    """J = 0, H = h z: every spin is independent; at rung k the energy of the
+    replica that sat there during the sweep averages -N h L(beta_k h)."""
+    L, N, h, T = 8, 512, 1.3, 6
+    temps = inputs.geometric_ladder(0.4, 3.0, T)
+    rng = np.random.default_rng(31)
+    D = 2
+    g = inputs.Group(L=L, n_samples=D, n_copies=2, temps=temps,
+                     J=np.zeros((D, 3, N), np.float32),
+                     H=np.tile(np.array([0, 0, h], np.float32)[None, :, None], (D, 1, N)),
+                     spins0=inputs.uniform_sphere(rng, (D, 2, T, N)).astype(np.float32))
+    lat = _lat(hsg, [g], 0x5EED, n_hb=1, n_or=2, pt_every=1)
+    M = 300
+    acc = np.zeros(T)
+    maps = _maps(lat)
+    for _ in range(M):
+        lat.sweep(1)
+        E = _energies(lat.get_energies(), lat)
+        for d in range(D):
+            for o in range(2):
+                acc += E[d, o, maps[d, o]]
+        maps = _maps(lat)
+    beta = 1.0 / temps
+    Lk = langevin(beta * h)
+    var_c = 1.0 - 2.0 * Lk / (beta * h) - Lk ** 2
+    n = M * D * 2
+    mean = acc / n
+    sigma = h * np.sqrt(N * var_c / n)
+    z = (mean + N * h * Lk) / sigma
+    print("z per rung:", np.round(z, 2), flush=True)
+    assert np.all(np.abs(z) < 5)
+    assert lat.get_pt_accepts().sum().item() > 0
+
+
+@pytest.mark.parametrize("beta", [1.0, 2.0])
+def test_gpu_open_chain(hsg, beta):
+    """Open 1D chains (J_x = 1 except across the periodic wrap, J_y = J_z = 0):
+    mean bond energy -L(beta) and variance per bond C / beta^2 with
+    C = 1 - beta^2 / sinh^2(beta)."""
+    L = 16
+    N = L ** 3
+    D = 4
+    x = np.arange(N) % L
+    J = np.zeros((D, 3, N), np.float32)
+    J[:, 0] = np.where(x == L - 1, 0.0, 1.0)
+    rng = np.random.default_rng(32)
+    g = inputs.Group(L=L, n_samples=D, n_copies=1, temps=np.array([1.0 / beta]), J=J, H=None,
+                     spins0=inputs.uniform_sphere(rng, (D, 1, 1, N)).astype(np.float32))
+    lat = _lat(hsg, [g], 0xC4A1 + int(beta), n_hb=1, n_or=1, pt_every=0)
+    lat.sweep(50)
+    M = 400
+    es = np.empty((M, D))
+    for m in range(M):
+        lat.sweep(1)
+        es[m] = lat.get_energies().cpu().numpy()
+    n_bonds = L * L * (L - 1)
+    e_bond = es / n_bonds
+    blocks = e_bond.reshape(20, -1).mean(axis=1)  # 20 blocks of 20 sweeps x D samples
+    err = blocks.std(ddof=1) / np.sqrt(len(blocks))
+    z = (e_bond.mean() + langevin(beta)) / err
+    C = 1.0 - beta ** 2 / np.sinh(beta) ** 2
+    ratio = es.var(axis=0, ddof=1).mean() / (n_bonds * C / beta ** 2)
+    print(f"beta {beta}: bond energy {e_bond.mean():.6f} vs {-langevin(beta):.6f} (z {z:.2f}); "
+          f"variance ratio {ratio:.3f}", flush=True)
+    assert abs(z) < 5
+    assert 0.85 < ratio < 1.15
+
+
+def test_gpu_over_relaxation_energy_drift(hsg):
+    """Over-relaxation conserves the energy; in float32 the energy may only
+    random-walk (no linear trend) over 10^4 OR half-sweep pairs."""
+    inst = inputs.make_instance("tiny")
+    g = inst.groups[0]
+    lat = _lat(hsg, inst.groups, inst.seed)
+    lat.sweep(50)
+    E0 = _energies(lat.measure_energy(), lat)
+    n_pairs, every = 10000, 250
+    ts, Es = [], []
+    for k in range(n_pairs // every):
+        for _ in range(every):
+            lat.half_sweep(1, 0)
+            lat.half_sweep(1, 1)
+        ts.append((k + 1) * every)
+        Es.append(_energies(lat.measure_energy(), lat) - E0)
+    ts = np.array(ts, float)
+    dE = np.array(Es).reshape(len(ts), -1) / g.N  # per site, every replica
+    slope = np.polyfit(ts, dE, 1)[0]              # per site per OR pair, per replica
+    print(f"max |dE|/N over 1e4 OR pairs {np.abs(dE).max():.2e}; max |slope| {np.abs(slope).max():.2e}"
+          f" mean slope {slope.mean():.2e}", flush=True)
+    assert np.abs(dE).max() < 2e-5
+    assert abs(slope.mean()) < 1e-10
+
+
+def test_gpu_long_run_statistics_vs_oracle(hsg, oracle_lib):
+    """Long runs of the GPU and the oracle from the same start (eight disorder
+    samples of the tiny workload's lattice and ladder, 500 sweeps): per-rung mean
+    energy and overlap q^2 over sweeps 100..500 agree. Errors from 10 time blocks
+    per sample and run, summed over samples. The 16 per-rung z-scores must lie
+    within 3.5 sigma (a 3-sigma family-wise level for 8 rungs per observable) and
+    the rung-averaged z-score of each observable within 3 sigma."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 50))
+    g = inputs.make_group(rng, 8, 8, 2, inputs.geometric_ladder(0.10, 0.30, 8))
+    seed = inputs.PHILOX_KEY_BASE + 50
+    lat = _lat(hsg, [g], seed)
+    o = oracle_lib.Oracle.from_group(g, seed=seed)
+    S, burn = 500, 100
+    D, T = g.n_samples, g.n_temps
+    Eg, Eo = np.zeros((S, D, T)), np.zeros((S, D, T))
+    Qg, Qo = np.zeros((S, D, T)), np.zeros((S, D, T))
+    for t in range(S):
+        lat.sweep(1)
+        o.sweep(1)
+        E = _energies(lat.get_energies(), lat)
+        m = _maps(lat)
+        Eg[t] = np.take_along_axis(E[:, 0], m[:, 0], axis=1)  # copy 0, by rung
+        Eo[t] = np.take_along_axis(o.E[:, 0], o.slot_at_temp[:, 0], axis=1)
+        Qg[t] = lat.measure_overlap().cpu().numpy().reshape(D, T, 10)[:, :, 9]
+        Qo[t] = o.measure_overlap()[:, :, 9]
+    for name, A, B in (("E", Eg, Eo), ("q2", Qg, Qo)):
+        a, b = A[burn:], B[burn:]
+        nb = 10
+        ab = a.reshape(nb, -1, D, T).mean(axis=1)
+        bb = b.reshape(nb, -1, D, T).mean(axis=1)
+        var = ab.var(axis=0, ddof=1) / nb + bb.var(axis=0, ddof=1) / nb  # [D, T]
+        diff = a.mean(axis=0) - b.mean(axis=0)                            # [D, T]
+        z = diff.sum(axis=0) / np.sqrt(var.sum(axis=0))                   # per rung
+        z_all = diff.sum() / np.sqrt(var.sum())
+        print(f"{name}: z per rung {np.round(z, 2)}, all rungs {z_all:.2f}", flush=True)
+        assert np.all(np.abs(z) < 3.5), (name, z)
+        assert abs(z_all) < 3.0, (name, z_all)

@@ -2,7 +2,8 @@
 
 * Philox4x32-10 against rocRAND's independent implementation (host build).
 * The uniform maps against their exact definitions on the integer grid.
-* The Duff et al. frame: orthonormality and handedness.
+* The Frisvad frame: orthonormality, handedness, continuity across the equator
+  and accuracy next to its one singular point.
 * The heat-bath draw of Eq. (2) against the von Mises-Fisher closed forms
   (Langevin function, second moments) and a KS test of the CDF.
 * The over-relaxation reflection of Eq. (3): invariants.
@@ -82,6 +83,9 @@ def test_frame_orthonormal_right_handed(oracle_lib):
     rng = np.random.default_rng(3)
     ns = [np.array(v, dtype=float) for v in ((0, 0, 1), (0, 0, -1), (1, 0, 0), (0, 1, 0),
                                               (1, 0, -0.0), (0.6, 0.8, 0.0))]
+    for eps in (1e-3, 1e-6, 1e-9):  # next to the singular point n = -z
+        v = np.array([eps, -0.5 * eps, -1.0])
+        ns.append(v / np.linalg.norm(v))
     v = rng.standard_normal((200, 3))
     ns += list(v / np.linalg.norm(v, axis=1, keepdims=True))
     for n in ns:
@@ -89,6 +93,24 @@ def test_frame_orthonormal_right_handed(oracle_lib):
         M = np.stack([e1, e2, n])
         assert np.abs(M @ M.T - np.eye(3)).max() < 1e-14
         assert np.abs(np.cross(e1, e2) - n).max() < 1e-14
+
+
+def test_frame_continuous_away_from_south_pole(oracle_lib):
+    """A small change of n moves the frame by a comparable amount everywhere
+    except at n = -z, in particular across the equator n_z = 0."""
+    rng = np.random.default_rng(4)
+    for _ in range(2000):
+        n = rng.standard_normal(3)
+        if rng.random() < 0.5:
+            n[2] = rng.uniform(-1e-7, 1e-7)  # straddle the equator
+        n /= np.linalg.norm(n)
+        if n[2] < -0.999:
+            continue
+        m = n + 1e-9 * rng.standard_normal(3)
+        m /= np.linalg.norm(m)
+        a1, a2 = oracle_lib.frame(n)
+        b1, b2 = oracle_lib.frame(m)
+        assert np.abs(a1 - b1).max() < 1e-6 and np.abs(a2 - b2).max() < 1e-6
 
 
 # ------------------------------------------------------------------ heat bath
