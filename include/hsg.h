@@ -177,6 +177,11 @@ hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_cal
  * (1..R_O R_T, 0 = automatic). */
 hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
 
+/* Tuning (results do not depend on it): 0 = automatic; 1 = the gather kernel
+ * (any even L); 2 = the z-march kernel (used automatically when L % 4 == 0;
+ * other lattice sizes keep the gather kernel). */
+hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
+
 /* Wait for `stream` and report any device error. */
 hsg_status hsg_sync(hsg_lattice *h, hsg_stream_t stream);
 

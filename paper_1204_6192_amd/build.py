@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsg.so")
-SOURCES = ["api.hip", "kernels.hip"]
+SOURCES = ["api.hip", "kernels.hip", "sweep_stream.hip"]
 ARCH = os.environ.get("HSG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -61,7 +61,36 @@ struct Group {
     uint64_t o_scr;                              // scratch
     int32_t n_pb_sweep;                          // blocks of 256 site pairs per replica
     int32_t n_pb_site;                           // blocks of 256 sites per replica half
+    // z-march geometry (L divisible by 4), see hsg::StreamArgs
+    bool stream_ok;
+    int32_t s_TY, s_RB, s_rows, s_ytiles;
 };
+
+// Work-group shape of the z-march for lattice size L (L % 4 == 0): the whole
+// plane in LDS when L * L / 4 <= 256 threads (several replicas per group for
+// small L), otherwise the tallest row band that fits, with two halo rows.
+void stream_geometry(Group &g)
+{
+    g.stream_ok = (g.L % 4) == 0;
+    if (!g.stream_ok) return;
+    const int P = g.L / 4;
+    if (P * g.L <= hsg::kBlock) {
+        g.s_TY = g.L;
+        g.s_rows = g.L;
+    } else {
+        int ty = 0;
+        for (int c = 2; c <= g.L; ++c)
+            if (g.L % c == 0 && P * c <= hsg::kBlock) ty = c;
+        if (ty < 2) {
+            g.stream_ok = false;
+            return;
+        }
+        g.s_TY = ty;
+        g.s_rows = ty + 2;
+    }
+    g.s_RB = hsg::kBlock / (P * g.s_TY);
+    g.s_ytiles = g.L / g.s_TY;
+}
 
 struct Layout {
     std::vector<Group> g;
@@ -126,6 +155,7 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         const int64_t pairs = g.Nh / 2;
         g.n_pb_sweep = (int32_t)((pairs + hsg::kBlock - 1) / hsg::kBlock);
         g.n_pb_site = (int32_t)((g.Nh + hsg::kBlock - 1) / hsg::kBlock);
+        stream_geometry(g);
         // state
         g.o_spins = st;
         st = align_up(st + (uint64_t)g.n_rep * 6 * g.Nh * bytes_per_component(desc->storage));
@@ -149,7 +179,7 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         if (g.field) fd = align_up(fd + (uint64_t)g.D * 2 * 3 * g.Nh * 4);
         // scratch: the largest of the three reductions of this group
         g.o_scr = sc;
-        const uint64_t e_sweep = (uint64_t)g.n_rep * g.n_pb_sweep * 8;
+        const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > g.s_ytiles ? g.n_pb_sweep : g.s_ytiles) * 8;
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.n_pb_site * 9 * 8;
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
@@ -178,6 +208,7 @@ struct hsg_lattice {
     uint64_t t = 0, pt_calls = 0;
     char *state = nullptr, *coup = nullptr, *field = nullptr, *scratch = nullptr;
     int32_t slots_per_item = 0;
+    int32_t kernel_variant = 0;  // 0 automatic, 1 gather kernel, 2 z-march
     bool have_energies = false;
 };
 
@@ -219,17 +250,62 @@ hsg::SweepArgs sweep_args(const hsg_lattice *h, const Group &g, int parity, uint
     return a;
 }
 
+bool use_stream(const hsg_lattice *h, const Group &g)
+{
+    if (h->kernel_variant == 1) return false;
+    return g.stream_ok;
+}
+
+hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep)
+{
+    hsg::StreamArgs a{};
+    a.spins = h->state + g.o_spins;
+    a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+    a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+    a.temp_of_slot = reinterpret_cast<const int32_t *>(h->state + g.o_tos);
+    a.beta32 = reinterpret_cast<const float *>(h->coup + g.o_b32);
+    a.e_partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+    a.Nh = g.Nh;
+    a.n_rep = g.n_rep;
+    a.L = g.L;
+    a.Lh = g.L / 2;
+    a.P = g.L / 4;
+    a.TY = g.s_TY;
+    a.RB = g.s_RB;
+    a.rows = g.s_rows;
+    a.n_ytiles = g.s_ytiles;
+    a.n_blocks = (int32_t)((g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles);
+    a.slots_per_sample = g.O * g.T;
+    a.T = g.T;
+    a.t = (uint32_t)(h->t & 0xFFFFFFFFu);
+    a.rep = rep;
+    a.parity = (uint32_t)parity;
+    a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+    a.key1 = (uint32_t)(h->seed >> 32);
+    a.uid_base = g.uid_base;
+    return a;
+}
+
 hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool energy, hipStream_t s)
 {
     for (const Group &g : h->lay.g) {
-        const hsg::SweepArgs a = sweep_args(h, g, parity, (uint32_t)rep);
-        if ((int64_t)g.D * a.n_chunks * a.n_pb > 0x7FFFFFFFll)
-            return fail(HSG_E_SIZE, "grid too large");
-        hipError_t e = hsg::launch_half_sweep(a, h->storage, kind, g.field, energy, s);
+        double *partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+        int n_pb = 0;
+        hipError_t e;
+        if (use_stream(h, g)) {
+            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep);
+            if ((g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
+            e = hsg::launch_half_sweep_stream(a, h->storage, kind, g.field, energy, s);
+            n_pb = a.n_ytiles;
+        } else {
+            const hsg::SweepArgs a = sweep_args(h, g, parity, (uint32_t)rep);
+            if ((int64_t)g.D * a.n_chunks * a.n_pb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
+            e = hsg::launch_half_sweep(a, h->storage, kind, g.field, energy, s);
+            n_pb = a.n_pb;
+        }
         if (e != hipSuccess) return hip_fail(e, "half-sweep launch");
         if (energy) {
-            e = hsg::launch_reduce_partials(a.e_partials, a.n_pb, g.n_rep,
-                                            reinterpret_cast<double *>(h->state + g.o_E), s);
+            e = hsg::launch_reduce_partials(partials, n_pb, g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
             if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
         }
     }
@@ -565,6 +641,14 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item)
     if (slots_per_item < 0 || slots_per_item > 16 * 256)
         return fail(HSG_E_INVALID, "slots_per_item = %d", slots_per_item);
     h->slots_per_item = slots_per_item;
+    return HSG_OK;
+}
+
+hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (variant < 0 || variant > 2) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..2", variant);
+    h->kernel_variant = variant;
     return HSG_OK;
 }
 

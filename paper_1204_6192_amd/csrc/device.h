@@ -183,6 +183,22 @@ struct Codec<0> {  // float32: stored renormalised, read as is
         p[2 * cs + j] = s.z;
     }
     __device__ static __forceinline__ v3 stored_value(v3 s) { return s; }
+    // Two neighbouring sites j0, j0 + 1 (j0 even, 8-byte aligned): one 8-byte
+    // access per component plane.
+    __device__ static __forceinline__ void load_pair(const T *p, int64_t cs, int64_t j0, v3 &a, v3 &b)
+    {
+        const float2 x = *reinterpret_cast<const float2 *>(p + j0);
+        const float2 y = *reinterpret_cast<const float2 *>(p + cs + j0);
+        const float2 z = *reinterpret_cast<const float2 *>(p + 2 * cs + j0);
+        a = v3{x.x, y.x, z.x};
+        b = v3{x.y, y.y, z.y};
+    }
+    __device__ static __forceinline__ void store_pair(T *p, int64_t cs, int64_t j0, v3 a, v3 b)
+    {
+        *reinterpret_cast<float2 *>(p + j0) = make_float2(a.x, b.x);
+        *reinterpret_cast<float2 *>(p + cs + j0) = make_float2(a.y, b.y);
+        *reinterpret_cast<float2 *>(p + 2 * cs + j0) = make_float2(a.z, b.z);
+    }
 };
 
 template <>
@@ -202,6 +218,20 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
     {
         return normalise3(v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
                              __half2float(__float2half_rn(s.z))});
+    }
+    __device__ static __forceinline__ void load_pair(const T *p, int64_t cs, int64_t j0, v3 &a, v3 &b)
+    {
+        const __half2 x = *reinterpret_cast<const __half2 *>(p + j0);
+        const __half2 y = *reinterpret_cast<const __half2 *>(p + cs + j0);
+        const __half2 z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
+        a = normalise3(v3{__low2float(x), __low2float(y), __low2float(z)});
+        b = normalise3(v3{__high2float(x), __high2float(y), __high2float(z)});
+    }
+    __device__ static __forceinline__ void store_pair(T *p, int64_t cs, int64_t j0, v3 a, v3 b)
+    {
+        *reinterpret_cast<__half2 *>(p + j0) = __halves2half2(__float2half_rn(a.x), __float2half_rn(b.x));
+        *reinterpret_cast<__half2 *>(p + cs + j0) = __halves2half2(__float2half_rn(a.y), __float2half_rn(b.y));
+        *reinterpret_cast<__half2 *>(p + 2 * cs + j0) = __halves2half2(__float2half_rn(a.z), __float2half_rn(b.z));
     }
 };
 
@@ -230,6 +260,21 @@ struct Codec<2> {
     {
         return normalise3(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
                              bf16_to_f32(f32_to_bf16_rne(s.z))});
+    }
+    __device__ static __forceinline__ void load_pair(const T *p, int64_t cs, int64_t j0, v3 &a, v3 &b)
+    {
+        const uint32_t x = *reinterpret_cast<const uint32_t *>(p + j0);
+        const uint32_t y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
+        const uint32_t z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
+        a = normalise3(v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)});
+        b = normalise3(v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u),
+                          __uint_as_float(z & 0xFFFF0000u)});
+    }
+    __device__ static __forceinline__ void store_pair(T *p, int64_t cs, int64_t j0, v3 a, v3 b)
+    {
+        *reinterpret_cast<uint32_t *>(p + j0) = (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(b.x) << 16);
+        *reinterpret_cast<uint32_t *>(p + cs + j0) = (uint32_t)f32_to_bf16_rne(a.y) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
+        *reinterpret_cast<uint32_t *>(p + 2 * cs + j0) = (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(b.z) << 16);
     }
 };
 

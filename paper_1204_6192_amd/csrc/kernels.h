@@ -35,6 +35,25 @@ struct SweepArgs {
 hipError_t launch_half_sweep(const SweepArgs &a, int storage, int kind, bool field, bool energy,
                              hipStream_t s);
 
+// z-march variant (L divisible by 4): a work-group owns RB replicas x TY rows
+// and walks z; P = L / 4 site pairs per row; rows = TY (whole plane in LDS) or
+// TY + 2 (with halo rows). Energy partials are [replica][n_ytiles].
+struct StreamArgs {
+    void *spins;
+    const float *J6;
+    const float *Hp;
+    const int32_t *temp_of_slot;
+    const float *beta32;
+    double *e_partials;
+    int64_t Nh, n_rep;
+    int32_t L, Lh, P, TY, RB, rows, n_ytiles, n_blocks;
+    int32_t slots_per_sample, T;
+    uint32_t t, rep, parity;
+    uint32_t key0, key1, uid_base;
+};
+hipError_t launch_half_sweep_stream(const StreamArgs &a, int storage, int kind, bool field, bool energy,
+                                    hipStream_t s);
+
 // E[r] = sum over the n_pb partials of replica r, for n_rep replicas.
 hipError_t launch_reduce_partials(const double *partials, int n_pb, int64_t n_rep, double *E,
                                   hipStream_t s);

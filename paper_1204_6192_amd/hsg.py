@@ -88,6 +88,7 @@ _SIG = {
     "hsg_get_state": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
     "hsg_set_state": [_vp, _u64, _u64],
     "hsg_set_tuning": [_vp, _i32],
+    "hsg_set_kernel": [_vp, _i32],
     "hsg_sync": [_vp, _vp],
     "hsg_debug_philox": [_vp, _vp, _vp, _i64, _vp],
 }
@@ -246,6 +247,9 @@ class Lattice:
 
     def set_tuning(self, slots_per_item: int) -> None:
         check(lib.hsg_set_tuning(self.h, int(slots_per_item)))
+
+    def set_kernel(self, variant: int) -> None:
+        check(lib.hsg_set_kernel(self.h, int(variant)))
 
     def sync(self) -> None:
         check(lib.hsg_sync(self.h, _stream(self.stream)))
