@@ -184,8 +184,8 @@ struct Codec<0> {  // float32: stored renormalised, read as is
     }
     __device__ static __forceinline__ v3 stored_value(v3 s) { return s; }
     // Two neighbouring sites j0, j0 + 1 (j0 even, 8-byte aligned): one 8-byte
-    // access per component plane.
-    __device__ static __forceinline__ void load_pair(const T *p, int64_t cs, int64_t j0, v3 &a, v3 &b)
+    // access per component plane; 32-bit offsets (3 Nh < 2^32 for L <= 1024).
+    __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
         const float2 x = *reinterpret_cast<const float2 *>(p + j0);
         const float2 y = *reinterpret_cast<const float2 *>(p + cs + j0);
@@ -193,7 +193,7 @@ struct Codec<0> {  // float32: stored renormalised, read as is
         a = v3{x.x, y.x, z.x};
         b = v3{x.y, y.y, z.y};
     }
-    __device__ static __forceinline__ void store_pair(T *p, int64_t cs, int64_t j0, v3 a, v3 b)
+    __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
         *reinterpret_cast<float2 *>(p + j0) = make_float2(a.x, b.x);
         *reinterpret_cast<float2 *>(p + cs + j0) = make_float2(a.y, b.y);
@@ -219,7 +219,7 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
         return normalise3(v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
                              __half2float(__float2half_rn(s.z))});
     }
-    __device__ static __forceinline__ void load_pair(const T *p, int64_t cs, int64_t j0, v3 &a, v3 &b)
+    __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
         const __half2 x = *reinterpret_cast<const __half2 *>(p + j0);
         const __half2 y = *reinterpret_cast<const __half2 *>(p + cs + j0);
@@ -227,7 +227,7 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
         a = normalise3(v3{__low2float(x), __low2float(y), __low2float(z)});
         b = normalise3(v3{__high2float(x), __high2float(y), __high2float(z)});
     }
-    __device__ static __forceinline__ void store_pair(T *p, int64_t cs, int64_t j0, v3 a, v3 b)
+    __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
         *reinterpret_cast<__half2 *>(p + j0) = __halves2half2(__float2half_rn(a.x), __float2half_rn(b.x));
         *reinterpret_cast<__half2 *>(p + cs + j0) = __halves2half2(__float2half_rn(a.y), __float2half_rn(b.y));
@@ -261,7 +261,7 @@ struct Codec<2> {
         return normalise3(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
                              bf16_to_f32(f32_to_bf16_rne(s.z))});
     }
-    __device__ static __forceinline__ void load_pair(const T *p, int64_t cs, int64_t j0, v3 &a, v3 &b)
+    __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
         const uint32_t x = *reinterpret_cast<const uint32_t *>(p + j0);
         const uint32_t y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
@@ -270,7 +270,7 @@ struct Codec<2> {
         b = normalise3(v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u),
                           __uint_as_float(z & 0xFFFF0000u)});
     }
-    __device__ static __forceinline__ void store_pair(T *p, int64_t cs, int64_t j0, v3 a, v3 b)
+    __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
         *reinterpret_cast<uint32_t *>(p + j0) = (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(b.x) << 16);
         *reinterpret_cast<uint32_t *>(p + cs + j0) = (uint32_t)f32_to_bf16_rne(a.y) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);

@@ -19,7 +19,10 @@
 
 namespace hsg {
 
-template <int STORE, int KIND, bool FIELD, bool ENERGY>
+// UNI: every wave holds a single replica (TY * P a multiple of 64), so the
+// replica's base addresses are wave-uniform and live in scalar registers, and
+// the per-lane addressing is 32-bit.
+template <int STORE, int KIND, bool FIELD, bool ENERGY, bool UNI>
 __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
 {
     using C = Codec<STORE>;
@@ -29,45 +32,41 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
 
     const int lb = xcd_remap((int)blockIdx.x, a.n_blocks);
     const int ytile = lb % a.n_ytiles;
-    const int64_t rblk = lb / a.n_ytiles;
+    const int rblk = lb / a.n_ytiles;
     const int tid = threadIdx.x;
     const int per_rep = a.TY * a.P;
     const int rb = tid / per_rep;
     const int rem = tid - rb * per_rep;
     const int ty = rem / a.P, m = rem - ty * a.P;
-    const int64_t r = rblk * a.RB + rb;  // replica (canonical order within the group)
-    const bool active = rb < a.RB && r < a.n_rep;
+    const int64_t r_lane = (int64_t)rblk * a.RB + rb;  // replica (canonical order within the group)
+    const bool active = rb < a.RB && r_lane < a.n_rep;
     const int L = a.L, Lh = a.Lh;
-    const int64_t Nh = a.Nh;
+    const uint32_t Nh = (uint32_t)a.Nh;
     const int p = (int)a.parity;
     const bool full = a.TY == L;
     const int y = ytile * a.TY + ty;
-    const int lrow = full ? ty : ty + 1;                            // my row in the LDS plane
-    const int lrm = full ? (ty == 0 ? L - 1 : ty - 1) : ty;         // row y - 1
-    const int lrp = full ? (ty == L - 1 ? 0 : ty + 1) : ty + 2;     // row y + 1
-    const int cstride = a.rows * Lh;                                // floats per component plane
+    const int lrow = full ? ty : ty + 1;                         // my row in the LDS plane
+    const int lrm = full ? (ty == 0 ? L - 1 : ty - 1) : ty;      // row y - 1
+    const int lrp = full ? (ty == L - 1 ? 0 : ty + 1) : ty + 2;  // row y + 1
+    const int cstride = a.rows * Lh;                             // floats per component plane
     const int xh0 = 2 * m;
+    const int rbc = active ? rb : 0;
+    const int lbuf[2] = {rbc * 3 * cstride, (a.RB + rbc) * 3 * cstride};
 
-    float *buf[2];
-    buf[0] = lds + (int64_t)(active ? rb : 0) * 3 * cstride;
-    buf[1] = lds + (int64_t)(a.RB + (active ? rb : 0)) * 3 * cstride;
-
-    T *own = nullptr;
-    const T *oth = nullptr;
-    const float *Jb = nullptr, *Hb = nullptr, *Ho = nullptr;
+    int64_t r = r_lane;
+    if (UNI) r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r_lane >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r_lane & 0xFFFFFFFF));
+    const int64_t d = r / a.slots_per_sample;
+    const int sis = (int)(r - d * a.slots_per_sample);
+    T *base = (T *)a.spins + r * 6 * (int64_t)Nh;
+    T *own = base + (int64_t)p * 3 * Nh;
+    const T *oth = base + (int64_t)(1 - p) * 3 * Nh;
+    const float *Jb = a.J6 + (d * 2 + p) * 6 * (int64_t)Nh;
+    const float *Hb = FIELD ? a.Hp + (d * 2 + p) * 3 * (int64_t)Nh : nullptr;
+    const float *Ho = FIELD ? a.Hp + (d * 2 + (1 - p)) * 3 * (int64_t)Nh : nullptr;
     float beta = 0.0f;
     uint32_t c2 = 0, uid = 0;
     if (active) {
-        const int64_t d = r / a.slots_per_sample;
-        const int sis = (int)(r - d * a.slots_per_sample);
-        T *base = (T *)a.spins + r * 6 * Nh;
-        own = base + (int64_t)p * 3 * Nh;
-        oth = base + (int64_t)(1 - p) * 3 * Nh;
-        Jb = a.J6 + (d * 2 + p) * 6 * Nh;
-        if (FIELD) {
-            Hb = a.Hp + (d * 2 + p) * 3 * Nh;
-            Ho = a.Hp + (d * 2 + (1 - p)) * 3 * Nh;
-        }
         beta = a.beta32[a.temp_of_slot[r]];
         const int o = sis / a.T, ts = sis - o * a.T;
         c2 = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12) | ((uint32_t)p << 16);
@@ -77,48 +76,23 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
     // rolling planes of the other parity at my two positions
     v3 prv0{}, prv1{}, cur0{}, cur1{}, nxt0{}, nxt1{};
     if (active) {
-        C::load_pair(oth, Nh, ((int64_t)(L - 1) * L + y) * Lh + xh0, prv0, prv1);
-        C::load_pair(oth, Nh, ((int64_t)0 * L + y) * Lh + xh0, cur0, cur1);
+        C::load_pair(oth, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), prv0, prv1);
+        C::load_pair(oth, Nh, (uint32_t)(y * Lh + xh0), cur0, cur1);
     }
     double e = 0.0;
 
     for (int z = 0; z < L; ++z) {
-        float *bf = buf[z & 1];
+        const int lo = lbuf[z & 1];
         const int zn = (z + 1 == L) ? 0 : z + 1;
-        const int64_t j0 = ((int64_t)z * L + y) * Lh + xh0;  // my first site, half-index
+        const uint32_t j0 = (uint32_t)((z * L + y) * Lh + xh0);  // my first site, half-index
+        float2 jc[6];
+        v3 hs0{0.f, 0.f, 0.f}, hs1{0.f, 0.f, 0.f}, old0{}, old1{};
+        u32x4 rr{0u, 0u, 0u, 0u};
         if (active) {
-            C::load_pair(oth, Nh, ((int64_t)zn * L + y) * Lh + xh0, nxt0, nxt1);
-            float2 *row = reinterpret_cast<float2 *>(bf + lrow * Lh + xh0);
-            row[0] = make_float2(cur0.x, cur1.x);
-            row[cstride / 2] = make_float2(cur0.y, cur1.y);
-            row[cstride] = make_float2(cur0.z, cur1.z);
-            if (!full && (ty == 0 || ty == a.TY - 1)) {  // halo rows y0 - 1 and y0 + TY
-                const int hy = (ty == 0) ? (y == 0 ? L - 1 : y - 1) : (y + 1 == L ? 0 : y + 1);
-                const int hrow = (ty == 0) ? 0 : a.TY + 1;
-                v3 h0, h1;
-                C::load_pair(oth, Nh, ((int64_t)z * L + hy) * Lh + xh0, h0, h1);
-                float2 *hr = reinterpret_cast<float2 *>(bf + hrow * Lh + xh0);
-                hr[0] = make_float2(h0.x, h1.x);
-                hr[cstride / 2] = make_float2(h0.y, h1.y);
-                hr[cstride] = make_float2(h0.z, h1.z);
-            }
-        }
-        __syncthreads();
-        if (active) {
-            const int o = (y + z + p) & 1;  // x = 2 x/2 + o on this row
-            // the x-neighbour that is not one of my own two positions
-            const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
-            const v3 ex{bf[lrow * Lh + xe], bf[cstride + lrow * Lh + xe], bf[2 * cstride + lrow * Lh + xe]};
-            const float2 ym0 = *reinterpret_cast<const float2 *>(bf + lrm * Lh + xh0);
-            const float2 ym1 = *reinterpret_cast<const float2 *>(bf + cstride + lrm * Lh + xh0);
-            const float2 ym2 = *reinterpret_cast<const float2 *>(bf + 2 * cstride + lrm * Lh + xh0);
-            const float2 yp0 = *reinterpret_cast<const float2 *>(bf + lrp * Lh + xh0);
-            const float2 yp1 = *reinterpret_cast<const float2 *>(bf + cstride + lrp * Lh + xh0);
-            const float2 yp2 = *reinterpret_cast<const float2 *>(bf + 2 * cstride + lrp * Lh + xh0);
-            float2 jc[6];
+            // every global access of this step is issued before the barrier
+            C::load_pair(oth, Nh, (uint32_t)((zn * L + y) * Lh + xh0), nxt0, nxt1);
 #pragma unroll
             for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
-            v3 hs0{0.f, 0.f, 0.f}, hs1{0.f, 0.f, 0.f};
             if (FIELD) {
                 const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
                 const float2 hy = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
@@ -126,10 +100,37 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
                 hs0 = v3{hx.x, hy.x, hz.x};
                 hs1 = v3{hx.y, hy.y, hz.y};
             }
-            v3 old0{}, old1{};
             if (KIND == 1) C::load_pair(own, Nh, j0, old0, old1);
-            u32x4 rr{0u, 0u, 0u, 0u};
-            if (KIND == 0) rr = philox4x32_10(u32x4{(uint32_t)(j0 >> 1), a.t, c2, uid}, a.key0, a.key1);
+            // stage plane z (my two positions) in LDS
+            const int w = lo + lrow * Lh + xh0;
+            *reinterpret_cast<float2 *>(&lds[w]) = make_float2(cur0.x, cur1.x);
+            *reinterpret_cast<float2 *>(&lds[w + cstride]) = make_float2(cur0.y, cur1.y);
+            *reinterpret_cast<float2 *>(&lds[w + 2 * cstride]) = make_float2(cur0.z, cur1.z);
+            if (!full && (ty == 0 || ty == a.TY - 1)) {  // halo rows y0 - 1 and y0 + TY
+                const int hy = (ty == 0) ? (y == 0 ? L - 1 : y - 1) : (y + 1 == L ? 0 : y + 1);
+                const int hw = lo + ((ty == 0) ? 0 : a.TY + 1) * Lh + xh0;
+                v3 g0, g1;
+                C::load_pair(oth, Nh, (uint32_t)((z * L + hy) * Lh + xh0), g0, g1);
+                *reinterpret_cast<float2 *>(&lds[hw]) = make_float2(g0.x, g1.x);
+                *reinterpret_cast<float2 *>(&lds[hw + cstride]) = make_float2(g0.y, g1.y);
+                *reinterpret_cast<float2 *>(&lds[hw + 2 * cstride]) = make_float2(g0.z, g1.z);
+            }
+            if (KIND == 0) rr = philox4x32_10(u32x4{j0 >> 1, a.t, c2, uid}, a.key0, a.key1);
+        }
+        __syncthreads();
+        if (active) {
+            const int o = (y + z + p) & 1;  // x = 2 x/2 + o on this row
+            // the x-neighbour that is not one of my own two positions
+            const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
+            const int we = lo + lrow * Lh + xe;
+            const v3 ex{lds[we], lds[we + cstride], lds[we + 2 * cstride]};
+            const int wm = lo + lrm * Lh + xh0, wp = lo + lrp * Lh + xh0;
+            const float2 ym0 = *reinterpret_cast<const float2 *>(&lds[wm]);
+            const float2 ym1 = *reinterpret_cast<const float2 *>(&lds[wm + cstride]);
+            const float2 ym2 = *reinterpret_cast<const float2 *>(&lds[wm + 2 * cstride]);
+            const float2 yp0 = *reinterpret_cast<const float2 *>(&lds[wp]);
+            const float2 yp1 = *reinterpret_cast<const float2 *>(&lds[wp + cstride]);
+            const float2 yp2 = *reinterpret_cast<const float2 *>(&lds[wp + 2 * cstride]);
             // neighbours in the order +x, -x, +y, -y, +z, -z
             v3 nb0[6], nb1[6];
             if (o) {  // site k at x = 2(xh0 + k) + 1: +x -> xh0 + k + 1, -x -> xh0 + k
@@ -191,11 +192,11 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
         red[tid] = e;
         __syncthreads();
         if (tid < a.RB) {
-            const int64_t rr2 = rblk * a.RB + tid;
-            if (rr2 < a.n_rep) {
+            const int64_t r2 = (int64_t)rblk * a.RB + tid;
+            if (r2 < a.n_rep) {
                 double s = 0.0;
                 for (int k = 0; k < per_rep; ++k) s += red[tid * per_rep + k];
-                a.e_partials[rr2 * a.n_ytiles + ytile] = s;
+                a.e_partials[r2 * a.n_ytiles + ytile] = s;
             }
         }
     }
@@ -205,8 +206,13 @@ template <int STORE>
 static hipError_t launch_stream_s(const StreamArgs &a, int kind, bool field, bool energy, unsigned threads,
                                   size_t lds_bytes, hipStream_t s)
 {
+    const bool uni = (a.TY * a.P) % 64 == 0;
     const dim3 grid((unsigned)a.n_blocks), block(threads);
-#define HSG_L(K, F, E) hipLaunchKernelGGL((k_half_sweep_stream<STORE, K, F, E>), grid, block, lds_bytes, s, a)
+#define HSG_L(K, F, E)                                                                                      \
+    do {                                                                                                    \
+        if (uni) hipLaunchKernelGGL((k_half_sweep_stream<STORE, K, F, E, true>), grid, block, lds_bytes, s, a); \
+        else hipLaunchKernelGGL((k_half_sweep_stream<STORE, K, F, E, false>), grid, block, lds_bytes, s, a);   \
+    } while (0)
     if (kind == 0) {
         if (field) { if (energy) HSG_L(0, true, true); else HSG_L(0, true, false); }
         else { if (energy) HSG_L(0, false, true); else HSG_L(0, false, false); }
