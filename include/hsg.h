@@ -168,10 +168,12 @@ hsg_status hsg_set_temp_map(hsg_lattice *h, const int32_t *d_slot_at_temp, hsg_s
  * for k = 0..n_temps-2 (device). */
 hsg_status hsg_get_pt_accepts(const hsg_lattice *h, uint64_t *d_accepts, hsg_stream_t stream);
 
-/* Generator position for checkpoint / resume (host values). */
+/* Generator position for checkpoint / resume. get_ returns host values; set_
+ * also writes the device copy of the sweep counter, ordered on `stream`. */
 hsg_status hsg_get_state(const hsg_lattice *h, uint64_t *sweep_counter, uint64_t *pt_calls,
                          uint64_t *seed);
-hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls);
+hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls,
+                         hsg_stream_t stream);
 
 /* Tuning (results do not depend on it): slots processed per work item
  * (1..R_O R_T, 0 = automatic). */
@@ -182,6 +184,10 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
  * other lattice sizes keep the gather kernel). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
+/* Replay whole sweeps as captured HIP graphs (default on; used when tempering
+ * runs every sweep or never). Results do not depend on it. */
+hsg_status hsg_set_graphs(hsg_lattice *h, int32_t enable);
+
 /* Wait for `stream` and report any device error. */
 hsg_status hsg_sync(hsg_lattice *h, hsg_stream_t stream);
 
@@ -190,6 +196,10 @@ void hsg_destroy(hsg_lattice *h);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *hsg_last_error(void);
+
+/* Identity of the sources this library was built from (a hash): measurements
+ * taken with hardware counters are valid for one build id only. */
+const char *hsg_build_id(void);
 
 /* Test hook: n Philox4x32-10 blocks, d_ctr [n][4], d_key [n][2] -> d_out [n][4]
  * (device arrays). Exposes the device generator for a bit-exact comparison. */

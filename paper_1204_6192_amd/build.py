@@ -4,6 +4,7 @@ Flags: -O3; no FMA contraction (every fused multiply-add in the kernels is
 written explicitly); packed-FP32 instructions disabled; position independent.
 """
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -22,12 +23,29 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def source_id() -> str:
+    """Hash of the kernel and host sources (and the build flags) of libhsg.so."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(HERE, "..", "include", "hsg.h"), "rb") as f:
+        h.update(f.read())
+    h.update(" ".join(FLAGS).encode())
+    return h.hexdigest()[:16]
+
+
+FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Xclang", "-target-feature",
+         "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include"),
-           "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    cmd = [hipcc(), f"--offload-arch={ARCH}"] + FLAGS + [
+        f'-DHSG_BUILD_ID="{source_id()}"', "-I", os.path.join(HERE, "..", "include"),
+        "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

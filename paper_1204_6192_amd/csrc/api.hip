@@ -113,7 +113,8 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
     if (desc->n_hb + desc->n_or < 1) return fail(HSG_E_INVALID, "a sweep needs n_hb + n_or >= 1");
     if (desc->pt_every < 0) return fail(HSG_E_INVALID, "pt_every = %d < 0", desc->pt_every);
     lay.g.clear();
-    uint64_t st = 0, cp = 0, fd = 0, sc = 0;
+    // the state buffer starts with a control block: the device sweep counter
+    uint64_t st = kAlign, cp = 0, fd = 0, sc = 0;
     int64_t rep0 = 0, spins = 0, sites = 0;
     for (int gi = 0; gi < desc->n_groups; ++gi) {
         const hsg_group_desc &gd = desc->groups[gi];
@@ -210,11 +211,30 @@ struct hsg_lattice {
     int32_t slots_per_item = 0;
     int32_t kernel_variant = 0;  // 0 automatic, 1 gather kernel, 2 z-march
     bool have_energies = false;
+    // hipGraph replay of whole sweeps (tempering every sweep or never)
+    bool use_graphs = true;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};         // 1 sweep, kGraphSweeps sweeps
+    hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
 };
 
 namespace {
 
+constexpr int kGraphSweeps = 8;
+
 hipStream_t S(hsg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+uint32_t *dev_counter(const hsg_lattice *h) { return reinterpret_cast<uint32_t *>(h->state); }
+
+void drop_graphs(hsg_lattice *h)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (h->graph_exec[k]) (void)hipGraphExecDestroy(h->graph_exec[k]);
+        if (h->graph[k]) (void)hipGraphDestroy(h->graph[k]);
+        h->graph_exec[k] = nullptr;
+        h->graph[k] = nullptr;
+    }
+}
 
 int chunk_for(const hsg_lattice *h, const Group &g)
 {
@@ -241,7 +261,7 @@ hsg::SweepArgs sweep_args(const hsg_lattice *h, const Group &g, int parity, uint
     a.n_chunks = (a.slots_per_sample + a.chunk - 1) / a.chunk;
     a.n_pb = g.n_pb_sweep;
     a.n_blocks = g.D * a.n_chunks * a.n_pb;
-    a.t = (uint32_t)(h->t & 0xFFFFFFFFu);
+    a.tptr = dev_counter(h);
     a.rep = rep;
     a.parity = (uint32_t)parity;
     a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
@@ -277,7 +297,7 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     a.n_blocks = (int32_t)((g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles);
     a.slots_per_sample = g.O * g.T;
     a.T = g.T;
-    a.t = (uint32_t)(h->t & 0xFFFFFFFFu);
+    a.tptr = dev_counter(h);
     a.rep = rep;
     a.parity = (uint32_t)parity;
     a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
@@ -312,6 +332,7 @@ hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool en
     return HSG_OK;
 }
 
+// purpose 1: in-sweep pass, counter read from the device; 2: standalone pass.
 hsg_status run_pt(hsg_lattice *h, uint32_t ctr1, uint32_t purpose, hipStream_t s)
 {
     for (const Group &g : h->lay.g) {
@@ -324,6 +345,7 @@ hsg_status run_pt(hsg_lattice *h, uint32_t ctr1, uint32_t purpose, hipStream_t s
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
+        a.tptr = purpose == 1 ? dev_counter(h) : nullptr;
         a.ctr1 = ctr1;
         a.purpose = purpose;
         a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
@@ -349,11 +371,78 @@ hsg::PackArgs pack_args(const hsg_lattice *h, const Group &g)
 
 bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign - 1)) == 0; }
 
+// All launches of one sweep, kernels only (capturable): heat-bath pairs,
+// over-relaxation pairs with the energy fused into the last pass, tempering,
+// then the device sweep counter advances.
+hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
+{
+    const int last_kind = h->n_or > 0 ? 1 : 0;
+    for (int r = 0; r < h->n_hb; ++r)
+        for (int p = 0; p < 2; ++p) {
+            const bool energy = (last_kind == 0) && r == h->n_hb - 1 && p == 1;
+            hsg_status st = run_half_sweep(h, 0, p, r, energy, s);
+            if (st != HSG_OK) return st;
+        }
+    for (int r = 0; r < h->n_or; ++r)
+        for (int p = 0; p < 2; ++p) {
+            const bool energy = r == h->n_or - 1 && p == 1;
+            hsg_status st = run_half_sweep(h, 1, p, 0, energy, s);
+            if (st != HSG_OK) return st;
+        }
+    if (pt) {
+        hsg_status st = run_pt(h, 0u, 1u, s);
+        if (st != HSG_OK) return st;
+    }
+    const hipError_t e = hsg::launch_advance(dev_counter(h), s);
+    if (e != hipSuccess) return hip_fail(e, "counter launch");
+    return HSG_OK;
+}
+
+// Graph k holds 1 (k = 0) or kGraphSweeps (k = 1) sweeps, each with tempering
+// when pt_every == 1. Captured once on a private stream, replayed on the
+// caller's stream.
+hsg_status launch_graph(hsg_lattice *h, int k, hipStream_t s)
+{
+    if (h->graph_exec[k] == nullptr) {
+        hipError_t e = hipSuccess;
+        if (h->capture_stream == nullptr) e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "capture stream");
+        e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "begin capture");
+        const int n = k == 0 ? 1 : kGraphSweeps;
+        hsg_status st = HSG_OK;
+        for (int i = 0; i < n && st == HSG_OK; ++i) st = enqueue_sweep(h, h->pt_every == 1, h->capture_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->capture_stream, &g);
+        if (st != HSG_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return hip_fail(e, "end capture");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "graph instantiate");
+        }
+        h->graph[k] = g;
+        h->graph_exec[k] = x;
+    }
+    const hipError_t e = hipGraphLaunch(h->graph_exec[k], s);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    return HSG_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *hsg_last_error(void) { return g_err.c_str(); }
+
+#ifndef HSG_BUILD_ID
+#define HSG_BUILD_ID "unknown"
+#endif
+const char *hsg_build_id(void) { return HSG_BUILD_ID; }
 
 hsg_status hsg_query_sizes(const hsg_desc *desc, hsg_sizes *out)
 {
@@ -397,6 +486,13 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
     h->field = static_cast<char *>(d_field);
     h->scratch = static_cast<char *>(d_scratch);
     hipStream_t s = S(stream);
+    {
+        const hipError_t e = hipMemsetAsync(h->state, 0, kAlign, s);
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "init");
+        }
+    }
 
     for (const Group &g : h->lay.g) {
         hsg::PackArgs a = pack_args(h, g);
@@ -447,27 +543,30 @@ hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream)
     if (h->t + (uint64_t)n_sweeps > 0x100000000ull)
         return fail(HSG_E_SIZE, "the sweep counter would pass 2^32 (the counter map limit)");
     hipStream_t s = S(stream);
-    for (int it = 0; it < n_sweeps; ++it) {
-        const int last_kind = h->n_or > 0 ? 1 : 0;
-        for (int r = 0; r < h->n_hb; ++r)
-            for (int p = 0; p < 2; ++p) {
-                const bool energy = (last_kind == 0) && r == h->n_hb - 1 && p == 1;
-                hsg_status st = run_half_sweep(h, 0, p, r, energy, s);
-                if (st != HSG_OK) return st;
-            }
-        for (int r = 0; r < h->n_or; ++r)
-            for (int p = 0; p < 2; ++p) {
-                const bool energy = r == h->n_or - 1 && p == 1;
-                hsg_status st = run_half_sweep(h, 1, p, 0, energy, s);
-                if (st != HSG_OK) return st;
-            }
-        h->have_energies = true;
-        if (h->pt_every > 0 && ((h->t + 1) % (uint64_t)h->pt_every) == 0) {
-            hsg_status st = run_pt(h, (uint32_t)(h->t & 0xFFFFFFFFu), 1u, s);
+    const bool graphs = h->use_graphs && h->pt_every <= 1;
+    int done = 0;
+    if (graphs) {
+        while (n_sweeps - done >= kGraphSweeps) {
+            hsg_status st = launch_graph(h, 1, s);
             if (st != HSG_OK) return st;
+            done += kGraphSweeps;
+            h->t += kGraphSweeps;
         }
-        h->t += 1;
+        while (done < n_sweeps) {
+            hsg_status st = launch_graph(h, 0, s);
+            if (st != HSG_OK) return st;
+            done += 1;
+            h->t += 1;
+        }
+    } else {
+        for (; done < n_sweeps; ++done) {
+            const bool pt = h->pt_every > 0 && ((h->t + 1) % (uint64_t)h->pt_every) == 0;
+            hsg_status st = enqueue_sweep(h, pt, s);
+            if (st != HSG_OK) return st;
+            h->t += 1;
+        }
     }
+    h->have_energies = n_sweeps > 0 || h->have_energies;
     return HSG_OK;
 }
 
@@ -625,11 +724,13 @@ hsg_status hsg_get_state(const hsg_lattice *h, uint64_t *sweep_counter, uint64_t
     return HSG_OK;
 }
 
-hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls)
+hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls, hsg_stream_t stream)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
     if (sweep_counter > 0xFFFFFFFFull || pt_calls > 0xFFFFFFFFull)
         return fail(HSG_E_SIZE, "counters are limited to 32 bits");
+    const hipError_t e = hsg::launch_set_u32(dev_counter(h), (uint32_t)sweep_counter, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "set_state");
     h->t = sweep_counter;
     h->pt_calls = pt_calls;
     return HSG_OK;
@@ -641,6 +742,7 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item)
     if (slots_per_item < 0 || slots_per_item > 16 * 256)
         return fail(HSG_E_INVALID, "slots_per_item = %d", slots_per_item);
     h->slots_per_item = slots_per_item;
+    drop_graphs(h);
     return HSG_OK;
 }
 
@@ -649,6 +751,14 @@ hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
     if (variant < 0 || variant > 2) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..2", variant);
     h->kernel_variant = variant;
+    drop_graphs(h);
+    return HSG_OK;
+}
+
+hsg_status hsg_set_graphs(hsg_lattice *h, int32_t enable)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    h->use_graphs = enable != 0;
     return HSG_OK;
 }
 
@@ -661,7 +771,13 @@ hsg_status hsg_sync(hsg_lattice *h, hsg_stream_t stream)
     return HSG_OK;
 }
 
-void hsg_destroy(hsg_lattice *h) { delete h; }
+void hsg_destroy(hsg_lattice *h)
+{
+    if (h == nullptr) return;
+    drop_graphs(h);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    delete h;
+}
 
 hsg_status hsg_debug_philox(const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int64_t n,
                             hsg_stream_t stream)

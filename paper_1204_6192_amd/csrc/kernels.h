@@ -27,7 +27,8 @@ struct SweepArgs {
     int32_t slots_per_sample;    // O * T
     int32_t T;
     int32_t chunk, n_chunks, n_pb, n_blocks;
-    uint32_t t, rep, parity;
+    const uint32_t *tptr;        // device sweep counter (read at launch time)
+    uint32_t rep, parity;
     uint32_t key0, key1, uid_base;
 };
 
@@ -48,7 +49,8 @@ struct StreamArgs {
     int64_t Nh, n_rep;
     int32_t L, Lh, P, TY, RB, rows, n_ytiles, n_blocks;
     int32_t slots_per_sample, T;
-    uint32_t t, rep, parity;
+    const uint32_t *tptr;  // device sweep counter
+    uint32_t rep, parity;
     uint32_t key0, key1, uid_base;
 };
 hipError_t launch_half_sweep_stream(const StreamArgs &a, int storage, int kind, bool field, bool energy,
@@ -65,6 +67,7 @@ struct PtArgs {
     const double *beta64;        // [T]
     unsigned long long *accepts; // [D][O][T-1]
     int32_t D, O, T;
+    const uint32_t *tptr;  // in-sweep passes read the counter here; nullptr: use ctr1
     uint32_t ctr1, purpose;
     uint32_t key0, key1, uid_base;
 };
@@ -111,6 +114,9 @@ hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slo
                                      int32_t T, hipStream_t s);
 hipError_t launch_invert_maps(const int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
                               int32_t T, hipStream_t s);
+// Advance the device sweep counter by one (end of a sweep).
+hipError_t launch_advance(uint32_t *tptr, hipStream_t s);
+hipError_t launch_set_u32(uint32_t *ptr, uint32_t value, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
                          hipStream_t s);
 

@@ -83,6 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
     }
 
     T *spins = (T *)a.spins;
+    const uint32_t tsweep = *a.tptr;
     for (int cs = 0; cs < a.chunk; ++cs) {
         const int sis = ch * a.chunk + cs;  // replica index inside the sample: o * T + slot
         if (sis >= a.slots_per_sample) break;
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
             if (KIND == 0) {
                 const int o = sis / a.T, ts = sis - o * a.T;
                 const uint32_t c2 = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12) | ((uint32_t)p << 16);
-                r = philox4x32_10(u32x4{(uint32_t)q, a.t, c2, a.uid_base + (uint32_t)d}, a.key0, a.key1);
+                r = philox4x32_10(u32x4{(uint32_t)q, tsweep, c2, a.uid_base + (uint32_t)d}, a.key0, a.key1);
             }
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
@@ -196,11 +197,12 @@ __global__ __launch_bounds__(64) void k_pt(PtArgs a)
     int32_t *sat = a.slot_at_temp + lad * a.T;
     int32_t *tos = a.temp_of_slot + lad * a.T;
     const double *E = a.E + lad * a.T;
+    const uint32_t ctr1 = a.tptr ? *a.tptr : a.ctr1;
     for (int k = 0; k + 1 < a.T; ++k) {
         const int32_t sa = sat[k], sb = sat[k + 1];
         const double delta = (a.beta64[k + 1] - a.beta64[k]) * (E[sb] - E[sa]);
         const u32x4 r = philox4x32_10(
-            u32x4{(uint32_t)k, a.ctr1, ((uint32_t)o << 8) | (a.purpose << 20), a.uid_base + (uint32_t)d}, a.key0,
+            u32x4{(uint32_t)k, ctr1, ((uint32_t)o << 8) | (a.purpose << 20), a.uid_base + (uint32_t)d}, a.key0,
             a.key1);
         const double u = u53(r.x, r.y);
         if (delta >= 0.0 || u <= exp(delta)) {
@@ -498,6 +500,28 @@ hipError_t launch_invert_maps(const int32_t *sat, int32_t *tos, int64_t n_lad, i
     const int64_t n = n_lad * T;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_invert, dim3(blocks_for(n)), dim3(256), 0, s, sat, tos, n_lad, T);
+    return hipGetLastError();
+}
+
+__global__ void k_advance(uint32_t *tptr)
+{
+    if (threadIdx.x == 0) *tptr += 1u;
+}
+
+hipError_t launch_advance(uint32_t *tptr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, tptr);
+    return hipGetLastError();
+}
+
+__global__ void k_set_u32(uint32_t *ptr, uint32_t value)
+{
+    if (threadIdx.x == 0) *ptr = value;
+}
+
+hipError_t launch_set_u32(uint32_t *ptr, uint32_t value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, s, ptr, value);
     return hipGetLastError();
 }
 

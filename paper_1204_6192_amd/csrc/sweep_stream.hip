@@ -66,6 +66,7 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
     const float *Ho = FIELD ? a.Hp + (d * 2 + (1 - p)) * 3 * (int64_t)Nh : nullptr;
     float beta = 0.0f;
     uint32_t c2 = 0, uid = 0;
+    const uint32_t tsweep = *a.tptr;
     if (active) {
         beta = a.beta32[a.temp_of_slot[r]];
         const int o = sis / a.T, ts = sis - o * a.T;
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
                 *reinterpret_cast<float2 *>(&lds[hw + cstride]) = make_float2(g0.y, g1.y);
                 *reinterpret_cast<float2 *>(&lds[hw + 2 * cstride]) = make_float2(g0.z, g1.z);
             }
-            if (KIND == 0) rr = philox4x32_10(u32x4{j0 >> 1, a.t, c2, uid}, a.key0, a.key1);
+            if (KIND == 0) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
         }
         __syncthreads();
         if (active) {

@@ -86,9 +86,10 @@ _SIG = {
     "hsg_set_temp_map": [_vp, _vp, _vp],
     "hsg_get_pt_accepts": [_vp, _vp, _vp],
     "hsg_get_state": [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)],
-    "hsg_set_state": [_vp, _u64, _u64],
+    "hsg_set_state": [_vp, _u64, _u64, _vp],
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
+    "hsg_set_graphs": [_vp, _i32],
     "hsg_sync": [_vp, _vp],
     "hsg_debug_philox": [_vp, _vp, _vp, _i64, _vp],
 }
@@ -100,6 +101,12 @@ lib.hsg_destroy.argtypes = [_vp]
 lib.hsg_destroy.restype = None
 lib.hsg_last_error.argtypes = []
 lib.hsg_last_error.restype = C.c_char_p
+lib.hsg_build_id.argtypes = []
+lib.hsg_build_id.restype = C.c_char_p
+
+
+def build_id() -> str:
+    return lib.hsg_build_id().decode()
 
 
 def declared_symbols() -> List[str]:
@@ -243,10 +250,13 @@ class Lattice:
         return int(t.value), int(n.value), int(s.value)
 
     def set_state(self, sweep_counter: int, pt_calls: int = 0) -> None:
-        check(lib.hsg_set_state(self.h, int(sweep_counter), int(pt_calls)))
+        check(lib.hsg_set_state(self.h, int(sweep_counter), int(pt_calls), _stream(self.stream)))
 
     def set_tuning(self, slots_per_item: int) -> None:
         check(lib.hsg_set_tuning(self.h, int(slots_per_item)))
+
+    def set_graphs(self, enable: bool) -> None:
+        check(lib.hsg_set_graphs(self.h, int(bool(enable))))
 
     def set_kernel(self, variant: int) -> None:
         check(lib.hsg_set_kernel(self.h, int(variant)))

@@ -481,3 +481,26 @@ def test_kernel_variants_bit_identical(hsg, storage):
     assert torch.equal(res[0][1], res[1][1])
     assert torch.allclose(res[0][2], res[1][2], rtol=1e-12, atol=1e-9)
     assert torch.equal(res[0][3], res[1][3])  # same spins, same recomputation
+
+
+@pytest.mark.parametrize("pt_every", [1, 0, 3])
+def test_graph_replay_matches_direct_launches(hsg, pt_every):
+    """Sweeps replayed as captured graphs give the same bits as direct launches.
+    The graphs are replayed many times (1-sweep and 8-sweep graphs), with eager
+    work (energy and overlap measurements, spin reads) and synchronisations
+    between replays, and every replay is compared."""
+    inst = inputs.make_instance("batched", scale_samples=2, L_override=16)
+    a = _lat(hsg, inst.groups, inst.seed, pt_every=pt_every)
+    b = _lat(hsg, inst.groups, inst.seed, pt_every=pt_every)
+    b.set_graphs(False)
+    for n in (1, 8, 3, 9, 1, 16):
+        a.sweep(n)
+        b.sweep(n)
+        assert torch.equal(a.get_energies(), b.get_energies()), n
+        for lat in (a, b):
+            lat.measure_energy()
+            lat.measure_overlap()
+        torch.cuda.synchronize()
+        assert torch.equal(a.get_spins(), b.get_spins()), n
+        assert torch.equal(a.get_temp_map(), b.get_temp_map()), n
+    assert a.get_state()[0] == b.get_state()[0] == 38
