@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
 METRIC = "ns per spin update (HB+OR) & achieved HBM GB/s, FP32 vs batched+compressed"
-STORE_BYTES = {"f32": 12, "f16": 6, "bf16": 6}
+STORE_BYTES = {"f32": 12, "f16": 6, "bf16": 6, "qangle": 4}
 
 
 def log(*a):
@@ -45,7 +45,9 @@ def algorithmic_bytes(groups, storage, kind):
     for g in groups:
         upd = g.n_slots * g.N // 2
         spin = (3 if kind == 1 else 2) * bs
-        shared = 6 * 4 + (12 if g.H is not None else 0)
+        # couplings: six float32 per site, or one byte of sign bits for +-1
+        coupling = 1 if g.coupling_kind == 1 else 6 * 4
+        shared = coupling + (12 if g.H is not None else 0)
         total += upd * spin + g.n_samples * (g.N // 2) * shared
     return total
 
@@ -94,7 +96,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="batched",
                     choices=["tiny", "batched", "field", "uneven", "large"])
-    ap.add_argument("--storage", default=None, choices=["f32", "f16", "bf16"])
+    ap.add_argument("--storage", default=None, choices=["f32", "f16", "bf16", "qangle"])
+    ap.add_argument("--field-amp", type=float, default=None,
+                    help="random-field amplitude H_r of the field workload (default 0.1)")
+    ap.add_argument("--overlap-every", type=int, default=None,
+                    help="measure the overlap after every k-th sweep inside the timed region "
+                         "(default: 1 for the large workload, else never)")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=40)
@@ -114,9 +121,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_gen = time.perf_counter()
-    inst = inputs.make_instance(args.config, storage=args.storage)
-    if inst.storage == "qangle":
-        inst.storage = "f32"
+    inst = inputs.make_instance(args.config, storage=args.storage, field_amp=args.field_amp)
+    overlap_every = args.overlap_every
+    if overlap_every is None:
+        overlap_every = 1 if args.config == "large" else 0
     log(f"workload {args.config}: {len(inst.groups)} group(s), {inst.n_spins} spins, "
         f"storage {inst.storage}; inputs in {time.perf_counter() - t_gen:.1f} s")
     lat = hsg.Lattice(inst.groups, storage=inst.storage, n_hb=inst.n_hb, n_or=inst.n_or,
@@ -133,11 +141,19 @@ def main():
         log(f"calibration copy: {n} bytes read, {n} bytes written")
         del src, dst
 
+    q = torch.empty(sum(g.n_samples * g.n_temps * 10 for g in inst.groups), dtype=torch.float64,
+                    device="cuda")
     lat.sweep(args.warmup)
     lat.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    lat.sweep(args.steps)
+    if overlap_every > 0:
+        for step in range(args.steps):
+            lat.sweep(1)
+            if (step + 1) % overlap_every == 0:
+                lat.measure_overlap(out=q)
+    else:
+        lat.sweep(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lat.sync()
@@ -165,12 +181,16 @@ def main():
            "t_range": [float(inst.groups[0].temps[0]), float(inst.groups[0].temps[-1])],
            "couplings": "bimodal" if inst.groups[0].coupling_kind else "gaussian",
            "field": inst.groups[0].H is not None, "storage": inst.storage,
-           "sweep": f"{inst.n_hb} HB + {inst.n_or} OR + PT every {inst.pt_every}",
+           "sweep": f"{inst.n_hb} HB + {inst.n_or} OR + PT every {inst.pt_every}"
+                    + (f" + overlap every {overlap_every}" if overlap_every else ""),
+           "field_amp": None if inst.groups[0].H is None else float(
+               args.field_amp if args.field_amp is not None else 0.1),
            "spins": lat.n_spins, "replicas": lat.n_replicas}
     out = {
         "metric": METRIC, "value": ns_update, "unit": "ns/update", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "build_id": hsg.build_id(),
         "data": "synthetic", "config": cfg,
         "effective_gbs": eff_gbs,
         "roofline": {"bound": "hbm", "kernel": "k_half_sweep (over-relaxation)",

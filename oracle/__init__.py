@@ -90,6 +90,8 @@ def lib():
         L.hsgo_round_bf16.restype = C.c_double
         L.hsgo_hb_draw_many.argtypes = [dp, C.c_double, u32p, C.c_int64, dp]
         L.hsgo_set_noise.argtypes = [C.c_double, C.c_uint64]
+        L.hsgo_oct_encode.argtypes = [dp, i32p]
+        L.hsgo_oct_decode.argtypes = [i32p, dp]
         _lib = L
     return _lib
 
@@ -165,6 +167,20 @@ def round_f16(v: float) -> float:
 
 def round_bf16(v: float) -> float:
     return lib().hsgo_round_bf16(float(v))
+
+
+def oct_encode(v):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    q = np.zeros(2, dtype=np.int32)
+    lib().hsgo_oct_encode(_p(v, C.c_double), _p(q, C.c_int32))
+    return q
+
+
+def oct_decode(q):
+    q = np.ascontiguousarray(q, dtype=np.int32)
+    v = np.zeros(3)
+    lib().hsgo_oct_decode(_p(q, C.c_int32), _p(v, C.c_double))
+    return v
 
 
 def store_roundtrip(mode: str, s) -> np.ndarray:

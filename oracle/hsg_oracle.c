@@ -483,6 +483,48 @@ double hsgo_round_bf16(double v)
     return copysign(r, v);
 }
 
+/* Quantised-angle storage: the octahedral map of a unit vector (Cigolle,
+ * Donow, Evangelakos, Mara, McGuire, Meyer, "A Survey of Efficient
+ * Representations for Independent Unit Vectors", JCGT 3(2), 2014). v is
+ * projected onto the octahedron |x| + |y| + |z| = 1; the lower half (z < 0) is
+ * folded over the diagonals; the two coordinates in [-1, 1] are stored as 16-bit
+ * signed normalised integers q = round_to_nearest_even(c * 32767). sgn(0) = +1. */
+static double sgn_nz(double a) { return a >= 0.0 ? 1.0 : -1.0; }
+
+void hsgo_oct_encode(const double v[3], int32_t q[2])
+{
+    double l1 = fabs(v[0]) + fabs(v[1]) + fabs(v[2]);
+    double px = v[0] / l1, py = v[1] / l1;
+    if (v[2] < 0.0) {
+        double fx = (1.0 - fabs(py)) * sgn_nz(px);
+        double fy = (1.0 - fabs(px)) * sgn_nz(py);
+        px = fx;
+        py = fy;
+    }
+    if (px > 1.0) px = 1.0;
+    if (px < -1.0) px = -1.0;
+    if (py > 1.0) py = 1.0;
+    if (py < -1.0) py = -1.0;
+    q[0] = (int32_t)nearbyint(px * 32767.0);
+    q[1] = (int32_t)nearbyint(py * 32767.0);
+}
+
+void hsgo_oct_decode(const int32_t q[2], double v[3])
+{
+    double fx = (double)q[0] / 32767.0, fy = (double)q[1] / 32767.0;
+    double vz = 1.0 - fabs(fx) - fabs(fy);
+    if (vz < 0.0) {
+        double ax = (1.0 - fabs(fy)) * sgn_nz(fx);
+        double ay = (1.0 - fabs(fx)) * sgn_nz(fy);
+        fx = ax;
+        fy = ay;
+    }
+    v[0] = fx;
+    v[1] = fy;
+    v[2] = vz;
+    normalise3(v);
+}
+
 void hsgo_store_roundtrip(int mode, double s[3])
 {
     if (mode == 0) return;
@@ -490,6 +532,11 @@ void hsgo_store_roundtrip(int mode, double s[3])
         for (int m = 0; m < 3; ++m) s[m] = hsgo_round_f16(s[m]);
     } else if (mode == 2) {
         for (int m = 0; m < 3; ++m) s[m] = hsgo_round_bf16(s[m]);
+    } else if (mode == 3) {
+        int32_t q[2];
+        hsgo_oct_encode(s, q);
+        hsgo_oct_decode(q, s);
+        return;
     }
     normalise3(s);
 }

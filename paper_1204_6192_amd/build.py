@@ -12,7 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsg.so")
-SOURCES = ["api.hip", "kernels.hip", "sweep_stream.hip"]
+SOURCES = ["api.hip", "kernels.hip", "sweep_stream.hip", "sweep_stream_s0.hip", "sweep_stream_s1.hip",
+           "sweep_stream_s2.hip", "sweep_stream_s3.hip"]
 ARCH = os.environ.get("HSG_OFFLOAD_ARCH", "gfx950")
 
 
@@ -42,13 +43,28 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off", "-Xclang"
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object in parallel, then link libhsg.so."""
+    import concurrent.futures
+    import tempfile
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}"] + FLAGS + [
-        f'-DHSG_BUILD_ID="{source_id()}"', "-I", os.path.join(HERE, "..", "include"),
-        "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    bid = source_id()
+    with tempfile.TemporaryDirectory(prefix="hsg_build_") as work:
+        def compile_one(src):
+            obj = os.path.join(work, src + ".o")
+            cmd = [hipcc(), f"--offload-arch={ARCH}"] + [f for f in FLAGS if f != "-shared"] + [
+                f'-DHSG_BUILD_ID="{bid}"', "-I", os.path.join(HERE, "..", "include"), "-c",
+                os.path.join(CSRC, src), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.check_call(cmd)
+            return obj
+        jobs = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            objs = list(ex.map(compile_one, SOURCES))
+        link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(link), flush=True)
+        subprocess.check_call(link)
     os.replace(tmp, LIB)
     return LIB
 

@@ -41,7 +41,16 @@ hsg_status hip_fail(hipError_t e, const char *what)
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-int bytes_per_component(int storage) { return storage == HSG_STORE_F32 ? 4 : 2; }
+// Bytes of stored spin per site: 3 float32, 3 x 16-bit, or one 32-bit angle word.
+int bytes_per_spin(int storage)
+{
+    switch (storage) {
+    case HSG_STORE_F32: return 12;
+    case HSG_STORE_F16:
+    case HSG_STORE_BF16: return 6;
+    default: return 4;
+    }
+}
 
 struct Group {
     int32_t L, D, O, T;
@@ -56,7 +65,7 @@ struct Group {
     int64_t can_site0;  // element offset of the group in the canonical J and H arrays
     // byte offsets
     uint64_t o_spins, o_sat, o_tos, o_E, o_acc;  // state
-    uint64_t o_J6, o_b64, o_b32;                 // couplings
+    uint64_t o_J6, o_b64, o_b32, o_Jbits;        // couplings
     uint64_t o_H;                                // field
     uint64_t o_scr;                              // scratch
     int32_t n_pb_sweep;                          // blocks of 256 site pairs per replica
@@ -106,8 +115,6 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
     if (desc->groups == nullptr) return fail(HSG_E_INVALID, "groups is NULL");
     if (desc->storage < HSG_STORE_F32 || desc->storage > HSG_STORE_QANGLE)
         return fail(HSG_E_INVALID, "storage = %d is not an HSG_STORE_* value", desc->storage);
-    if (desc->storage == HSG_STORE_QANGLE)
-        return fail(HSG_E_UNSUPPORTED, "quantised-angle storage is not built in this library");
     if (desc->n_hb < 0 || desc->n_hb > 16) return fail(HSG_E_SIZE, "n_hb = %d, need 0..16", desc->n_hb);
     if (desc->n_or < 0 || desc->n_or > 64) return fail(HSG_E_SIZE, "n_or = %d, need 0..64", desc->n_or);
     if (desc->n_hb + desc->n_or < 1) return fail(HSG_E_INVALID, "a sweep needs n_hb + n_or >= 1");
@@ -159,7 +166,7 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         stream_geometry(g);
         // state
         g.o_spins = st;
-        st = align_up(st + (uint64_t)g.n_rep * 6 * g.Nh * bytes_per_component(desc->storage));
+        st = align_up(st + (uint64_t)g.n_rep * 2 * g.Nh * bytes_per_spin(desc->storage));
         g.o_sat = st;
         st = align_up(st + (uint64_t)g.n_rep * 4);
         g.o_tos = st;
@@ -175,6 +182,8 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         cp = align_up(cp + (uint64_t)g.T * 8);
         g.o_b32 = cp;
         cp = align_up(cp + (uint64_t)g.T * 4);
+        g.o_Jbits = cp;
+        if (g.ckind == 1) cp = align_up(cp + (uint64_t)g.D * 2 * g.Nh);
         // field
         g.o_H = fd;
         if (g.field) fd = align_up(fd + (uint64_t)g.D * 2 * 3 * g.Nh * 4);
@@ -281,6 +290,7 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     hsg::StreamArgs a{};
     a.spins = h->state + g.o_spins;
     a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+    a.Jbits = g.ckind == 1 ? reinterpret_cast<const uint8_t *>(h->coup + g.o_Jbits) : nullptr;
     a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
     a.temp_of_slot = reinterpret_cast<const int32_t *>(h->state + g.o_tos);
     a.beta32 = reinterpret_cast<const float *>(h->coup + g.o_b32);
@@ -306,26 +316,57 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     return a;
 }
 
+// One half-sweep of every group: the groups the z-march handles go into as few
+// launches as possible (up to kMaxStreamGroups per launch); the others use the
+// gather kernel one group at a time.
 hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool energy, hipStream_t s)
 {
+    hsg::MultiStreamArgs m{};
+    unsigned threads = 0;
+    size_t lds = 0;
+    int64_t blocks = 0;
+    auto flush = [&]() -> hsg_status {
+        if (m.n_groups == 0) return HSG_OK;
+        m.block_start[m.n_groups] = (int32_t)blocks;
+        m.n_blocks = (int32_t)blocks;
+        const hipError_t e = hsg::launch_half_sweep_stream(m, h->storage, kind, energy, threads, lds, s);
+        m = hsg::MultiStreamArgs{};
+        threads = 0;
+        lds = 0;
+        blocks = 0;
+        if (e != hipSuccess) return hip_fail(e, "half-sweep launch");
+        return HSG_OK;
+    };
     for (const Group &g : h->lay.g) {
-        double *partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
-        int n_pb = 0;
-        hipError_t e;
         if (use_stream(h, g)) {
+            if (m.n_groups == hsg::kMaxStreamGroups) {
+                hsg_status st = flush();
+                if (st != HSG_OK) return st;
+            }
             const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep);
-            if ((g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
-            e = hsg::launch_half_sweep_stream(a, h->storage, kind, g.field, energy, s);
-            n_pb = a.n_ytiles;
+            const int64_t nb = (int64_t)a.n_blocks;
+            if (blocks + nb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
+            m.block_start[m.n_groups] = (int32_t)blocks;
+            m.g[m.n_groups++] = a;
+            blocks += nb;
+            const unsigned t = (unsigned)((a.RB * a.TY * a.P + 63) / 64 * 64);
+            threads = t > threads ? t : threads;
+            const size_t l = (size_t)2 * a.RB * 3 * a.rows * a.Lh * sizeof(float);
+            lds = l > lds ? l : lds;
         } else {
             const hsg::SweepArgs a = sweep_args(h, g, parity, (uint32_t)rep);
             if ((int64_t)g.D * a.n_chunks * a.n_pb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
-            e = hsg::launch_half_sweep(a, h->storage, kind, g.field, energy, s);
-            n_pb = a.n_pb;
+            const hipError_t e = hsg::launch_half_sweep(a, h->storage, kind, g.field, energy, s);
+            if (e != hipSuccess) return hip_fail(e, "half-sweep launch");
         }
-        if (e != hipSuccess) return hip_fail(e, "half-sweep launch");
-        if (energy) {
-            e = hsg::launch_reduce_partials(partials, n_pb, g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
+    }
+    hsg_status st = flush();
+    if (st != HSG_OK) return st;
+    if (energy) {
+        for (const Group &g : h->lay.g) {
+            const int n_pb = use_stream(h, g) ? g.s_ytiles : g.n_pb_sweep;
+            const hipError_t e = hsg::launch_reduce_partials(reinterpret_cast<double *>(h->scratch + g.o_scr), n_pb,
+                                                             g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
             if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
         }
     }
@@ -501,6 +542,19 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
         a.H_can = g.field ? d_H + g.can_site0 : nullptr;
         hipError_t e = hsg::launch_pack_spins(a, h->storage, s);
         if (e == hipSuccess) e = hsg::launch_pack_couplings(a, s);
+        if (e == hipSuccess && g.ckind == 1) {
+            int32_t *flag = reinterpret_cast<int32_t *>(h->scratch + g.o_scr);
+            e = hsg::launch_check_pm1(a.J_can, (int64_t)g.D * 3 * g.N, flag, s);
+            int32_t bad = 0;
+            if (e == hipSuccess) e = hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            if (e == hipSuccess && bad != 0) {
+                delete h;
+                return fail(HSG_E_INVALID, "group with coupling_kind = 1 has couplings other than +-1");
+            }
+            if (e == hipSuccess)
+                e = hsg::launch_pack_jbits(a.J_can, reinterpret_cast<uint8_t *>(h->coup + g.o_Jbits), g.D, g.L, s);
+        }
         if (e == hipSuccess && g.field) e = hsg::launch_pack_field(a, s);
         // ladders: float64 and float32 inverse temperatures
         std::vector<double> b64(g.T);

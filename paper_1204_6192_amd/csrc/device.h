@@ -172,6 +172,7 @@ struct Codec;
 template <>
 struct Codec<0> {  // float32: stored renormalised, read as is
     using T = float;
+    static constexpr int kPlanes = 3;  // component planes per parity
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
         return v3{p[j], p[cs + j], p[2 * cs + j]};
@@ -204,6 +205,7 @@ struct Codec<0> {  // float32: stored renormalised, read as is
 template <>
 struct Codec<1> {  // float16 components (round to nearest even), renormalised on load
     using T = __half;
+    static constexpr int kPlanes = 3;
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
         return normalise3(v3{__half2float(p[j]), __half2float(p[cs + j]), __half2float(p[2 * cs + j])});
@@ -244,8 +246,9 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float v)
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
 template <>
-struct Codec<2> {
+struct Codec<2> {  // bfloat16 components, renormalised on load
     using T = uint16_t;
+    static constexpr int kPlanes = 3;
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
         return normalise3(v3{bf16_to_f32(p[j]), bf16_to_f32(p[cs + j]), bf16_to_f32(p[2 * cs + j])});
@@ -275,6 +278,62 @@ struct Codec<2> {
         *reinterpret_cast<uint32_t *>(p + j0) = (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(b.x) << 16);
         *reinterpret_cast<uint32_t *>(p + cs + j0) = (uint32_t)f32_to_bf16_rne(a.y) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
         *reinterpret_cast<uint32_t *>(p + 2 * cs + j0) = (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(b.z) << 16);
+    }
+};
+
+// Quantised angle: octahedral map (Cigolle et al., JCGT 3(2), 2014). The unit
+// vector is projected onto |x| + |y| + |z| = 1, the lower half folded over the
+// diagonals, and the two coordinates stored as 16-bit signed normalised
+// integers (round to nearest even of c * 32767) packed in one 32-bit word per
+// site, x in the low half. One plane per parity; renormalised on load.
+__device__ __forceinline__ float sgn_nz(float a) { return a >= 0.0f ? 1.0f : -1.0f; }
+
+__device__ __forceinline__ uint32_t oct_encode(v3 v)
+{
+    const float l1 = fabsf(v.x) + fabsf(v.y) + fabsf(v.z);
+    float px = v.x / l1, py = v.y / l1;
+    if (v.z < 0.0f) {
+        const float fx = (1.0f - fabsf(py)) * sgn_nz(px);
+        const float fy = (1.0f - fabsf(px)) * sgn_nz(py);
+        px = fx;
+        py = fy;
+    }
+    px = fminf(1.0f, fmaxf(-1.0f, px));
+    py = fminf(1.0f, fmaxf(-1.0f, py));
+    const int qx = (int)rintf(px * 32767.0f), qy = (int)rintf(py * 32767.0f);
+    return ((uint32_t)qx & 0xFFFFu) | ((uint32_t)qy << 16);
+}
+
+__device__ __forceinline__ v3 oct_decode(uint32_t w)
+{
+    float fx = (float)(int16_t)(w & 0xFFFFu) / 32767.0f;
+    float fy = (float)(int16_t)(w >> 16) / 32767.0f;
+    const float vz = 1.0f - fabsf(fx) - fabsf(fy);
+    if (vz < 0.0f) {
+        const float ax = (1.0f - fabsf(fy)) * sgn_nz(fx);
+        const float ay = (1.0f - fabsf(fx)) * sgn_nz(fy);
+        fx = ax;
+        fy = ay;
+    }
+    return normalise3(v3{fx, fy, vz});
+}
+
+template <>
+struct Codec<3> {
+    using T = uint32_t;
+    static constexpr int kPlanes = 1;
+    __device__ static __forceinline__ v3 load(const T *p, int64_t, int64_t j) { return oct_decode(p[j]); }
+    __device__ static __forceinline__ void store(T *p, int64_t, int64_t j, v3 s) { p[j] = oct_encode(s); }
+    __device__ static __forceinline__ v3 stored_value(v3 s) { return oct_decode(oct_encode(s)); }
+    __device__ static __forceinline__ void load_pair(const T *p, uint32_t, uint32_t j0, v3 &a, v3 &b)
+    {
+        const uint2 w = *reinterpret_cast<const uint2 *>(p + j0);
+        a = oct_decode(w.x);
+        b = oct_decode(w.y);
+    }
+    __device__ static __forceinline__ void store_pair(T *p, uint32_t, uint32_t j0, v3 a, v3 b)
+    {
+        *reinterpret_cast<uint2 *>(p + j0) = make_uint2(oct_encode(a), oct_encode(b));
     }
 };
 

@@ -42,6 +42,7 @@ hipError_t launch_half_sweep(const SweepArgs &a, int storage, int kind, bool fie
 struct StreamArgs {
     void *spins;
     const float *J6;
+    const uint8_t *Jbits;  // non-null: couplings are +-1, bit n of byte j set <=> J_n(j) = -1
     const float *Hp;
     const int32_t *temp_of_slot;
     const float *beta32;
@@ -53,8 +54,22 @@ struct StreamArgs {
     uint32_t rep, parity;
     uint32_t key0, key1, uid_base;
 };
-hipError_t launch_half_sweep_stream(const StreamArgs &a, int storage, int kind, bool field, bool energy,
-                                    hipStream_t s);
+// Up to kMaxStreamGroups lattice-size groups in one launch: group k owns the
+// blocks [block_start[k], block_start[k + 1]).
+constexpr int kMaxStreamGroups = 8;
+struct MultiStreamArgs {
+    int32_t n_groups, n_blocks;
+    int32_t block_start[kMaxStreamGroups + 1];
+    StreamArgs g[kMaxStreamGroups];
+};
+hipError_t launch_half_sweep_stream(const MultiStreamArgs &m, int storage, int kind, bool energy,
+                                    unsigned threads, size_t lds_bytes, hipStream_t s);
+
+// *flag = 1 if any of the n values is not exactly +1 or -1, else 0.
+hipError_t launch_check_pm1(const float *v, int64_t n, int32_t *flag, hipStream_t s);
+
+// Six coupling sign bits per site, [d][parity][Nh] bytes, from canonical J.
+hipError_t launch_pack_jbits(const float *J_can, uint8_t *Jbits, int64_t D, int32_t L, hipStream_t s);
 
 // E[r] = sum over the n_pb partials of replica r, for n_rep replicas.
 hipError_t launch_reduce_partials(const double *partials, int n_pb, int64_t n_rep, double *E,

@@ -91,9 +91,9 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
         double e = 0.0;
         if (active) {
             const float beta = a.beta32[a.temp_of_slot[rep]];
-            T *base = spins + rep * 6 * Nh;
-            T *own = base + (int64_t)p * 3 * Nh;
-            const T *oth = base + (int64_t)(1 - p) * 3 * Nh;
+            T *base = spins + rep * 2 * C::kPlanes * Nh;
+            T *own = base + (int64_t)p * C::kPlanes * Nh;
+            const T *oth = base + (int64_t)(1 - p) * C::kPlanes * Nh;
             u32x4 r{0u, 0u, 0u, 0u};
             if (KIND == 0) {
                 const int o = sis / a.T, ts = sis - o * a.T;
@@ -161,6 +161,7 @@ hipError_t launch_half_sweep(const SweepArgs &a, int storage, int kind, bool fie
     case 0: return launch_half_sweep_s<0>(a, kind, field, energy, s);
     case 1: return launch_half_sweep_s<1>(a, kind, field, energy, s);
     case 2: return launch_half_sweep_s<2>(a, kind, field, energy, s);
+    case 3: return launch_half_sweep_s<3>(a, kind, field, energy, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(256) void k_pack_spins(PackArgs a)
     const Site c = site_of(i, a.L);
     const int p = (c.x + c.y + c.z) & 1;
     const float *src = a.spins_can + rep * 3 * N;
-    typename C::T *dst = (typename C::T *)a.spins_int + rep * 6 * Nh + (int64_t)p * 3 * Nh;
+    typename C::T *dst = (typename C::T *)a.spins_int + (rep * 2 + p) * C::kPlanes * Nh;
     C::store(dst, Nh, i >> 1, v3{src[i], src[N + i], src[2 * N + i]});
 }
 
@@ -267,7 +268,7 @@ __global__ __launch_bounds__(256) void k_unpack_spins(PackArgs a)
     const int64_t rep = gid / N, i = gid - rep * N;
     const Site c = site_of(i, a.L);
     const int p = (c.x + c.y + c.z) & 1;
-    const typename C::T *src = (const typename C::T *)a.spins_int + rep * 6 * Nh + (int64_t)p * 3 * Nh;
+    const typename C::T *src = (const typename C::T *)a.spins_int + (rep * 2 + p) * C::kPlanes * Nh;
     const v3 s = C::load(src, Nh, i >> 1);
     float *dst = a.spins_can + rep * 3 * N;
     dst[i] = s.x;
@@ -308,7 +309,54 @@ __global__ __launch_bounds__(256) void k_pack_field(PackArgs a)
     for (int m = 0; m < 3; ++m) Hp[m * Nh + j] = Hc[m * N + i];
 }
 
+// Coupling sign bits: bit n of byte [d][p][j] is set when the n-th coupling of
+// the site (order +x, -x, +y, -y, +z, -z) is negative.
+__global__ __launch_bounds__(256) void k_pack_jbits(const float *J_can, uint8_t *Jbits, int64_t D, int32_t L)
+{
+    const int64_t N = (int64_t)L * L * L, Nh = N / 2;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= D * N) return;
+    const int64_t d = gid / N, i = gid - d * N;
+    const int32_t x = (int32_t)(i % L), y = (int32_t)((i / L) % L), z = (int32_t)(i / ((int64_t)L * L));
+    const int p = (x + y + z) & 1;
+    const float *Jc = J_can + d * 3 * N;
+    const int64_t xm = (int64_t)((x + L - 1) % L) + (int64_t)L * (y + (int64_t)L * z);
+    const int64_t ym = (int64_t)x + (int64_t)L * (((y + L - 1) % L) + (int64_t)L * z);
+    const int64_t zm = (int64_t)x + (int64_t)L * (y + (int64_t)L * ((z + L - 1) % L));
+    const float j6[6] = {Jc[i], Jc[xm], Jc[N + i], Jc[N + ym], Jc[2 * N + i], Jc[2 * N + zm]};
+    uint32_t b = 0;
+    for (int n = 0; n < 6; ++n) b |= (j6[n] < 0.0f ? 1u : 0u) << n;
+    Jbits[(d * 2 + p) * Nh + (i >> 1)] = (uint8_t)b;
+}
+
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+__global__ void k_clear_i32(int32_t *flag)
+{
+    if (threadIdx.x == 0) *flag = 0;
+}
+
+__global__ __launch_bounds__(256) void k_check_pm1(const float *v, int64_t n, int32_t *flag)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n && v[g] != 1.0f && v[g] != -1.0f) atomicOr(flag, 1);
+}
+
+hipError_t launch_check_pm1(const float *v, int64_t n, int32_t *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_i32, dim3(1), dim3(64), 0, s, flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || n == 0) return e;
+    hipLaunchKernelGGL(k_check_pm1, dim3(blocks_for(n)), dim3(256), 0, s, v, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_jbits(const float *J_can, uint8_t *Jbits, int64_t D, int32_t L, hipStream_t s)
+{
+    const int64_t n = D * (int64_t)L * L * L;
+    hipLaunchKernelGGL(k_pack_jbits, dim3(blocks_for(n)), dim3(256), 0, s, J_can, Jbits, D, L);
+    return hipGetLastError();
+}
 
 hipError_t launch_pack_spins(const PackArgs &a, int storage, hipStream_t s)
 {
@@ -318,6 +366,7 @@ hipError_t launch_pack_spins(const PackArgs &a, int storage, hipStream_t s)
     case 0: hipLaunchKernelGGL(k_pack_spins<0>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_pack_spins<1>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_pack_spins<2>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_pack_spins<3>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -331,6 +380,7 @@ hipError_t launch_unpack_spins(const PackArgs &a, int storage, hipStream_t s)
     case 0: hipLaunchKernelGGL(k_unpack_spins<0>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_unpack_spins<1>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_unpack_spins<2>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_unpack_spins<3>, dim3(blocks_for(n)), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -367,18 +417,18 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
     const int64_t d = rep / a.slots_per_sample;
     double e = 0.0;
     if (j < Nh) {
-        const T *base = (const T *)a.spins + rep * 6 * Nh;
+        const T *base = (const T *)a.spins + rep * 2 * C::kPlanes * Nh;
         int64_t nb[6];
         neighbours(j, a.L, a.Lh, 0, nb);
         const v3 s0 = C::load(base, Nh, j);
         const float *J6 = a.J6 + (d * 2 + 0) * 6 * Nh;
         for (int n = 0; n < 6; ++n) {
-            const v3 sn = C::load(base + 3 * Nh, Nh, nb[n]);
+            const v3 sn = C::load(base + C::kPlanes * Nh, Nh, nb[n]);
             const double sd = (double)s0.x * sn.x + (double)s0.y * sn.y + (double)s0.z * sn.z;
             e -= (double)J6[n * Nh + j] * sd;
         }
         if (a.Hp != nullptr) {
-            const v3 s1 = C::load(base + 3 * Nh, Nh, j);
+            const v3 s1 = C::load(base + C::kPlanes * Nh, Nh, j);
             const float *H0 = a.Hp + (d * 2 + 0) * 3 * Nh;
             const float *H1 = a.Hp + (d * 2 + 1) * 3 * Nh;
             e -= (double)H0[j] * s0.x + (double)H0[Nh + j] * s0.y + (double)H0[2 * Nh + j] * s0.z;
@@ -397,6 +447,7 @@ hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s)
     case 0: hipLaunchKernelGGL(k_energy<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_energy<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_energy<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_energy<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -416,13 +467,13 @@ __global__ __launch_bounds__(kBlock) void k_overlap(OverlapArgs a)
     const int64_t j = (int64_t)pb * kBlock + threadIdx.x;
     const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
     const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
-    const T *A = (const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 6 * Nh;
-    const T *B = (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 6 * Nh;
+    const T *A = (const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh;
+    const T *B = (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     if (j < Nh) {
         for (int p = 0; p < 2; ++p) {
-            const v3 x = C::load(A + (int64_t)p * 3 * Nh, Nh, j);
-            const v3 y = C::load(B + (int64_t)p * 3 * Nh, Nh, j);
+            const v3 x = C::load(A + (int64_t)p * C::kPlanes * Nh, Nh, j);
+            const v3 y = C::load(B + (int64_t)p * C::kPlanes * Nh, Nh, j);
             const double xa[3] = {x.x, x.y, x.z}, ya[3] = {y.x, y.y, y.z};
             for (int m = 0; m < 3; ++m)
                 for (int n = 0; n < 3; ++n) acc[3 * m + n] += xa[m] * ya[n];
@@ -458,6 +509,7 @@ hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
     case 0: hipLaunchKernelGGL(k_overlap<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     case 1: hipLaunchKernelGGL(k_overlap<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     case 2: hipLaunchKernelGGL(k_overlap<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_overlap<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

@@ -1,241 +1,22 @@
-// sweep_stream.hip -- checkerboard half-sweep as a z-march (L divisible by 4).
-//
-// One work-group owns RB replicas x TY rows (all of x) and walks z = 0 .. L-1.
-// At step z every thread updates the two parity-p sites (x/2 = 2m, 2m + 1) of
-// its row in plane z (Eqs. (2) and (3)). Their six neighbours all lie on the
-// other parity:
-//   - plane z of the other parity is staged in LDS (decoded and renormalised
-//     once per site), giving the +-x and +-y neighbours, with periodic wrap;
-//   - planes z - 1 and z + 1 at the thread's own two positions stay in
-//     registers and roll forward, giving the +-z neighbours.
-// So each stored spin of a replica is read from HBM once per half-sweep (plus
-// two halo rows per plane when the tile is narrower than the lattice). The
-// sample's couplings stay in L2: the replicas of one sample run as consecutive
-// work-groups on the same XCD. The arithmetic per site is the one of the
-// generic kernel (same neighbour order, same functions), so both produce the
-// same bits.
-#include "device.h"
+// sweep_stream.hip -- dispatch of the z-march half-sweep by storage codec.
 #include "kernels.h"
 
 namespace hsg {
 
-// UNI: every wave holds a single replica (TY * P a multiple of 64), so the
-// replica's base addresses are wave-uniform and live in scalar registers, and
-// the per-lane addressing is 32-bit.
-template <int STORE, int KIND, bool FIELD, bool ENERGY, bool UNI>
-__global__ __launch_bounds__(kBlock) void k_half_sweep_stream(StreamArgs a)
-{
-    using C = Codec<STORE>;
-    using T = typename C::T;
-    extern __shared__ float lds[];  // two buffers of [RB][3][rows][Lh] floats
-    __shared__ double red[kBlock];
-
-    const int lb = xcd_remap((int)blockIdx.x, a.n_blocks);
-    const int ytile = lb % a.n_ytiles;
-    const int rblk = lb / a.n_ytiles;
-    const int tid = threadIdx.x;
-    const int per_rep = a.TY * a.P;
-    const int rb = tid / per_rep;
-    const int rem = tid - rb * per_rep;
-    const int ty = rem / a.P, m = rem - ty * a.P;
-    const int64_t r_lane = (int64_t)rblk * a.RB + rb;  // replica (canonical order within the group)
-    const bool active = rb < a.RB && r_lane < a.n_rep;
-    const int L = a.L, Lh = a.Lh;
-    const uint32_t Nh = (uint32_t)a.Nh;
-    const int p = (int)a.parity;
-    const bool full = a.TY == L;
-    const int y = ytile * a.TY + ty;
-    const int lrow = full ? ty : ty + 1;                         // my row in the LDS plane
-    const int lrm = full ? (ty == 0 ? L - 1 : ty - 1) : ty;      // row y - 1
-    const int lrp = full ? (ty == L - 1 ? 0 : ty + 1) : ty + 2;  // row y + 1
-    const int cstride = a.rows * Lh;                             // floats per component plane
-    const int xh0 = 2 * m;
-    const int rbc = active ? rb : 0;
-    const int lbuf[2] = {rbc * 3 * cstride, (a.RB + rbc) * 3 * cstride};
-
-    int64_t r = r_lane;
-    if (UNI) r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r_lane >> 32)) << 32) |
-                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r_lane & 0xFFFFFFFF));
-    const int64_t d = r / a.slots_per_sample;
-    const int sis = (int)(r - d * a.slots_per_sample);
-    T *base = (T *)a.spins + r * 6 * (int64_t)Nh;
-    T *own = base + (int64_t)p * 3 * Nh;
-    const T *oth = base + (int64_t)(1 - p) * 3 * Nh;
-    const float *Jb = a.J6 + (d * 2 + p) * 6 * (int64_t)Nh;
-    const float *Hb = FIELD ? a.Hp + (d * 2 + p) * 3 * (int64_t)Nh : nullptr;
-    const float *Ho = FIELD ? a.Hp + (d * 2 + (1 - p)) * 3 * (int64_t)Nh : nullptr;
-    float beta = 0.0f;
-    uint32_t c2 = 0, uid = 0;
-    const uint32_t tsweep = *a.tptr;
-    if (active) {
-        beta = a.beta32[a.temp_of_slot[r]];
-        const int o = sis / a.T, ts = sis - o * a.T;
-        c2 = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12) | ((uint32_t)p << 16);
-        uid = a.uid_base + (uint32_t)d;
-    }
-
-    // rolling planes of the other parity at my two positions
-    v3 prv0{}, prv1{}, cur0{}, cur1{}, nxt0{}, nxt1{};
-    if (active) {
-        C::load_pair(oth, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), prv0, prv1);
-        C::load_pair(oth, Nh, (uint32_t)(y * Lh + xh0), cur0, cur1);
-    }
-    double e = 0.0;
-
-    for (int z = 0; z < L; ++z) {
-        const int lo = lbuf[z & 1];
-        const int zn = (z + 1 == L) ? 0 : z + 1;
-        const uint32_t j0 = (uint32_t)((z * L + y) * Lh + xh0);  // my first site, half-index
-        float2 jc[6];
-        v3 hs0{0.f, 0.f, 0.f}, hs1{0.f, 0.f, 0.f}, old0{}, old1{};
-        u32x4 rr{0u, 0u, 0u, 0u};
-        if (active) {
-            // every global access of this step is issued before the barrier
-            C::load_pair(oth, Nh, (uint32_t)((zn * L + y) * Lh + xh0), nxt0, nxt1);
-#pragma unroll
-            for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
-            if (FIELD) {
-                const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
-                const float2 hy = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
-                const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
-                hs0 = v3{hx.x, hy.x, hz.x};
-                hs1 = v3{hx.y, hy.y, hz.y};
-            }
-            if (KIND == 1) C::load_pair(own, Nh, j0, old0, old1);
-            // stage plane z (my two positions) in LDS
-            const int w = lo + lrow * Lh + xh0;
-            *reinterpret_cast<float2 *>(&lds[w]) = make_float2(cur0.x, cur1.x);
-            *reinterpret_cast<float2 *>(&lds[w + cstride]) = make_float2(cur0.y, cur1.y);
-            *reinterpret_cast<float2 *>(&lds[w + 2 * cstride]) = make_float2(cur0.z, cur1.z);
-            if (!full && (ty == 0 || ty == a.TY - 1)) {  // halo rows y0 - 1 and y0 + TY
-                const int hy = (ty == 0) ? (y == 0 ? L - 1 : y - 1) : (y + 1 == L ? 0 : y + 1);
-                const int hw = lo + ((ty == 0) ? 0 : a.TY + 1) * Lh + xh0;
-                v3 g0, g1;
-                C::load_pair(oth, Nh, (uint32_t)((z * L + hy) * Lh + xh0), g0, g1);
-                *reinterpret_cast<float2 *>(&lds[hw]) = make_float2(g0.x, g1.x);
-                *reinterpret_cast<float2 *>(&lds[hw + cstride]) = make_float2(g0.y, g1.y);
-                *reinterpret_cast<float2 *>(&lds[hw + 2 * cstride]) = make_float2(g0.z, g1.z);
-            }
-            if (KIND == 0) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
-        }
-        __syncthreads();
-        if (active) {
-            const int o = (y + z + p) & 1;  // x = 2 x/2 + o on this row
-            // the x-neighbour that is not one of my own two positions
-            const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
-            const int we = lo + lrow * Lh + xe;
-            const v3 ex{lds[we], lds[we + cstride], lds[we + 2 * cstride]};
-            const int wm = lo + lrm * Lh + xh0, wp = lo + lrp * Lh + xh0;
-            const float2 ym0 = *reinterpret_cast<const float2 *>(&lds[wm]);
-            const float2 ym1 = *reinterpret_cast<const float2 *>(&lds[wm + cstride]);
-            const float2 ym2 = *reinterpret_cast<const float2 *>(&lds[wm + 2 * cstride]);
-            const float2 yp0 = *reinterpret_cast<const float2 *>(&lds[wp]);
-            const float2 yp1 = *reinterpret_cast<const float2 *>(&lds[wp + cstride]);
-            const float2 yp2 = *reinterpret_cast<const float2 *>(&lds[wp + 2 * cstride]);
-            // neighbours in the order +x, -x, +y, -y, +z, -z
-            v3 nb0[6], nb1[6];
-            if (o) {  // site k at x = 2(xh0 + k) + 1: +x -> xh0 + k + 1, -x -> xh0 + k
-                nb0[0] = cur1; nb0[1] = cur0;
-                nb1[0] = ex;   nb1[1] = cur1;
-            } else {  // x = 2(xh0 + k): +x -> xh0 + k, -x -> xh0 + k - 1
-                nb0[0] = cur0; nb0[1] = ex;
-                nb1[0] = cur1; nb1[1] = cur0;
-            }
-            nb0[2] = v3{yp0.x, yp1.x, yp2.x};
-            nb1[2] = v3{yp0.y, yp1.y, yp2.y};
-            nb0[3] = v3{ym0.x, ym1.x, ym2.x};
-            nb1[3] = v3{ym0.y, ym1.y, ym2.y};
-            nb0[4] = nxt0; nb1[4] = nxt1;
-            nb0[5] = prv0; nb1[5] = prv1;
-            v3 h0 = hs0, h1 = hs1;
-            double hx0 = hs0.x, hy0 = hs0.y, hz0 = hs0.z, hx1 = hs1.x, hy1 = hs1.y, hz1 = hs1.z;
-#pragma unroll
-            for (int n = 0; n < 6; ++n) {
-                acc3(h0, jc[n].x, nb0[n]);
-                acc3(h1, jc[n].y, nb1[n]);
-                if (ENERGY) {
-                    hx0 = fma((double)jc[n].x, (double)nb0[n].x, hx0);
-                    hy0 = fma((double)jc[n].x, (double)nb0[n].y, hy0);
-                    hz0 = fma((double)jc[n].x, (double)nb0[n].z, hz0);
-                    hx1 = fma((double)jc[n].y, (double)nb1[n].x, hx1);
-                    hy1 = fma((double)jc[n].y, (double)nb1[n].y, hy1);
-                    hz1 = fma((double)jc[n].y, (double)nb1[n].z, hz1);
-                }
-            }
-            v3 s0, s1;
-            if (KIND == 0) {
-                s0 = heat_bath(h0, beta, rr.x, rr.y);
-                s1 = heat_bath(h1, beta, rr.z, rr.w);
-            } else {
-                s0 = over_relax(old0, h0);
-                s1 = over_relax(old1, h1);
-            }
-            C::store_pair(own, Nh, j0, s0, s1);
-            if (ENERGY) {
-                // each bond has exactly one endpoint on this (odd) parity
-                const v3 v0 = C::stored_value(s0), v1 = C::stored_value(s1);
-                e -= (double)v0.x * hx0 + (double)v0.y * hy0 + (double)v0.z * hz0;
-                e -= (double)v1.x * hx1 + (double)v1.y * hy1 + (double)v1.z * hz1;
-                if (FIELD) {  // field term of the even sites at my two half-indices
-                    const float2 fx = *reinterpret_cast<const float2 *>(Ho + j0);
-                    const float2 fy = *reinterpret_cast<const float2 *>(Ho + Nh + j0);
-                    const float2 fz = *reinterpret_cast<const float2 *>(Ho + 2 * Nh + j0);
-                    e -= (double)fx.x * cur0.x + (double)fy.x * cur0.y + (double)fz.x * cur0.z;
-                    e -= (double)fx.y * cur1.x + (double)fy.y * cur1.y + (double)fz.y * cur1.z;
-                }
-            }
-        }
-        prv0 = cur0; prv1 = cur1;
-        cur0 = nxt0; cur1 = nxt1;
-    }
-
-    if (ENERGY) {
-        red[tid] = e;
-        __syncthreads();
-        if (tid < a.RB) {
-            const int64_t r2 = (int64_t)rblk * a.RB + tid;
-            if (r2 < a.n_rep) {
-                double s = 0.0;
-                for (int k = 0; k < per_rep; ++k) s += red[tid * per_rep + k];
-                a.e_partials[r2 * a.n_ytiles + ytile] = s;
-            }
-        }
-    }
-}
-
 template <int STORE>
-static hipError_t launch_stream_s(const StreamArgs &a, int kind, bool field, bool energy, unsigned threads,
-                                  size_t lds_bytes, hipStream_t s)
-{
-    const bool uni = (a.TY * a.P) % 64 == 0;
-    const dim3 grid((unsigned)a.n_blocks), block(threads);
-#define HSG_L(K, F, E)                                                                                      \
-    do {                                                                                                    \
-        if (uni) hipLaunchKernelGGL((k_half_sweep_stream<STORE, K, F, E, true>), grid, block, lds_bytes, s, a); \
-        else hipLaunchKernelGGL((k_half_sweep_stream<STORE, K, F, E, false>), grid, block, lds_bytes, s, a);   \
-    } while (0)
-    if (kind == 0) {
-        if (field) { if (energy) HSG_L(0, true, true); else HSG_L(0, true, false); }
-        else { if (energy) HSG_L(0, false, true); else HSG_L(0, false, false); }
-    } else {
-        if (field) { if (energy) HSG_L(1, true, true); else HSG_L(1, true, false); }
-        else { if (energy) HSG_L(1, false, true); else HSG_L(1, false, false); }
-    }
-#undef HSG_L
-    return hipGetLastError();
-}
+hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, unsigned threads, size_t lds_bytes,
+                           hipStream_t s);
 
-hipError_t launch_half_sweep_stream(const StreamArgs &a, int storage, int kind, bool field, bool energy,
-                                    hipStream_t s)
+hipError_t launch_half_sweep_stream(const MultiStreamArgs &m, int storage, int kind, bool energy,
+                                    unsigned threads, size_t lds_bytes, hipStream_t s)
 {
-    const int per_rep = a.TY * a.P;
-    const unsigned threads = (unsigned)((a.RB * per_rep + 63) / 64 * 64);
-    if (threads == 0 || threads > (unsigned)kBlock) return hipErrorInvalidValue;
-    const size_t lds_bytes = (size_t)2 * a.RB * 3 * a.rows * a.Lh * sizeof(float);
+    if (threads == 0 || threads > (unsigned)kBlock || m.n_groups < 1 || m.n_groups > kMaxStreamGroups)
+        return hipErrorInvalidValue;
     switch (storage) {
-    case 0: return launch_stream_s<0>(a, kind, field, energy, threads, lds_bytes, s);
-    case 1: return launch_stream_s<1>(a, kind, field, energy, threads, lds_bytes, s);
-    case 2: return launch_stream_s<2>(a, kind, field, energy, threads, lds_bytes, s);
+    case 0: return launch_stream_s<0>(m, kind, energy, threads, lds_bytes, s);
+    case 1: return launch_stream_s<1>(m, kind, energy, threads, lds_bytes, s);
+    case 2: return launch_stream_s<2>(m, kind, energy, threads, lds_bytes, s);
+    case 3: return launch_stream_s<3>(m, kind, energy, threads, lds_bytes, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,7 @@
+// Instantiation of the z-march kernels for spin storage codec 3 (one
+// translation unit per codec so that the library builds in parallel).
+#include "sweep_stream.h"
+
+namespace hsg {
+template hipError_t launch_stream_s<3>(const MultiStreamArgs &, int, bool, unsigned, size_t, hipStream_t);
+}  // namespace hsg

@@ -214,9 +214,11 @@ class Lattice:
         check(lib.hsg_get_energies(self.h, _ptr(E), _stream(self.stream)))
         return E
 
-    def measure_overlap(self):
+    def measure_overlap(self, out=None):
         n = sum(g.n_samples * g.n_temps * 10 for g in self.groups)
-        q = self.torch.empty(n, dtype=self.torch.float64, device=self.device)
+        q = out if out is not None else self.torch.empty(n, dtype=self.torch.float64,
+                                                          device=self.device)
+        assert q.dtype == self.torch.float64 and q.numel() == n and q.is_contiguous()
         check(lib.hsg_measure_overlap(self.h, _ptr(q), _stream(self.stream)))
         return q
 

@@ -42,6 +42,8 @@ def test_query_sizes_formula():
         assert getattr(sz, f) % 256 == 0
     d16, keep16 = _desc([g], storage="f16")
     assert hsg.query_sizes(d16).state_bytes < sz.state_bytes
+    dq, keepq = _desc([g], storage="qangle")
+    assert hsg.query_sizes(dq).state_bytes < hsg.query_sizes(d16).state_bytes
     d0, keep0 = _desc([_group(field=False)])
     assert hsg.query_sizes(d0).field_bytes == 0
 
@@ -81,7 +83,7 @@ def test_bad_mix_and_storage():
     d.storage = 9
     assert _status(d) == hsg.E_INVALID
     d.storage = hsg.STORAGE["qangle"]
-    assert _status(d) == hsg.E_UNSUPPORTED
+    assert _status(d) == hsg.OK
     d, keep = _desc([g])
     d.n_groups = 0
     assert _status(d) == hsg.E_INVALID

@@ -311,7 +311,7 @@ def test_standalone_tempering_matches_oracle(hsg, oracle_lib):
         assert np.array_equal(_maps(lat), o.slot_at_temp)
 
 
-@pytest.mark.parametrize("storage", ["f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f16", "bf16", "qangle"])
 def test_trajectory_compressed_storage(hsg, oracle_lib, storage):
     """Compressed spin storage against the oracle's emulation of the same codec
     (components rounded to nearest even, renormalised when read)."""
@@ -456,18 +456,21 @@ def test_gpu_long_run_statistics_vs_oracle(hsg, oracle_lib):
         assert abs(z_all) < 3.0, (name, z_all)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "qangle"])
 def test_kernel_variants_bit_identical(hsg, storage):
     """The z-march kernel (L divisible by 4) and the gather kernel compute the same
     per-site arithmetic: spins and temperature maps agree bit for bit. Covers a
-    whole plane in LDS with 16 and 7 replicas per work-group (L = 8, 12), one
-    replica per group (L = 24, 144 threads) and row bands with halo rows (L = 36)."""
+    whole plane in LDS with 16, 7 and 4 replicas per work-group (L = 8, 12, 16; at
+    L = 16 every wave holds one replica), one replica per group (L = 24, 144
+    threads) and row bands with halo rows (L = 36), all five lattice sizes in one
+    launch, and +-1 couplings read as sign bits (L = 16)."""
     rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 60))
     groups, uid = [], 0
-    for L, D, T, field in ((8, 2, 5, None), (12, 3, 3, ("gaussian", 0.3)), (24, 1, 2, None),
-                           (36, 1, 2, ("gaussian", 0.1))):
+    for L, D, T, field, cpl in ((8, 2, 5, None, "gaussian"), (12, 3, 3, ("gaussian", 0.3), "gaussian"),
+                                (16, 2, 3, None, "bimodal"), (24, 1, 2, None, "gaussian"),
+                                (36, 1, 2, ("gaussian", 0.1), "gaussian")):
         groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, T),
-                                        field=field, sample_uid_base=uid))
+                                        couplings=cpl, field=field, sample_uid_base=uid))
         uid += D
     seed = inputs.PHILOX_KEY_BASE + 60
     res = []
@@ -504,3 +507,12 @@ def test_graph_replay_matches_direct_launches(hsg, pt_every):
         assert torch.equal(a.get_spins(), b.get_spins()), n
         assert torch.equal(a.get_temp_map(), b.get_temp_map()), n
     assert a.get_state()[0] == b.get_state()[0] == 38
+
+
+def test_bimodal_kind_rejects_other_values(hsg):
+    rng = np.random.default_rng(70)
+    g = inputs.make_group(rng, 8, 1, 2, inputs.geometric_ladder(0.1, 0.3, 2), couplings="bimodal")
+    g.J[0, 1, 5] = 0.5
+    with pytest.raises(hsg.HSGError) as ei:
+        hsg.Lattice([g], seed=1)
+    assert ei.value.status == hsg.E_INVALID

@@ -268,3 +268,42 @@ def test_f16_bf16_rounding_against_numpy(oracle_lib):
     ref = rounded.astype(np.uint32).view(np.float32)
     for v, r in zip(f32, ref):
         assert oracle_lib.round_bf16(float(v)) == float(r), v
+
+
+# ------------------------------------------------------------------ quantised angle
+def test_octahedral_special_points(oracle_lib):
+    """+z maps to the centre, -z to a corner, the equator to the diamond's edge."""
+    assert list(oracle_lib.oct_encode([0, 0, 1])) == [0, 0]
+    assert list(oracle_lib.oct_encode([0, 0, -1])) == [32767, 32767]
+    assert list(oracle_lib.oct_encode([1, 0, 0])) == [32767, 0]
+    assert list(oracle_lib.oct_encode([0, -1, 0])) == [0, -32767]
+    for v in ([0, 0, 1], [0, 0, -1], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0]):
+        assert np.array_equal(oracle_lib.oct_decode(oracle_lib.oct_encode(v)), np.array(v, float))
+
+
+def test_octahedral_roundtrip_error_and_idempotence(oracle_lib):
+    """16-bit octahedral storage: angle error below 1e-4 everywhere on the sphere
+    (cells of side 2/32767, stretched at most ~2x by the map); every stored code
+    decodes to a vector that encodes back to the same code."""
+    rng = np.random.default_rng(21)
+    v = rng.standard_normal((20000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    err = max(np.linalg.norm(oracle_lib.oct_decode(oracle_lib.oct_encode(x)) - x) for x in v)
+    assert err < 1e-4
+    q = rng.integers(-32767, 32768, size=(5000, 2))
+    for qq in q:
+        back = oracle_lib.oct_encode(oracle_lib.oct_decode(qq))
+        assert np.abs(back - qq).max() <= 1, qq
+
+
+def test_octahedral_continuity_across_fold(oracle_lib):
+    """Points on either side of the equator decode close to each other: the
+    lower-half fold matches the upper half along the diamond's edge."""
+    for phi in np.linspace(0, 2 * np.pi, 37):
+        a = np.array([np.cos(phi), np.sin(phi), 1e-7])
+        b = np.array([np.cos(phi), np.sin(phi), -1e-7])
+        a /= np.linalg.norm(a)
+        b /= np.linalg.norm(b)
+        da = oracle_lib.oct_decode(oracle_lib.oct_encode(a))
+        db = oracle_lib.oct_decode(oracle_lib.oct_encode(b))
+        assert np.linalg.norm(da - db) < 2e-4
