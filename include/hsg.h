@@ -179,9 +179,11 @@ hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_cal
  * (1..R_O R_T, 0 = automatic). */
 hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
 
-/* Tuning (results do not depend on it): 0 = automatic; 1 = the gather kernel
- * (any even L); 2 = the z-march kernel (used automatically when L % 4 == 0;
- * other lattice sizes keep the gather kernel). */
+/* Tuning (results do not depend on it): 1 = the gather kernel (any even L);
+ * 2 = the z-march kernel, one launch per half-sweep (L % 4 == 0; other sizes
+ * keep the gather kernel); 3 = the z-march kernel with both half-sweeps of a
+ * pair in one launch where the whole plane fits a work-group (L <= 32), else
+ * as 2; 0 = automatic (currently 3). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
 /* Replay whole sweeps as captured HIP graphs (default on; used when tempering

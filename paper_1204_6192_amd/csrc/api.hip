@@ -218,7 +218,7 @@ struct hsg_lattice {
     uint64_t t = 0, pt_calls = 0;
     char *state = nullptr, *coup = nullptr, *field = nullptr, *scratch = nullptr;
     int32_t slots_per_item = 0;
-    int32_t kernel_variant = 0;  // 0 automatic, 1 gather kernel, 2 z-march
+    int32_t kernel_variant = 0;  // 0 automatic (= 3), 1 gather, 2 z-march, 3 z-march with fused pairs
     bool have_energies = false;
     // hipGraph replay of whole sweeps (tempering every sweep or never)
     bool use_graphs = true;
@@ -285,6 +285,13 @@ bool use_stream(const hsg_lattice *h, const Group &g)
     return g.stream_ok;
 }
 
+// Both half-sweeps of a pair in one z-march: whole planes in LDS (TY = L).
+bool use_pair(const hsg_lattice *h, const Group &g)
+{
+    if (h->kernel_variant == 1 || h->kernel_variant == 2) return false;
+    return g.stream_ok && g.s_TY == g.L;
+}
+
 hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep)
 {
     hsg::StreamArgs a{};
@@ -316,10 +323,14 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     return a;
 }
 
-// One half-sweep of every group: the groups the z-march handles go into as few
-// launches as possible (up to kMaxStreamGroups per launch); the others use the
-// gather kernel one group at a time.
-hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool energy, hipStream_t s)
+// One half-sweep (pair = false, of parity `parity`) or one fused pair of
+// half-sweeps (pair = true) for the groups selected by `pick`: the z-march
+// groups go into as few launches as possible (up to kMaxStreamGroups per
+// launch); the others use the gather kernel one group at a time. The energy of
+// every selected group is reduced afterwards when `energy` is set.
+template <class Pick>
+hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy, bool pair, Pick pick,
+                      hipStream_t s)
 {
     hsg::MultiStreamArgs m{};
     unsigned threads = 0;
@@ -329,7 +340,7 @@ hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool en
         if (m.n_groups == 0) return HSG_OK;
         m.block_start[m.n_groups] = (int32_t)blocks;
         m.n_blocks = (int32_t)blocks;
-        const hipError_t e = hsg::launch_half_sweep_stream(m, h->storage, kind, energy, threads, lds, s);
+        const hipError_t e = hsg::launch_half_sweep_stream(m, h->storage, kind, energy, pair, threads, lds, s);
         m = hsg::MultiStreamArgs{};
         threads = 0;
         lds = 0;
@@ -338,7 +349,8 @@ hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool en
         return HSG_OK;
     };
     for (const Group &g : h->lay.g) {
-        if (use_stream(h, g)) {
+        if (!pick(g)) continue;
+        if (pair || use_stream(h, g)) {
             if (m.n_groups == hsg::kMaxStreamGroups) {
                 hsg_status st = flush();
                 if (st != HSG_OK) return st;
@@ -351,7 +363,7 @@ hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool en
             blocks += nb;
             const unsigned t = (unsigned)((a.RB * a.TY * a.P + 63) / 64 * 64);
             threads = t > threads ? t : threads;
-            const size_t l = (size_t)2 * a.RB * 3 * a.rows * a.Lh * sizeof(float);
+            const size_t l = (size_t)(pair ? 18 : 6) * a.RB * a.rows * a.Lh * sizeof(float);
             lds = l > lds ? l : lds;
         } else {
             const hsg::SweepArgs a = sweep_args(h, g, parity, (uint32_t)rep);
@@ -364,11 +376,40 @@ hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool en
     if (st != HSG_OK) return st;
     if (energy) {
         for (const Group &g : h->lay.g) {
+            if (!pick(g)) continue;
             const int n_pb = use_stream(h, g) ? g.s_ytiles : g.n_pb_sweep;
             const hipError_t e = hsg::launch_reduce_partials(reinterpret_cast<double *>(h->scratch + g.o_scr), n_pb,
                                                              g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
             if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
         }
+    }
+    return HSG_OK;
+}
+
+hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool energy, hipStream_t s)
+{
+    return run_groups(h, kind, parity, rep, energy, false, [](const Group &) { return true; }, s);
+}
+
+// A pair of half-sweeps (parity 0, then parity 1) of every group: fused where
+// the group holds whole planes, as two single passes otherwise. `energy`: the
+// parity-1 pass computes the energies.
+hsg_status run_pair(hsg_lattice *h, int kind, int rep, bool energy, hipStream_t s)
+{
+    bool any_pair = false, any_single = false;
+    for (const Group &g : h->lay.g) {
+        any_pair = any_pair || use_pair(h, g);
+        any_single = any_single || !use_pair(h, g);
+    }
+    if (any_pair) {
+        hsg_status st = run_groups(h, kind, 0, rep, energy, true, [h](const Group &g) { return use_pair(h, g); }, s);
+        if (st != HSG_OK) return st;
+    }
+    if (any_single) {
+        auto single = [h](const Group &g) { return !use_pair(h, g); };
+        hsg_status st = run_groups(h, kind, 0, rep, false, false, single, s);
+        if (st == HSG_OK) st = run_groups(h, kind, 1, rep, energy, false, single, s);
+        if (st != HSG_OK) return st;
     }
     return HSG_OK;
 }
@@ -418,18 +459,14 @@ bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign -
 hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
 {
     const int last_kind = h->n_or > 0 ? 1 : 0;
-    for (int r = 0; r < h->n_hb; ++r)
-        for (int p = 0; p < 2; ++p) {
-            const bool energy = (last_kind == 0) && r == h->n_hb - 1 && p == 1;
-            hsg_status st = run_half_sweep(h, 0, p, r, energy, s);
-            if (st != HSG_OK) return st;
-        }
-    for (int r = 0; r < h->n_or; ++r)
-        for (int p = 0; p < 2; ++p) {
-            const bool energy = r == h->n_or - 1 && p == 1;
-            hsg_status st = run_half_sweep(h, 1, p, 0, energy, s);
-            if (st != HSG_OK) return st;
-        }
+    for (int r = 0; r < h->n_hb; ++r) {
+        hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s);
+        if (st != HSG_OK) return st;
+    }
+    for (int r = 0; r < h->n_or; ++r) {
+        hsg_status st = run_pair(h, 1, 0, r == h->n_or - 1, s);
+        if (st != HSG_OK) return st;
+    }
     if (pt) {
         hsg_status st = run_pt(h, 0u, 1u, s);
         if (st != HSG_OK) return st;
@@ -803,7 +840,7 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item)
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
-    if (variant < 0 || variant > 2) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..2", variant);
+    if (variant < 0 || variant > 3) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..3", variant);
     h->kernel_variant = variant;
     drop_graphs(h);
     return HSG_OK;

@@ -62,7 +62,9 @@ struct MultiStreamArgs {
     int32_t block_start[kMaxStreamGroups + 1];
     StreamArgs g[kMaxStreamGroups];
 };
-hipError_t launch_half_sweep_stream(const MultiStreamArgs &m, int storage, int kind, bool energy,
+// pair = false: one half-sweep of parity a.parity; pair = true: both parities
+// of a pair (every group must hold whole planes, TY = L).
+hipError_t launch_half_sweep_stream(const MultiStreamArgs &m, int storage, int kind, bool energy, bool pair,
                                     unsigned threads, size_t lds_bytes, hipStream_t s);
 
 // *flag = 1 if any of the n values is not exactly +1 or -1, else 0.

@@ -212,6 +212,306 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     }
 }
 
+// ---------------------------------------------------------------- fused pair
+// One site pair's update from its six neighbours: the x and y neighbours of
+// the plane staged in LDS at offset lo (with the thread's own two positions of
+// that plane in c0, c1 and the third x neighbour read from LDS), the z
+// neighbours in registers. Same arithmetic and neighbour order as the
+// single-pass kernels. Returns the energy term of the two sites when ENERGY.
+template <int STORE, int KIND, bool ENERGY>
+__device__ __forceinline__ double update_pair(const float *lds, int lo, int cstride, int Lh, int lrow, int lrm,
+                                              int lrp, int xh0, int o, v3 c0, v3 c1, v3 zp0, v3 zp1, v3 zm0,
+                                              v3 zm1, const float2 (&jc)[6], v3 hs0, v3 hs1, v3 old0, v3 old1,
+                                              u32x4 rr, float beta, v3 &s0, v3 &s1)
+{
+    using C = Codec<STORE>;
+    const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
+    const int we = lo + lrow * Lh + xe;
+    const v3 ex{lds[we], lds[we + cstride], lds[we + 2 * cstride]};
+    const int wm = lo + lrm * Lh + xh0, wp = lo + lrp * Lh + xh0;
+    const float2 ym0 = *reinterpret_cast<const float2 *>(&lds[wm]);
+    const float2 ym1 = *reinterpret_cast<const float2 *>(&lds[wm + cstride]);
+    const float2 ym2 = *reinterpret_cast<const float2 *>(&lds[wm + 2 * cstride]);
+    const float2 yp0 = *reinterpret_cast<const float2 *>(&lds[wp]);
+    const float2 yp1 = *reinterpret_cast<const float2 *>(&lds[wp + cstride]);
+    const float2 yp2 = *reinterpret_cast<const float2 *>(&lds[wp + 2 * cstride]);
+    v3 nb0[6], nb1[6];
+    if (o) {
+        nb0[0] = c1; nb0[1] = c0;
+        nb1[0] = ex; nb1[1] = c1;
+    } else {
+        nb0[0] = c0; nb0[1] = ex;
+        nb1[0] = c1; nb1[1] = c0;
+    }
+    nb0[2] = v3{yp0.x, yp1.x, yp2.x};
+    nb1[2] = v3{yp0.y, yp1.y, yp2.y};
+    nb0[3] = v3{ym0.x, ym1.x, ym2.x};
+    nb1[3] = v3{ym0.y, ym1.y, ym2.y};
+    nb0[4] = zp0; nb1[4] = zp1;
+    nb0[5] = zm0; nb1[5] = zm1;
+    v3 h0 = hs0, h1 = hs1;
+    double hx0 = hs0.x, hy0 = hs0.y, hz0 = hs0.z, hx1 = hs1.x, hy1 = hs1.y, hz1 = hs1.z;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        acc3(h0, jc[n].x, nb0[n]);
+        acc3(h1, jc[n].y, nb1[n]);
+        if (ENERGY) {
+            hx0 = fma((double)jc[n].x, (double)nb0[n].x, hx0);
+            hy0 = fma((double)jc[n].x, (double)nb0[n].y, hy0);
+            hz0 = fma((double)jc[n].x, (double)nb0[n].z, hz0);
+            hx1 = fma((double)jc[n].y, (double)nb1[n].x, hx1);
+            hy1 = fma((double)jc[n].y, (double)nb1[n].y, hy1);
+            hz1 = fma((double)jc[n].y, (double)nb1[n].z, hz1);
+        }
+    }
+    if (KIND == 0) {
+        s0 = heat_bath(h0, beta, rr.x, rr.y);
+        s1 = heat_bath(h1, beta, rr.z, rr.w);
+    } else {
+        s0 = over_relax(old0, h0);
+        s1 = over_relax(old1, h1);
+    }
+    double e = 0.0;
+    if (ENERGY) {
+        const v3 v0 = C::stored_value(s0), v1 = C::stored_value(s1);
+        e -= (double)v0.x * hx0 + (double)v0.y * hy0 + (double)v0.z * hz0;
+        e -= (double)v1.x * hx1 + (double)v1.y * hy1 + (double)v1.z * hz1;
+    }
+    return e;
+}
+
+__device__ __forceinline__ void lds_put_pair(float *lds, int w, int cstride, v3 a, v3 b)
+{
+    *reinterpret_cast<float2 *>(&lds[w]) = make_float2(a.x, b.x);
+    *reinterpret_cast<float2 *>(&lds[w + cstride]) = make_float2(a.y, b.y);
+    *reinterpret_cast<float2 *>(&lds[w + 2 * cstride]) = make_float2(a.z, b.z);
+}
+
+__device__ __forceinline__ void lds_get_pair(const float *lds, int w, int cstride, v3 &a, v3 &b)
+{
+    const float2 x = *reinterpret_cast<const float2 *>(&lds[w]);
+    const float2 y = *reinterpret_cast<const float2 *>(&lds[w + cstride]);
+    const float2 z = *reinterpret_cast<const float2 *>(&lds[w + 2 * cstride]);
+    a = v3{x.x, y.x, z.x};
+    b = v3{x.y, y.y, z.y};
+}
+
+template <bool JB, bool FIELD>
+__device__ __forceinline__ void load_couplings(const float *Jb, const uint8_t *Jbb, const float *Hb, bool jbits,
+                                               bool field, uint32_t Nh, uint32_t j0, float2 (&jc)[6], v3 &hs0,
+                                               v3 &hs1)
+{
+    if (JB && jbits) {
+        const uint32_t bits = *reinterpret_cast<const uint16_t *>(Jbb + j0);
+#pragma unroll
+        for (int n = 0; n < 6; ++n)
+            jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
+    } else {
+#pragma unroll
+        for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
+    }
+    hs0 = v3{0.f, 0.f, 0.f};
+    hs1 = v3{0.f, 0.f, 0.f};
+    if (FIELD && field) {
+        const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
+        const float2 hy = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
+        const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
+        hs0 = v3{hx.x, hy.x, hz.x};
+        hs1 = v3{hx.y, hy.y, hz.y};
+    }
+}
+
+// Both half-sweeps of a pair (parity 0, then parity 1, of the same kind) in one
+// z-march over whole planes (TY = L). At step z, stage A updates the parity-0
+// sites of plane z from the old parity-1 planes z - 1, z, z + 1; stage B then
+// updates the parity-1 sites of plane z - 1 from the new parity-0 planes
+// z - 2, z - 1, z. The periodic seam is closed after the march: the parity-1
+// sites of planes L - 1 and 0 need new parity-0 planes 0 and 1, kept in LDS
+// from the first two steps. The result equals the two single half-sweeps bit
+// for bit; every stored spin is read and written once per pair.
+template <int STORE, int KIND, bool FIELD, bool ENERGY, bool UNI, bool JB>
+__device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, float *lds, double *red)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    const int tid = threadIdx.x;
+    const int per_rep = a.TY * a.P;
+    const int rb = tid / per_rep;
+    const int rem = tid - rb * per_rep;
+    const int ty = rem / a.P, m = rem - ty * a.P;
+    const int64_t r_lane = (int64_t)lb * a.RB + rb;
+    const bool active = rb < a.RB && r_lane < a.n_rep;
+    const int L = a.L, Lh = a.Lh;
+    const uint32_t Nh = (uint32_t)a.Nh;
+    const int y = ty;
+    const int lrm = ty == 0 ? L - 1 : ty - 1;
+    const int lrp = ty == L - 1 ? 0 : ty + 1;
+    const int cstride = L * Lh;
+    const int xh0 = 2 * m;
+    const int rbc = active ? rb : 0;
+    const int base_l = rbc * 18 * cstride;  // [A0 A1 B0 B1 S0 S1] x 3 components
+    const int lA[2] = {base_l, base_l + 3 * cstride};
+    const int lB[2] = {base_l + 6 * cstride, base_l + 9 * cstride};
+    const int lS[2] = {base_l + 12 * cstride, base_l + 15 * cstride};
+    const int lrow_w = ty * Lh + xh0;
+
+    int64_t r = r_lane;
+    if (UNI) r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r_lane >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r_lane & 0xFFFFFFFF));
+    const int64_t d = r / a.slots_per_sample;
+    const int sis = (int)(r - d * a.slots_per_sample);
+    T *sp0 = (T *)a.spins + r * 2 * C::kPlanes * (int64_t)Nh;
+    T *sp1 = sp0 + (int64_t)C::kPlanes * Nh;
+    const bool jbits = JB && a.Jbits != nullptr;
+    const bool field = FIELD && a.Hp != nullptr;
+    const float *J0 = a.J6 + (d * 2 + 0) * 6 * (int64_t)Nh;
+    const float *J1 = a.J6 + (d * 2 + 1) * 6 * (int64_t)Nh;
+    const uint8_t *Jb0 = jbits ? a.Jbits + (d * 2 + 0) * (int64_t)Nh : nullptr;
+    const uint8_t *Jb1 = jbits ? a.Jbits + (d * 2 + 1) * (int64_t)Nh : nullptr;
+    const float *H0 = field ? a.Hp + (d * 2 + 0) * 3 * (int64_t)Nh : nullptr;
+    const float *H1 = field ? a.Hp + (d * 2 + 1) * 3 * (int64_t)Nh : nullptr;
+    float beta = 0.0f;
+    uint32_t c2A = 0, c2B = 0, uid = 0;
+    const uint32_t tsweep = *a.tptr;
+    if (active) {
+        beta = a.beta32[a.temp_of_slot[r]];
+        const int o = sis / a.T, ts = sis - o * a.T;
+        c2A = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12);
+        c2B = c2A | (1u << 16);
+        uid = a.uid_base + (uint32_t)d;
+    }
+
+    v3 o_prv0{}, o_prv1{}, o_cur0{}, o_cur1{}, o_nxt0{}, o_nxt1{};  // old parity 1, planes z-1, z, z+1
+    v3 a_m10{}, a_m11{}, a_m20{}, a_m21{};                          // new parity 0, planes z-1, z-2
+    if (active) {
+        C::load_pair(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), o_prv0, o_prv1);
+        C::load_pair(sp1, Nh, (uint32_t)(y * Lh + xh0), o_cur0, o_cur1);
+    }
+    double e = 0.0;
+
+    for (int z = 0; z < L; ++z) {
+        const int zn = (z + 1 == L) ? 0 : z + 1;
+        const uint32_t jA = (uint32_t)((z * L + y) * Lh + xh0);
+        const uint32_t jB = (uint32_t)(((z - 1) * L + y) * Lh + xh0);  // valid when z >= 1
+        const bool doB = z >= 2;
+        float2 jcA[6], jcB[6];
+        v3 hA0, hA1, hB0, hB1, oldA0{}, oldA1{};
+        u32x4 rrA{0u, 0u, 0u, 0u}, rrB{0u, 0u, 0u, 0u};
+        if (active) {
+            C::load_pair(sp1, Nh, (uint32_t)((zn * L + y) * Lh + xh0), o_nxt0, o_nxt1);
+            load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
+            if (KIND == 1) C::load_pair(sp0, Nh, jA, oldA0, oldA1);
+            if (doB) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
+            lds_put_pair(lds, lA[z & 1] + lrow_w, cstride, o_cur0, o_cur1);
+            if (KIND == 0) {
+                rrA = philox4x32_10(u32x4{jA >> 1, tsweep, c2A, uid}, a.key0, a.key1);
+                if (doB) rrB = philox4x32_10(u32x4{jB >> 1, tsweep, c2B, uid}, a.key0, a.key1);
+            }
+        }
+        __syncthreads();
+        if (active) {
+            v3 sA0, sA1;
+            update_pair<STORE, KIND, false>(lds, lA[z & 1], cstride, Lh, ty, lrm, lrp, xh0, (y + z) & 1, o_cur0,
+                                            o_cur1, o_nxt0, o_nxt1, o_prv0, o_prv1, jcA, hA0, hA1, oldA0, oldA1, rrA,
+                                            beta, sA0, sA1);
+            C::store_pair(sp0, Nh, jA, sA0, sA1);
+            // later stages read the stored (rounded) values, as the single passes do
+            sA0 = C::stored_value(sA0);
+            sA1 = C::stored_value(sA1);
+            lds_put_pair(lds, lB[z & 1] + lrow_w, cstride, sA0, sA1);
+            if (z < 2) lds_put_pair(lds, lS[z] + lrow_w, cstride, sA0, sA1);
+            if (doB) {
+                v3 sB0, sB1;
+                e += update_pair<STORE, KIND, ENERGY>(lds, lB[(z - 1) & 1], cstride, Lh, ty, lrm, lrp, xh0,
+                                                      (y + z) & 1, a_m10, a_m11, sA0, sA1, a_m20, a_m21, jcB, hB0,
+                                                      hB1, o_prv0, o_prv1, rrB, beta, sB0, sB1);
+                C::store_pair(sp1, Nh, jB, sB0, sB1);
+                if (ENERGY && field) {  // field on the parity-0 sites at the same half-indices
+                    const float2 fx = *reinterpret_cast<const float2 *>(H0 + jB);
+                    const float2 fy = *reinterpret_cast<const float2 *>(H0 + Nh + jB);
+                    const float2 fz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + jB);
+                    e -= (double)fx.x * a_m10.x + (double)fy.x * a_m10.y + (double)fz.x * a_m10.z;
+                    e -= (double)fx.y * a_m11.x + (double)fy.y * a_m11.y + (double)fz.y * a_m11.z;
+                }
+            }
+            a_m20 = a_m10; a_m21 = a_m11;
+            a_m10 = sA0; a_m11 = sA1;
+        }
+        o_prv0 = o_cur0; o_prv1 = o_cur1;
+        o_cur0 = o_nxt0; o_cur1 = o_nxt1;
+    }
+
+    // seam: parity-1 sites of planes L - 1 and 0
+    {
+        const uint32_t jL = (uint32_t)(((L - 1) * L + y) * Lh + xh0);
+        const uint32_t j0 = (uint32_t)(y * Lh + xh0);
+        float2 jcL[6], jc0[6];
+        v3 hL0, hL1, hZ0, hZ1;
+        u32x4 rrL{0u, 0u, 0u, 0u}, rr0{0u, 0u, 0u, 0u};
+        if (active) {
+            load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
+            load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
+            if (KIND == 0) {
+                rrL = philox4x32_10(u32x4{jL >> 1, tsweep, c2B, uid}, a.key0, a.key1);
+                rr0 = philox4x32_10(u32x4{j0 >> 1, tsweep, c2B, uid}, a.key0, a.key1);
+            }
+        }
+        __syncthreads();  // the parity-0 plane L - 1 written at the last step
+        if (active) {
+            v3 n00, n01, n10, n11;  // new parity 0, planes 0 and 1, my positions
+            lds_get_pair(lds, lS[0] + lrow_w, cstride, n00, n01);
+            lds_get_pair(lds, lS[1] + lrow_w, cstride, n10, n11);
+            v3 sL0, sL1, sZ0, sZ1;
+            // plane L - 1: parity-0 neighbours L - 2 (a_m2), L - 1 (a_m1, LDS B), 0 (saved)
+            e += update_pair<STORE, KIND, ENERGY>(lds, lB[(L - 1) & 1], cstride, Lh, ty, lrm, lrp, xh0,
+                                                  (y + L) & 1, a_m10, a_m11, n00, n01, a_m20, a_m21, jcL, hL0, hL1,
+                                                  o_prv0, o_prv1, rrL, beta, sL0, sL1);
+            // plane 0: parity-0 neighbours L - 1 (a_m1), 0 (saved, LDS S0), 1 (saved)
+            e += update_pair<STORE, KIND, ENERGY>(lds, lS[0], cstride, Lh, ty, lrm, lrp, xh0, (y + 1) & 1, n00,
+                                                  n01, n10, n11, a_m10, a_m11, jc0, hZ0, hZ1, o_cur0, o_cur1, rr0,
+                                                  beta, sZ0, sZ1);
+            C::store_pair(sp1, Nh, jL, sL0, sL1);
+            C::store_pair(sp1, Nh, j0, sZ0, sZ1);
+            if (ENERGY && field) {
+                const float2 fx = *reinterpret_cast<const float2 *>(H0 + jL);
+                const float2 fy = *reinterpret_cast<const float2 *>(H0 + Nh + jL);
+                const float2 fz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + jL);
+                e -= (double)fx.x * a_m10.x + (double)fy.x * a_m10.y + (double)fz.x * a_m10.z;
+                e -= (double)fx.y * a_m11.x + (double)fy.y * a_m11.y + (double)fz.y * a_m11.z;
+                const float2 gx = *reinterpret_cast<const float2 *>(H0 + j0);
+                const float2 gy = *reinterpret_cast<const float2 *>(H0 + Nh + j0);
+                const float2 gz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + j0);
+                e -= (double)gx.x * n00.x + (double)gy.x * n00.y + (double)gz.x * n00.z;
+                e -= (double)gx.y * n01.x + (double)gy.y * n01.y + (double)gz.y * n01.z;
+            }
+        }
+    }
+
+    if (ENERGY) {
+        red[tid] = e;
+        __syncthreads();
+        if (tid < a.RB) {
+            const int64_t r2 = (int64_t)lb * a.RB + tid;
+            if (r2 < a.n_rep) {
+                double sum = 0.0;
+                for (int k = 0; k < per_rep; ++k) sum += red[tid * per_rep + k];
+                a.e_partials[r2 * a.n_ytiles] = sum;
+            }
+        }
+    }
+}
+
+template <int STORE, int KIND, bool ENERGY, bool FIELD, bool UNI, bool JB>
+__global__ __launch_bounds__(kBlock) void k_pair_stream(MultiStreamArgs m)
+{
+    extern __shared__ float lds[];  // [RB][A0 A1 B0 B1 S0 S1][3][L][L/2] floats of the group
+    __shared__ double red[kBlock];
+    const int b = xcd_remap((int)blockIdx.x, m.n_blocks);
+    int k = 0;
+    while (k + 1 < m.n_groups && b >= m.block_start[k + 1]) ++k;
+    pair_body<STORE, KIND, FIELD, ENERGY, UNI, JB>(m.g[k], b - m.block_start[k], lds, red);
+}
+
 // One launch for every group of the table.
 template <int STORE, int KIND, bool ENERGY, bool FIELD, bool UNI, bool JB>
 __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(MultiStreamArgs m)
@@ -225,10 +525,14 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(MultiStreamArgs m)
 }
 
 template <int STORE, int KIND, bool ENERGY>
-static hipError_t launch_stream_e(const MultiStreamArgs &m, bool field, bool uni, bool jb, dim3 grid, dim3 block,
-                                  size_t lds_bytes, hipStream_t s)
+static hipError_t launch_stream_e(const MultiStreamArgs &m, bool pair, bool field, bool uni, bool jb, dim3 grid,
+                                  dim3 block, size_t lds_bytes, hipStream_t s)
 {
-#define HSG_L(F, U, J) hipLaunchKernelGGL((k_half_sweep_stream<STORE, KIND, ENERGY, F, U, J>), grid, block, lds_bytes, s, m)
+#define HSG_L(F, U, J)                                                                                        \
+    do {                                                                                                      \
+        if (pair) hipLaunchKernelGGL((k_pair_stream<STORE, KIND, ENERGY, F, U, J>), grid, block, lds_bytes, s, m); \
+        else hipLaunchKernelGGL((k_half_sweep_stream<STORE, KIND, ENERGY, F, U, J>), grid, block, lds_bytes, s, m); \
+    } while (0)
     if (field) {
         if (uni) { if (jb) HSG_L(true, true, true); else HSG_L(true, true, false); }
         else { if (jb) HSG_L(true, false, true); else HSG_L(true, false, false); }
@@ -241,8 +545,8 @@ static hipError_t launch_stream_e(const MultiStreamArgs &m, bool field, bool uni
 }
 
 template <int STORE>
-hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, unsigned threads,
-                                  size_t lds_bytes, hipStream_t s)
+hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, bool pair, unsigned threads,
+                           size_t lds_bytes, hipStream_t s)
 {
     bool field = false, uni = true, jb = false;
     for (int k = 0; k < m.n_groups; ++k) {
@@ -252,11 +556,11 @@ hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, unsi
     }
     const dim3 grid((unsigned)m.n_blocks), block(threads);
     if (kind == 0) {
-        if (energy) return launch_stream_e<STORE, 0, true>(m, field, uni, jb, grid, block, lds_bytes, s);
-        return launch_stream_e<STORE, 0, false>(m, field, uni, jb, grid, block, lds_bytes, s);
+        if (energy) return launch_stream_e<STORE, 0, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+        return launch_stream_e<STORE, 0, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
     }
-    if (energy) return launch_stream_e<STORE, 1, true>(m, field, uni, jb, grid, block, lds_bytes, s);
-    return launch_stream_e<STORE, 1, false>(m, field, uni, jb, grid, block, lds_bytes, s);
+    if (energy) return launch_stream_e<STORE, 1, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+    return launch_stream_e<STORE, 1, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
 }
 
 }  // namespace hsg

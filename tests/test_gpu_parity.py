@@ -458,8 +458,10 @@ def test_gpu_long_run_statistics_vs_oracle(hsg, oracle_lib):
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "qangle"])
 def test_kernel_variants_bit_identical(hsg, storage):
-    """The z-march kernel (L divisible by 4) and the gather kernel compute the same
-    per-site arithmetic: spins and temperature maps agree bit for bit. Covers a
+    """The gather kernel, the z-march kernel (L divisible by 4) and the z-march with
+    both half-sweeps of a pair fused (whole planes, L <= 32) compute the same
+    per-site arithmetic: spins and temperature maps agree bit for bit. L = 36
+    cannot fuse and runs as two single passes next to the fused groups. Covers a
     whole plane in LDS with 16, 7 and 4 replicas per work-group (L = 8, 12, 16; at
     L = 16 every wave holds one replica), one replica per group (L = 24, 144
     threads) and row bands with halo rows (L = 36), all five lattice sizes in one
@@ -474,16 +476,17 @@ def test_kernel_variants_bit_identical(hsg, storage):
         uid += D
     seed = inputs.PHILOX_KEY_BASE + 60
     res = []
-    for variant in (1, 2):
+    for variant in (1, 2, 3):
         lat = _lat(hsg, groups, seed, storage=storage)
         lat.set_kernel(variant)
         lat.sweep(3)
         res.append((lat.get_spins().cpu(), lat.get_temp_map().cpu(), lat.get_energies().cpu(),
                     lat.measure_energy().cpu()))
-    assert torch.equal(res[0][0], res[1][0])
-    assert torch.equal(res[0][1], res[1][1])
-    assert torch.allclose(res[0][2], res[1][2], rtol=1e-12, atol=1e-9)
-    assert torch.equal(res[0][3], res[1][3])  # same spins, same recomputation
+    for other in res[1:]:
+        assert torch.equal(res[0][0], other[0])
+        assert torch.equal(res[0][1], other[1])
+        assert torch.allclose(res[0][2], other[2], rtol=1e-12, atol=1e-9)
+        assert torch.equal(res[0][3], other[3])  # same spins, same recomputation
 
 
 @pytest.mark.parametrize("pt_every", [1, 0, 3])
