@@ -135,6 +135,11 @@ hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream);
 hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t rep,
                           hsg_stream_t stream);
 
+/* Both half-sweeps of a pair (parity 0, then parity 1) of every replica, as
+ * inside hsg_sweep: one fused launch where the kernel variant allows it,
+ * else two passes. Uses the current sweep counter and does not advance it. */
+hsg_status hsg_pair_sweep(hsg_lattice *h, int32_t kind, int32_t rep, hsg_stream_t stream);
+
 /* One standalone tempering pass over every ladder using the energies of the
  * last sweep (or of the last hsg_measure_energy); advances the standalone-call
  * counter. */
@@ -207,6 +212,11 @@ const char *hsg_build_id(void);
  * (device arrays). Exposes the device generator for a bit-exact comparison. */
 hsg_status hsg_debug_philox(const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out,
                             int64_t n, hsg_stream_t stream);
+
+/* Test hook: the hardware transcendentals the kernels use, for x = d_x[i]:
+ * d_out[6 i ..] = sin(2 pi x), cos(2 pi x), ln x, e^-x, 1/x, 1/sqrt(x)
+ * (device arrays), so that their accuracy can be checked against float64. */
+hsg_status hsg_debug_hw_math(const float *d_x, float *d_out, int64_t n, hsg_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,7 @@ struct Group {
     uint64_t o_scr;                              // scratch
     int32_t n_pb_sweep;                          // blocks of 256 site pairs per replica
     int32_t n_pb_site;                           // blocks of 256 sites per replica half
+    int32_t q_pb, q_chunk;                       // overlap: work-groups per rung pair, sites each
     // z-march geometry (L divisible by 4), see hsg::StreamArgs
     bool stream_ok;
     int32_t s_TY, s_RB, s_rows, s_ytiles;
@@ -163,6 +164,15 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         const int64_t pairs = g.Nh / 2;
         g.n_pb_sweep = (int32_t)((pairs + hsg::kBlock - 1) / hsg::kBlock);
         g.n_pb_site = (int32_t)((g.Nh + hsg::kBlock - 1) / hsg::kBlock);
+        {  // about 4096 work-groups in all for the overlap, each over whole blocks of 256 sites
+            const int64_t pairs = (int64_t)g.D * g.T;
+            int64_t qpb = (4096 + pairs - 1) / pairs;
+            if (qpb > g.n_pb_site) qpb = g.n_pb_site;
+            if (qpb < 1) qpb = 1;
+            const int64_t per = (g.Nh + qpb - 1) / qpb;
+            g.q_chunk = (int32_t)((per + hsg::kBlock - 1) / hsg::kBlock * hsg::kBlock);
+            g.q_pb = (int32_t)((g.Nh + g.q_chunk - 1) / g.q_chunk);
+        }
         stream_geometry(g);
         // state
         g.o_spins = st;
@@ -191,7 +201,7 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         g.o_scr = sc;
         const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > g.s_ytiles ? g.n_pb_sweep : g.s_ytiles) * 8;
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
-        const uint64_t q_full = (uint64_t)g.D * g.T * g.n_pb_site * 9 * 8;
+        const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
         if (q_full > need) need = q_full;
         sc = align_up(sc + need);
@@ -670,6 +680,14 @@ hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t 
     return run_half_sweep(h, kind, parity, rep, false, S(stream));
 }
 
+hsg_status hsg_pair_sweep(hsg_lattice *h, int32_t kind, int32_t rep, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (kind != 0 && kind != 1) return fail(HSG_E_INVALID, "kind = %d, need 0 (HB) or 1 (OR)", kind);
+    if (rep < 0 || rep > 15) return fail(HSG_E_SIZE, "rep = %d, need 0..15", rep);
+    return run_pair(h, kind, rep, false, S(stream));
+}
+
 hsg_status hsg_pt_exchange(hsg_lattice *h, hsg_stream_t stream)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
@@ -733,7 +751,8 @@ hsg_status hsg_measure_overlap(hsg_lattice *h, double *d_q, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = g.n_pb_site;
+        a.n_pb = g.q_pb;
+        a.chunk = g.q_chunk;
         const hipError_t e = hsg::launch_overlap(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_overlap");
         off += (int64_t)g.D * g.T * 10;
@@ -877,6 +896,14 @@ hsg_status hsg_debug_philox(const uint32_t *d_ctr, const uint32_t *d_key, uint32
         return fail(HSG_E_INVALID, "bad philox arguments");
     const hipError_t e = hsg::launch_philox(d_ctr, d_key, d_out, n, S(stream));
     if (e != hipSuccess) return hip_fail(e, "philox");
+    return HSG_OK;
+}
+
+hsg_status hsg_debug_hw_math(const float *d_x, float *d_out, int64_t n, hsg_stream_t stream)
+{
+    if (n < 0 || (n > 0 && (d_x == nullptr || d_out == nullptr))) return fail(HSG_E_INVALID, "bad arguments");
+    const hipError_t e = hsg::launch_hw_math(d_x, d_out, n, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "hw_math");
     return HSG_OK;
 }
 

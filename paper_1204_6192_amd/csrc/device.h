@@ -58,6 +58,21 @@ __device__ __forceinline__ v3 scale3(v3 a, float f) { return v3{a.x * f, a.y * f
 
 __device__ __forceinline__ v3 normalise3(v3 a) { return scale3(a, 1.0f / sqrtf(dot3(a, a))); }
 
+// Renormalisation on load of a compressed spin (|a| within ~1e-2 of 1): the
+// hardware reciprocal square root (1 ulp) is ample next to the storage's own
+// rounding (2^-11 or coarser).
+__device__ __forceinline__ v3 normalise_rsq(v3 a) { return scale3(a, __builtin_amdgcn_rsqf(dot3(a, a))); }
+
+// Hardware transcendentals (one instruction each, about 1 ulp): log2, 2^x,
+// sin(2 pi x) and cos(2 pi x) for x in revolutions, reciprocal and reciprocal
+// square root. Their accuracy on this device is checked by a GPU test.
+__device__ __forceinline__ float hw_log(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945309f; }
+__device__ __forceinline__ float hw_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.442695040888963407f); }
+__device__ __forceinline__ float hw_sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float hw_cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 // Error-free sum a + b = s + e (Knuth's TwoSum).
 __device__ __forceinline__ float two_sum(float a, float b, float &e)
 {
@@ -208,7 +223,7 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
     static constexpr int kPlanes = 3;
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
-        return normalise3(v3{__half2float(p[j]), __half2float(p[cs + j]), __half2float(p[2 * cs + j])});
+        return normalise_rsq(v3{__half2float(p[j]), __half2float(p[cs + j]), __half2float(p[2 * cs + j])});
     }
     __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
     {
@@ -218,16 +233,16 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
     }
     __device__ static __forceinline__ v3 stored_value(v3 s)
     {
-        return normalise3(v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
-                             __half2float(__float2half_rn(s.z))});
+        return normalise_rsq(v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
+                                __half2float(__float2half_rn(s.z))});
     }
     __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
         const __half2 x = *reinterpret_cast<const __half2 *>(p + j0);
         const __half2 y = *reinterpret_cast<const __half2 *>(p + cs + j0);
         const __half2 z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
-        a = normalise3(v3{__low2float(x), __low2float(y), __low2float(z)});
-        b = normalise3(v3{__high2float(x), __high2float(y), __high2float(z)});
+        a = normalise_rsq(v3{__low2float(x), __low2float(y), __low2float(z)});
+        b = normalise_rsq(v3{__high2float(x), __high2float(y), __high2float(z)});
     }
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
@@ -251,7 +266,7 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
     static constexpr int kPlanes = 3;
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
-        return normalise3(v3{bf16_to_f32(p[j]), bf16_to_f32(p[cs + j]), bf16_to_f32(p[2 * cs + j])});
+        return normalise_rsq(v3{bf16_to_f32(p[j]), bf16_to_f32(p[cs + j]), bf16_to_f32(p[2 * cs + j])});
     }
     __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
     {
@@ -261,17 +276,17 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
     }
     __device__ static __forceinline__ v3 stored_value(v3 s)
     {
-        return normalise3(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
-                             bf16_to_f32(f32_to_bf16_rne(s.z))});
+        return normalise_rsq(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
+                                bf16_to_f32(f32_to_bf16_rne(s.z))});
     }
     __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
         const uint32_t x = *reinterpret_cast<const uint32_t *>(p + j0);
         const uint32_t y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
         const uint32_t z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
-        a = normalise3(v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)});
-        b = normalise3(v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u),
-                          __uint_as_float(z & 0xFFFF0000u)});
+        a = normalise_rsq(v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)});
+        b = normalise_rsq(v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u),
+                             __uint_as_float(z & 0xFFFF0000u)});
     }
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
@@ -290,8 +305,8 @@ __device__ __forceinline__ float sgn_nz(float a) { return a >= 0.0f ? 1.0f : -1.
 
 __device__ __forceinline__ uint32_t oct_encode(v3 v)
 {
-    const float l1 = fabsf(v.x) + fabsf(v.y) + fabsf(v.z);
-    float px = v.x / l1, py = v.y / l1;
+    const float il1 = hw_rcp(fabsf(v.x) + fabsf(v.y) + fabsf(v.z));
+    float px = v.x * il1, py = v.y * il1;
     if (v.z < 0.0f) {
         const float fx = (1.0f - fabsf(py)) * sgn_nz(px);
         const float fy = (1.0f - fabsf(px)) * sgn_nz(py);
@@ -306,8 +321,8 @@ __device__ __forceinline__ uint32_t oct_encode(v3 v)
 
 __device__ __forceinline__ v3 oct_decode(uint32_t w)
 {
-    float fx = (float)(int16_t)(w & 0xFFFFu) / 32767.0f;
-    float fy = (float)(int16_t)(w >> 16) / 32767.0f;
+    float fx = (float)(int16_t)(w & 0xFFFFu) * (1.0f / 32767.0f);
+    float fy = (float)(int16_t)(w >> 16) * (1.0f / 32767.0f);
     const float vz = 1.0f - fabsf(fx) - fabsf(fy);
     if (vz < 0.0f) {
         const float ax = (1.0f - fabsf(fy)) * sgn_nz(fx);
@@ -315,7 +330,7 @@ __device__ __forceinline__ v3 oct_decode(uint32_t w)
         fx = ax;
         fy = ay;
     }
-    return normalise3(v3{fx, fy, vz});
+    return normalise_rsq(v3{fx, fy, vz});
 }
 
 template <>

@@ -116,14 +116,15 @@ struct EnergyArgs {
 };
 hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s);
 
-// Overlap of copies 0 and 1 at every rung: partials [d][k][n_pb][9] -> q [d][k][10].
+// Overlap of copies 0 and 1 at every rung: partials [d][k][n_pb][9] -> q [d][k][10];
+// work-group pb covers the half-indices [pb * chunk, (pb + 1) * chunk).
 struct OverlapArgs {
     const void *spins;
     const int32_t *slot_at_temp;
     double *partials;
     double *q;
     int64_t Nh;
-    int32_t D, O, T, n_pb;
+    int32_t D, O, T, n_pb, chunk;
 };
 hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s);
 
@@ -136,5 +137,6 @@ hipError_t launch_advance(uint32_t *tptr, hipStream_t s);
 hipError_t launch_set_u32(uint32_t *ptr, uint32_t value, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
                          hipStream_t s);
+hipError_t launch_hw_math(const float *x, float *out, int64_t n, hipStream_t s);
 
 }  // namespace hsg

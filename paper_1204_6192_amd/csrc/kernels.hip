@@ -454,23 +454,26 @@ hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- overlap
+// Work-group (d * T + k, pb) sums s^mu(copy 0) s^nu(copy 1) over the sites
+// [pb * chunk, (pb + 1) * chunk) of both parities of rung k; one wave per
+// (d, k) then adds the n_pb partials in a fixed order and forms q^2.
 template <int STORE>
 __global__ __launch_bounds__(kBlock) void k_overlap(OverlapArgs a)
 {
     using C = Codec<STORE>;
     using T = typename C::T;
-    __shared__ double red[4];
+    __shared__ double red[4][9];
     const int64_t dk = blockIdx.x / a.n_pb;  // d * T + k
     const int pb = (int)(blockIdx.x - dk * a.n_pb);
     const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
     const int64_t Nh = a.Nh;
-    const int64_t j = (int64_t)pb * kBlock + threadIdx.x;
     const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
     const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
     const T *A = (const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh;
     const T *B = (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-    if (j < Nh) {
+    const int64_t j_end = ((int64_t)(pb + 1) * a.chunk < Nh) ? (int64_t)(pb + 1) * a.chunk : Nh;
+    for (int64_t j = (int64_t)pb * a.chunk + threadIdx.x; j < j_end; j += kBlock) {
         for (int p = 0; p < 2; ++p) {
             const v3 x = C::load(A + (int64_t)p * C::kPlanes * Nh, Nh, j);
             const v3 y = C::load(B + (int64_t)p * C::kPlanes * Nh, Nh, j);
@@ -479,26 +482,31 @@ __global__ __launch_bounds__(kBlock) void k_overlap(OverlapArgs a)
                 for (int n = 0; n < 3; ++n) acc[3 * m + n] += xa[m] * ya[n];
         }
     }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int m = 0; m < 9; ++m) {
-        const double tot = block_sum(acc[m], red);
-        if (threadIdx.x == 0) a.partials[(dk * a.n_pb + pb) * 9 + m] = tot;
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) red[wave][m] = v;
     }
+    __syncthreads();
+    if (threadIdx.x < 9)
+        a.partials[(dk * a.n_pb + pb) * 9 + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
 __global__ __launch_bounds__(64) void k_overlap_finish(OverlapArgs a)
 {
-    const int64_t dk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (dk >= (int64_t)a.D * a.T) return;
+    const int64_t dk = blockIdx.x;
+    const int lane = threadIdx.x;
     const double invN = 1.0 / (double)(2 * a.Nh);
     double q2 = 0.0;
     for (int m = 0; m < 9; ++m) {
         double v = 0.0;
-        for (int pb = 0; pb < a.n_pb; ++pb) v += a.partials[(dk * a.n_pb + pb) * 9 + m];
-        v *= invN;
-        a.q[dk * 10 + m] = v;
+        for (int pb = lane; pb < a.n_pb; pb += 64) v += a.partials[(dk * a.n_pb + pb) * 9 + m];
+        v = wave_sum(v) * invN;
+        if (lane == 0) a.q[dk * 10 + m] = v;
         q2 += v * v;
     }
-    a.q[dk * 10 + 9] = q2;
+    if (lane == 0) a.q[dk * 10 + 9] = q2;
 }
 
 hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
@@ -514,8 +522,7 @@ hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t n = (int64_t)a.D * a.T;
-    hipLaunchKernelGGL(k_overlap_finish, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_overlap_finish, dim3((unsigned)((int64_t)a.D * a.T)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -588,6 +595,27 @@ __global__ __launch_bounds__(256) void k_philox(const uint32_t *ctr, const uint3
     out[4 * g + 1] = r.y;
     out[4 * g + 2] = r.z;
     out[4 * g + 3] = r.w;
+}
+
+// out[6 i + k] = hw_sin_rev, hw_cos_rev, hw_log, hw_exp(-x), hw_rcp, hw_rsq of x[i].
+__global__ __launch_bounds__(256) void k_hw_math(const float *x, float *out, int64_t n)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    const float v = x[g];
+    out[6 * g + 0] = hw_sin_rev(v);
+    out[6 * g + 1] = hw_cos_rev(v);
+    out[6 * g + 2] = hw_log(v);
+    out[6 * g + 3] = hw_exp(-v);
+    out[6 * g + 4] = hw_rcp(v);
+    out[6 * g + 5] = hw_rsq(v);
+}
+
+hipError_t launch_hw_math(const float *x, float *out, int64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hw_math, dim3(blocks_for(n)), dim3(256), 0, s, x, out, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n, hipStream_t s)

@@ -76,6 +76,7 @@ _SIG = {
     "hsg_init_lattice": [C.POINTER(Desc), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.POINTER(_vp)],
     "hsg_sweep": [_vp, _i32, _vp],
     "hsg_half_sweep": [_vp, _i32, _i32, _i32, _vp],
+    "hsg_pair_sweep": [_vp, _i32, _i32, _vp],
     "hsg_pt_exchange": [_vp, _vp],
     "hsg_measure_energy": [_vp, _vp, _vp],
     "hsg_get_energies": [_vp, _vp, _vp],
@@ -92,6 +93,7 @@ _SIG = {
     "hsg_set_graphs": [_vp, _i32],
     "hsg_sync": [_vp, _vp],
     "hsg_debug_philox": [_vp, _vp, _vp, _i64, _vp],
+    "hsg_debug_hw_math": [_vp, _vp, _i64, _vp],
 }
 for _name, _args in _SIG.items():
     _f = getattr(lib, _name)
@@ -201,6 +203,9 @@ class Lattice:
     def half_sweep(self, kind: int, parity: int, rep: int = 0) -> None:
         check(lib.hsg_half_sweep(self.h, int(kind), int(parity), int(rep), _stream(self.stream)))
 
+    def pair_sweep(self, kind: int, rep: int = 0) -> None:
+        check(lib.hsg_pair_sweep(self.h, int(kind), int(rep), _stream(self.stream)))
+
     def pt_exchange(self) -> None:
         check(lib.hsg_pt_exchange(self.h, _stream(self.stream)))
 
@@ -290,3 +295,14 @@ def debug_philox(ctr, key):
     check(lib.hsg_debug_philox(_ptr(dc), _ptr(dk), _ptr(out), n, _stream(None)))
     torch.cuda.synchronize()
     return out.cpu().numpy().view(np.uint32)
+
+
+def debug_hw_math(x):
+    """Hardware sin(2 pi x), cos(2 pi x), ln x, e^-x, 1/x, 1/sqrt(x) on the device."""
+    import torch
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    dx = torch.from_numpy(x).cuda()
+    out = torch.empty((x.size, 6), dtype=torch.float32, device="cuda")
+    check(lib.hsg_debug_hw_math(_ptr(dx), _ptr(out), x.size, _stream(None)))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()

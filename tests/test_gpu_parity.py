@@ -519,3 +519,31 @@ def test_bimodal_kind_rejects_other_values(hsg):
     with pytest.raises(hsg.HSGError) as ei:
         hsg.Lattice([g], seed=1)
     assert ei.value.status == hsg.E_INVALID
+
+
+def test_hardware_transcendentals_accuracy(hsg):
+    """The one-instruction transcendentals the heat bath and the codecs use,
+    against float64 on their input ranges: sin/cos of 2 pi u for u on the
+    2^-24 grid of the uniforms, ln on (2^-24, 1], e^-x for the heat-bath
+    exponent, reciprocal and reciprocal square root near the values they see."""
+    rng = np.random.default_rng(80)
+    u = ((rng.integers(0, 2 ** 24, 200000) + 1) * 2.0 ** -24).astype(np.float32)
+    r = hsg.debug_hw_math(u)
+    u64 = u.astype(np.float64)
+    err_sin = np.abs(r[:, 0] - np.sin(2 * np.pi * u64)).max()
+    err_cos = np.abs(r[:, 1] - np.cos(2 * np.pi * u64)).max()
+    err_log = np.abs(r[:, 2] - np.log(u64)).max()
+    x = rng.uniform(0, 80, 200000).astype(np.float32)
+    e = hsg.debug_hw_math(x)[:, 3].astype(np.float64)
+    ref = np.exp(-x.astype(np.float64))
+    err_exp = (np.abs(e - ref) / np.maximum(ref, 1e-30))[ref > 1e-30].max()
+    y = rng.uniform(0.25, 4.0, 200000).astype(np.float32)
+    ry = hsg.debug_hw_math(y).astype(np.float64)
+    err_rcp = (np.abs(ry[:, 4] * y - 1.0)).max()
+    err_rsq = (np.abs(ry[:, 5] * np.sqrt(y.astype(np.float64)) - 1.0)).max()
+    print(f"max abs error sin {err_sin:.2e} cos {err_cos:.2e} log {err_log:.2e}; max rel error "
+          f"exp {err_exp:.2e} rcp {err_rcp:.2e} rsq {err_rsq:.2e}", flush=True)
+    assert err_sin < 1e-6 and err_cos < 1e-6
+    assert err_log < 2e-6
+    assert err_exp < 1e-5
+    assert err_rcp < 3e-7 and err_rsq < 3e-7
