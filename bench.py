@@ -8,9 +8,10 @@ Default workload: L = 32, 64 disorder samples x 2 copies x 32 temperatures
 4096 replicas, 134,217,728 spins. Inputs are seeded and synthetic.
 
 Prints one JSON line: ns per spin update (t / (steps x 5 x spins), the paper's
-per-update time), the roofline of the dominant kernel (the over-relaxation
-half-sweep, HBM-bound) from HIP events on the library's stream, and the float64
-oracle timed on a bounded sample of the same workload on host cores.
+per-update time), the roofline of the dominant kernel (the over-relaxation pair,
+HBM-bound; one fused launch for lattices up to L = 32) from HIP events on the
+library's stream, and the float64 oracle timed on a bounded sample of the same
+workload on host cores.
 """
 
 import argparse
@@ -75,6 +76,27 @@ def time_kernel(lat, kind, n, torch):
     stop.record(stream)
     stop.synchronize()
     return start.elapsed_time(stop) / n * 1e-3  # seconds per pair
+
+
+def measured_traffic(build_id, workload):
+    """HBM bytes per launch of the dominant kernel from the hardware counters, as
+    recorded in a profile summary under profiles/ by a line
+
+        traffic: build_id=<id> workload=<name> bytes_per_launch=<B> ...
+
+    (FETCH_SIZE and WRITE_SIZE of the same build and workload, each scaled by
+    what it reads for a plain copy of known size). None when no summary was
+    taken with this build, since counters of other code say nothing about it."""
+    import glob
+    for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(fn) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(tok.split("=", 1) for tok in line[len("traffic:"):].split() if "=" in tok)
+                if kv.get("build_id") == build_id and kv.get("workload") == workload:
+                    return float(kv["bytes_per_launch"]), os.path.relpath(fn, ROOT)
+    return None, None
 
 
 def cpu_baseline(inst, sweeps, log_fn):
@@ -175,11 +197,16 @@ def main():
     t_hb = time_kernel(lat, 0, max(4, args.kernel_launches // 4), torch)
     b_or = algorithmic_bytes(inst.groups, inst.storage, 1)
     b_hb = algorithmic_bytes(inst.groups, inst.storage, 0)
+    lat.set_math(1)
+    t_hb_hw = time_kernel(lat, 0, max(4, args.kernel_launches // 4), torch)
+    lat.set_math(0)
     gbs_or = b_or / t_or / 1e9
+    log(f"HB pair with hardware transcendentals: {t_hb_hw * 1e6:.1f} us")
     log(f"OR pair: {t_or * 1e6:.1f} us, {b_or / 1e9:.3f} GB -> {gbs_or:.0f} GB/s; "
         f"HB pair: {t_hb * 1e6:.1f} us, {b_hb / 1e9:.3f} GB -> {b_hb / t_hb / 1e9:.0f} GB/s")
     eff_gbs = (inst.n_hb * b_hb + inst.n_or * b_or) / (dt / args.steps) / 1e9
 
+    traffic, traffic_src = measured_traffic(hsg.build_id(), args.config)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, args.cpu_sweeps, log)
@@ -207,9 +234,13 @@ def main():
                                 if all(fused(g) for g in inst.groups) else
                                 "over-relaxation pair (z-march launches)"),
                      "achieved": gbs_or, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": gbs_or / PEAK_HBM_GBS, "traffic": None,
+                     "frac": gbs_or / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "traffic_vs_algorithmic": None if traffic is None else traffic / b_or,
+                     "traffic_source": traffic_src,
                      "launch_us": t_or * 1e6, "bytes_per_launch": b_or,
-                     "hb_pair_us": t_hb * 1e6, "hb_gbs": b_hb / t_hb / 1e9},
+                     "hb_pair_us": t_hb * 1e6, "hb_gbs": b_hb / t_hb / 1e9,
+                     "hb_pair_us_hw_math": t_hb_hw * 1e6},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

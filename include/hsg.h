@@ -191,6 +191,30 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
  * as 2; 0 = automatic (currently 3). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
+/* Arithmetic of the heat-bath draw (Eq. (2)). 0 (default): correctly rounded
+ * square root and division, library sincospi, log, exp, log1p and expm1.
+ * 1: the field's length, direction and the divisions from the hardware
+ * reciprocal square root and reciprocal (1 ulp), the azimuth from the hardware
+ * sin/cos (absolute error about 1.2e-7); log, exp, log1p and expm1 unchanged.
+ * Mode 1 changes the trajectory at the float32 rounding level and is the
+ * faster choice; over-relaxation is the same in both. */
+hsg_status hsg_set_math(hsg_lattice *h, int32_t mode);
+
+/* Autotuner of the launch configuration (the batching row of the method: tile
+ * shape and fusion per lattice size). Times n_sweeps (1..1000) whole sweeps of
+ * each distinct kernel variant of hsg_set_kernel (and, where lattices use the
+ * gather kernel, 2, 4, 8 or 16 slots per work item) with HIP events after one
+ * warm-up sweep each, and keeps the fastest. Every variant computes the same
+ * bits, so the trial sweeps are ordinary sweeps of the chain: with
+ * d_backup == NULL the chain advances by them (n_sweeps + 1 per candidate);
+ * with d_backup (device, state_bytes of hsg_query_sizes, 256-byte aligned,
+ * caller-owned) the state is saved first and restored afterwards, so the chain
+ * is left exactly as it was. Synchronises the stream. On success the chosen
+ * variant and slots per item (0 = automatic) are written to the non-NULL
+ * outputs; on error the previous tuning is kept. */
+hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_t *variant,
+                        int32_t *slots_per_item, hsg_stream_t stream);
+
 /* Replay whole sweeps as captured HIP graphs (default on; used when tempering
  * runs every sweep or never). Results do not depend on it. */
 hsg_status hsg_set_graphs(hsg_lattice *h, int32_t enable);

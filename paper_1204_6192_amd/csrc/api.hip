@@ -6,6 +6,7 @@
 // allocated here; every buffer belongs to the caller.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -73,7 +74,7 @@ struct Group {
     int32_t q_pb, q_chunk;                       // overlap: work-groups per rung pair, sites each
     // z-march geometry (L divisible by 4), see hsg::StreamArgs
     bool stream_ok;
-    int32_t s_TY, s_RB, s_rows, s_ytiles;
+    int32_t s_TY, s_RB, s_rows, s_ytiles, s_zslabs;
 };
 
 // Work-group shape of the z-march for lattice size L (L % 4 == 0): the whole
@@ -100,6 +101,12 @@ void stream_geometry(Group &g)
     }
     g.s_RB = hsg::kBlock / (P * g.s_TY);
     g.s_ytiles = g.L / g.s_TY;
+    // Single half-sweeps split z into slabs (each reads one extra plane at either
+    // end) until the launch has about 4096 work-groups, keeping slabs >= 16 planes.
+    const int64_t base = (g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles;
+    g.s_zslabs = 1;
+    while (base * g.s_zslabs < 4096 && g.L % (2 * g.s_zslabs) == 0 && g.L / (2 * g.s_zslabs) >= 16)
+        g.s_zslabs *= 2;
 }
 
 struct Layout {
@@ -199,7 +206,8 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         if (g.field) fd = align_up(fd + (uint64_t)g.D * 2 * 3 * g.Nh * 4);
         // scratch: the largest of the three reductions of this group
         g.o_scr = sc;
-        const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > g.s_ytiles ? g.n_pb_sweep : g.s_ytiles) * 8;
+        const int64_t n_pb_stream = g.stream_ok ? (int64_t)g.s_ytiles * g.s_zslabs : 1;
+        const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > n_pb_stream ? g.n_pb_sweep : n_pb_stream) * 8;
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
@@ -229,6 +237,7 @@ struct hsg_lattice {
     char *state = nullptr, *coup = nullptr, *field = nullptr, *scratch = nullptr;
     int32_t slots_per_item = 0;
     int32_t kernel_variant = 0;  // 0 automatic (= 3), 1 gather, 2 z-march, 3 z-march with fused pairs
+    bool hw_math = false;        // heat bath with the hardware transcendentals (kernel kind 2)
     bool have_energies = false;
     // hipGraph replay of whole sweeps (tempering every sweep or never)
     bool use_graphs = true;
@@ -302,7 +311,7 @@ bool use_pair(const hsg_lattice *h, const Group &g)
     return g.stream_ok && g.s_TY == g.L;
 }
 
-hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep)
+hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep, bool pair)
 {
     hsg::StreamArgs a{};
     a.spins = h->state + g.o_spins;
@@ -321,7 +330,10 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     a.RB = g.s_RB;
     a.rows = g.s_rows;
     a.n_ytiles = g.s_ytiles;
-    a.n_blocks = (int32_t)((g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles);
+    a.n_zslabs = pair ? 1 : g.s_zslabs;
+    a.zlen = g.L / a.n_zslabs;
+    const int64_t nb = (g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles * a.n_zslabs;
+    a.n_blocks = nb > 0x7FFFFFFFll ? -1 : (int32_t)nb;
     a.slots_per_sample = g.O * g.T;
     a.T = g.T;
     a.tptr = dev_counter(h);
@@ -342,6 +354,7 @@ template <class Pick>
 hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy, bool pair, Pick pick,
                       hipStream_t s)
 {
+    if (kind == 0 && h->hw_math) kind = 2;
     hsg::MultiStreamArgs m{};
     unsigned threads = 0;
     size_t lds = 0;
@@ -365,9 +378,9 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
                 hsg_status st = flush();
                 if (st != HSG_OK) return st;
             }
-            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep);
+            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep, pair);
             const int64_t nb = (int64_t)a.n_blocks;
-            if (blocks + nb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
+            if (nb < 0 || blocks + nb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
             m.block_start[m.n_groups] = (int32_t)blocks;
             m.g[m.n_groups++] = a;
             blocks += nb;
@@ -387,7 +400,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
     if (energy) {
         for (const Group &g : h->lay.g) {
             if (!pick(g)) continue;
-            const int n_pb = use_stream(h, g) ? g.s_ytiles : g.n_pb_sweep;
+            const int n_pb = pair ? 1 : use_stream(h, g) ? g.s_ytiles * g.s_zslabs : g.n_pb_sweep;
             const hipError_t e = hsg::launch_reduce_partials(reinterpret_cast<double *>(h->scratch + g.o_scr), n_pb,
                                                              g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
             if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
@@ -862,6 +875,109 @@ hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
     if (variant < 0 || variant > 3) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..3", variant);
     h->kernel_variant = variant;
     drop_graphs(h);
+    return HSG_OK;
+}
+
+hsg_status hsg_set_math(hsg_lattice *h, int32_t mode)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (mode != 0 && mode != 1) return fail(HSG_E_INVALID, "math mode = %d, need 0 or 1", mode);
+    h->hw_math = mode == 1;
+    drop_graphs(h);
+    return HSG_OK;
+}
+
+hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_t *variant_out,
+                        int32_t *slots_out, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (n_sweeps < 1 || n_sweeps > 1000) return fail(HSG_E_INVALID, "n_sweeps = %d, need 1..1000", n_sweeps);
+    if (d_backup != nullptr && (reinterpret_cast<uintptr_t>(d_backup) % kAlign) != 0)
+        return fail(HSG_E_INVALID, "backup buffer must be %d-byte aligned", (int)kAlign);
+    const uint64_t need = (uint64_t)n_sweeps + 1;  // trial sweeps per candidate
+    struct Cand {
+        int32_t variant, slots;
+    };
+    bool any_stream = false, any_pair = false, any_gather = false;
+    int max_spp = 1;
+    for (const Group &g : h->lay.g) {
+        any_stream = any_stream || g.stream_ok;
+        any_pair = any_pair || (g.stream_ok && g.s_TY == g.L);
+        any_gather = any_gather || !g.stream_ok;
+        max_spp = std::max(max_spp, g.O * g.T);
+    }
+    std::vector<int32_t> slot_opts;  // slots per work item of the gather kernel, distinct after clamping
+    for (int c : {2, 4, 8, 16}) {
+        const int v = std::min(c, max_spp);
+        if (std::find(slot_opts.begin(), slot_opts.end(), v) == slot_opts.end()) slot_opts.push_back(v);
+    }
+    std::vector<Cand> cands;
+    auto add = [&](int32_t v, bool gather_used) {
+        if (gather_used)
+            for (int32_t c : slot_opts) cands.push_back({v, c});
+        else
+            cands.push_back({v, 0});
+    };
+    if (any_pair) add(3, any_gather);
+    if (any_stream) add(2, any_gather);
+    add(1, true);
+    if (h->t + need * cands.size() > 0x100000000ull)
+        return fail(HSG_E_SIZE, "the trial sweeps would pass the sweep counter limit 2^32");
+
+    hipStream_t s = S(stream);
+    const uint64_t t0 = h->t, pt0 = h->pt_calls;
+    const bool have_e0 = h->have_energies;
+    const int32_t var0 = h->kernel_variant, slots0 = h->slots_per_item;
+    hipError_t e = hipSuccess;
+    if (d_backup != nullptr)
+        e = hipMemcpyAsync(d_backup, h->state, h->lay.sz.state_bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "autotune: saving the state");
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+    hsg_status st = e == hipSuccess ? HSG_OK : hip_fail(e, "autotune: event");
+    float best = 0.0f;
+    Cand pick{var0, slots0};
+    bool have_pick = false;
+    for (size_t k = 0; k < cands.size() && st == HSG_OK; ++k) {
+        h->kernel_variant = cands[k].variant;
+        h->slots_per_item = cands[k].slots;
+        drop_graphs(h);
+        st = hsg_sweep(h, 1, stream);  // warm-up (and graph capture)
+        if (st != HSG_OK) break;
+        e = hipEventRecord(ev[0], s);
+        if (e == hipSuccess) st = hsg_sweep(h, n_sweeps, stream);
+        if (st != HSG_OK) break;
+        if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "autotune: timing");
+            break;
+        }
+        if (!have_pick || ms < best) {
+            best = ms;
+            pick = cands[k];
+            have_pick = true;
+        }
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    h->kernel_variant = st == HSG_OK ? pick.variant : var0;
+    h->slots_per_item = st == HSG_OK ? pick.slots : slots0;
+    drop_graphs(h);
+    if (d_backup != nullptr) {
+        e = hipMemcpyAsync(h->state, d_backup, h->lay.sz.state_bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess && st == HSG_OK) st = hip_fail(e, "autotune: restoring the state");
+        h->t = t0;
+        h->pt_calls = pt0;
+        h->have_energies = have_e0;
+    }
+    if (st != HSG_OK) return st;
+    if (variant_out) *variant_out = h->kernel_variant;
+    if (slots_out) *slots_out = h->slots_per_item;
     return HSG_OK;
 }
 

@@ -73,6 +73,7 @@ __device__ __forceinline__ float hw_cos_rev(float x) { return __builtin_amdgcn_c
 __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+
 // Error-free sum a + b = s + e (Knuth's TwoSum).
 __device__ __forceinline__ float two_sum(float a, float b, float &e)
 {
@@ -121,30 +122,45 @@ __device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
 // with a jump along a whole great circle would turn float32 rounding of h into
 // O(1) jumps of the new spin); 1 + n_z is formed without cancellation for
 // n_z < 0. Zero field: uniform, z frame.
+//
+// HW = false uses the correctly rounded square root and division and the
+// library sincospi. HW = true (an opt-in variant) takes the field's length and
+// direction from the hardware reciprocal square root, the divisions from the
+// hardware reciprocal (1 ulp) and the azimuth from the hardware sin/cos of
+// revolutions (absolute error about 1.2e-7, one float32 spacing at 1). Both
+// keep the library log, exp, log1p and expm1: 1 - c must keep its relative
+// precision when the new spin is nearly parallel to the field.
+template <bool HW>
 __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t w1)
 {
     const float u1 = u24(w0);
     const float u2 = u24(w1);
     const float hh = dot3(h, h);
-    const float hn = sqrtf(hh);
+    float rs, hn;  // 1 / |h| and |h|
+    if constexpr (HW) {
+        rs = hw_rsq(hh);  // infinite for a zero field, then unused
+        hn = hh * rs;
+    } else {
+        hn = sqrtf(hh);
+        rs = 1.0f / hn;
+    }
     const float kappa = beta * hn;
     // omc = 1 - c is formed directly (it is -ln(...) / kappa), so neither c nor
     // the transverse length sqrt((1 - c)(1 + c)) loses precision when c -> 1.
     v3 n;
     float omc;
-    if (hn == 0.0f || kappa == 0.0f) {
+    if (hh == 0.0f || !(kappa > 0.0f)) {
         n = v3{0.0f, 0.0f, 1.0f};
         omc = 2.0f * (1.0f - u1);  // c = 2 u1 - 1, exact
     } else {
-        const float inv = 1.0f / hn;
-        n = v3{h.x * inv, h.y * inv, h.z * inv};
+        n = scale3(h, rs);
         const float omu = 1.0f - u1;  // exact on the 2^-24 grid
         float lg;
         if (kappa < 0.5f)
             lg = log1pf(omu * expm1f(-2.0f * kappa));
         else
             lg = logf(fmaf(omu, expf(-2.0f * kappa), u1));
-        omc = fminf(2.0f, fmaxf(0.0f, -lg / kappa));
+        omc = fminf(2.0f, fmaxf(0.0f, HW ? -lg * hw_rcp(kappa) : -lg / kappa));
     }
     const float c = 1.0f - omc;
     v3 e1, e2;
@@ -153,14 +169,24 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         e1 = v3{-1.0f, 0.0f, 0.0f};
         e2 = v3{0.0f, 1.0f, 0.0f};
     } else {
-        const float a = (n.z >= 0.0f) ? 1.0f / (1.0f + n.z) : (1.0f - n.z) / rxy;  // 1 / (1 + n_z)
+        float a;  // 1 / (1 + n_z)
+        if constexpr (HW)
+            a = (n.z >= 0.0f) ? hw_rcp(1.0f + n.z) : (1.0f - n.z) * hw_rcp(rxy);
+        else
+            a = (n.z >= 0.0f) ? 1.0f / (1.0f + n.z) : (1.0f - n.z) / rxy;
         const float b = -n.x * n.y * a;
         e1 = v3{fmaf(-n.x * n.x, a, 1.0f), b, -n.x};
         e2 = v3{b, fmaf(-n.y * n.y, a, 1.0f), -n.y};
     }
-    const float st = sqrtf(omc * (2.0f - omc));
-    float sp, cp;
-    sincospif(2.0f * u2, &sp, &cp);
+    float st, sp, cp;
+    if constexpr (HW) {
+        st = __builtin_amdgcn_sqrtf(omc * (2.0f - omc));
+        sp = hw_sin_rev(u2);
+        cp = hw_cos_rev(u2);
+    } else {
+        st = sqrtf(omc * (2.0f - omc));
+        sincospif(2.0f * u2, &sp, &cp);
+    }
     const float ta = st * cp, tb = st * sp;
     v3 s{fmaf(c, n.x, fmaf(ta, e1.x, tb * e2.x)), fmaf(c, n.y, fmaf(ta, e1.y, tb * e2.y)),
          fmaf(c, n.z, fmaf(ta, e1.z, tb * e2.z))};

@@ -37,8 +37,9 @@ hipError_t launch_half_sweep(const SweepArgs &a, int storage, int kind, bool fie
                              hipStream_t s);
 
 // z-march variant (L divisible by 4): a work-group owns RB replicas x TY rows
-// and walks z; P = L / 4 site pairs per row; rows = TY (whole plane in LDS) or
-// TY + 2 (with halo rows). Energy partials are [replica][n_ytiles].
+// and walks the zlen planes of one z-slab; P = L / 4 site pairs per row; rows =
+// TY (whole plane in LDS) or TY + 2 (with halo rows). Energy partials are
+// [replica][n_ytiles][n_zslabs]. The fused pair kernel takes one slab.
 struct StreamArgs {
     void *spins;
     const float *J6;
@@ -49,6 +50,7 @@ struct StreamArgs {
     double *e_partials;
     int64_t Nh, n_rep;
     int32_t L, Lh, P, TY, RB, rows, n_ytiles, n_blocks;
+    int32_t n_zslabs, zlen;
     int32_t slots_per_sample, T;
     const uint32_t *tptr;  // device sweep counter
     uint32_t rep, parity;

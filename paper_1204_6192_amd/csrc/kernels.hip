@@ -95,7 +95,7 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
             T *own = base + (int64_t)p * C::kPlanes * Nh;
             const T *oth = base + (int64_t)(1 - p) * C::kPlanes * Nh;
             u32x4 r{0u, 0u, 0u, 0u};
-            if (KIND == 0) {
+            if (KIND != 1) {
                 const int o = sis / a.T, ts = sis - o * a.T;
                 const uint32_t c2 = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12) | ((uint32_t)p << 16);
                 r = philox4x32_10(u32x4{(uint32_t)q, tsweep, c2, a.uid_base + (uint32_t)d}, a.key0, a.key1);
@@ -116,8 +116,8 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
                     }
                 }
                 v3 s1;
-                if (KIND == 0)
-                    s1 = heat_bath(h, beta, k ? r.z : r.x, k ? r.w : r.y);
+                if (KIND != 1)
+                    s1 = heat_bath<KIND == 2>(h, beta, k ? r.z : r.x, k ? r.w : r.y);
                 else
                     s1 = over_relax(C::load(own, Nh, j), h);
                 C::store(own, Nh, j, s1);
@@ -147,6 +147,9 @@ static hipError_t launch_half_sweep_s(const SweepArgs &a, int kind, bool field, 
     if (kind == 0) {
         if (field) { if (energy) HSG_L(0, true, true); else HSG_L(0, true, false); }
         else { if (energy) HSG_L(0, false, true); else HSG_L(0, false, false); }
+    } else if (kind == 2) {
+        if (field) { if (energy) HSG_L(2, true, true); else HSG_L(2, true, false); }
+        else { if (energy) HSG_L(2, false, true); else HSG_L(2, false, false); }
     } else {
         if (field) { if (energy) HSG_L(1, true, true); else HSG_L(1, true, false); }
         else { if (energy) HSG_L(1, false, true); else HSG_L(1, false, false); }

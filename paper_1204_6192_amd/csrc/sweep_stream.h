@@ -1,6 +1,8 @@
 // sweep_stream.h -- checkerboard half-sweep as a z-march (L divisible by 4).
 //
-// One work-group owns RB replicas x TY rows (all of x) and walks z = 0 .. L-1.
+// One work-group owns RB replicas x TY rows (all of x) and walks the planes
+// z0 .. z0 + zlen - 1 of one z-slab (the whole lattice, or a slab when a
+// launch would otherwise have too few work-groups to keep HBM busy).
 // At step z every thread updates the two parity-p sites (x/2 = 2m, 2m + 1) of
 // its row in plane z (Eqs. (2) and (3)). Their six neighbours all lie on the
 // other parity:
@@ -31,7 +33,10 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     using C = Codec<STORE>;
     using T = typename C::T;
     const int ytile = lb % a.n_ytiles;
-    const int rblk = lb / a.n_ytiles;
+    const int zrest = lb / a.n_ytiles;
+    const int zslab = zrest % a.n_zslabs;
+    const int rblk = zrest / a.n_zslabs;
+    const int z0 = zslab * a.zlen, z1 = z0 + a.zlen;
     const int tid = threadIdx.x;
     const int per_rep = a.TY * a.P;
     const int rb = tid / per_rep;
@@ -79,12 +84,12 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     // rolling planes of the other parity at my two positions
     v3 prv0{}, prv1{}, cur0{}, cur1{}, nxt0{}, nxt1{};
     if (active) {
-        C::load_pair(oth, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), prv0, prv1);
-        C::load_pair(oth, Nh, (uint32_t)(y * Lh + xh0), cur0, cur1);
+        C::load_pair(oth, Nh, (uint32_t)((((z0 == 0 ? L : z0) - 1) * L + y) * Lh + xh0), prv0, prv1);
+        C::load_pair(oth, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), cur0, cur1);
     }
     double e = 0.0;
 
-    for (int z = 0; z < L; ++z) {
+    for (int z = z0; z < z1; ++z) {
         const int lo = lbuf[z & 1];
         const int zn = (z + 1 == L) ? 0 : z + 1;
         const uint32_t j0 = (uint32_t)((z * L + y) * Lh + xh0);  // my first site, half-index
@@ -125,7 +130,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
                 *reinterpret_cast<float2 *>(&lds[hw + cstride]) = make_float2(g0.y, g1.y);
                 *reinterpret_cast<float2 *>(&lds[hw + 2 * cstride]) = make_float2(g0.z, g1.z);
             }
-            if (KIND == 0) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
+            if (KIND != 1) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
         }
         __syncthreads();
         if (active) {
@@ -172,9 +177,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
                 }
             }
             v3 s0, s1;
-            if (KIND == 0) {
-                s0 = heat_bath(h0, beta, rr.x, rr.y);
-                s1 = heat_bath(h1, beta, rr.z, rr.w);
+            if (KIND != 1) {
+                s0 = heat_bath<KIND == 2>(h0, beta, rr.x, rr.y);
+                s1 = heat_bath<KIND == 2>(h1, beta, rr.z, rr.w);
             } else {
                 s0 = over_relax(old0, h0);
                 s1 = over_relax(old1, h1);
@@ -206,7 +211,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
             if (r2 < a.n_rep) {
                 double s = 0.0;
                 for (int k = 0; k < per_rep; ++k) s += red[tid * per_rep + k];
-                a.e_partials[r2 * a.n_ytiles + ytile] = s;
+                a.e_partials[(r2 * a.n_ytiles + ytile) * a.n_zslabs + zslab] = s;
             }
         }
     }
@@ -264,9 +269,9 @@ __device__ __forceinline__ double update_pair(const float *lds, int lo, int cstr
             hz1 = fma((double)jc[n].y, (double)nb1[n].z, hz1);
         }
     }
-    if (KIND == 0) {
-        s0 = heat_bath(h0, beta, rr.x, rr.y);
-        s1 = heat_bath(h1, beta, rr.z, rr.w);
+    if (KIND != 1) {
+        s0 = heat_bath<KIND == 2>(h0, beta, rr.x, rr.y);
+        s1 = heat_bath<KIND == 2>(h1, beta, rr.z, rr.w);
     } else {
         s0 = over_relax(old0, h0);
         s1 = over_relax(old1, h1);
@@ -383,27 +388,38 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
 
     v3 o_prv0{}, o_prv1{}, o_cur0{}, o_cur1{}, o_nxt0{}, o_nxt1{};  // old parity 1, planes z-1, z, z+1
     v3 a_m10{}, a_m11{}, a_m20{}, a_m21{};                          // new parity 0, planes z-1, z-2
+    // Global loads run one step ahead: what step z + 1 needs is issued at the
+    // top of step z and lands while step z computes.
+    v3 o_nn0{}, o_nn1{}, oldA0{}, oldA1{}, oldN0{}, oldN1{};
+    float2 jcA[6], jcB[6], jcAn[6], jcBn[6];
+    v3 hA0{}, hA1{}, hB0{}, hB1{}, hAn0{}, hAn1{}, hBn0{}, hBn1{};
+#pragma unroll
+    for (int n = 0; n < 6; ++n) jcB[n] = jcBn[n] = make_float2(0.f, 0.f);
     if (active) {
         C::load_pair(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), o_prv0, o_prv1);
         C::load_pair(sp1, Nh, (uint32_t)(y * Lh + xh0), o_cur0, o_cur1);
+        C::load_pair(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), o_nxt0, o_nxt1);
+        load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, (uint32_t)(y * Lh + xh0), jcA, hA0, hA1);
+        if (KIND == 1) C::load_pair(sp0, Nh, (uint32_t)(y * Lh + xh0), oldA0, oldA1);
     }
     double e = 0.0;
 
     for (int z = 0; z < L; ++z) {
-        const int zn = (z + 1 == L) ? 0 : z + 1;
         const uint32_t jA = (uint32_t)((z * L + y) * Lh + xh0);
         const uint32_t jB = (uint32_t)(((z - 1) * L + y) * Lh + xh0);  // valid when z >= 1
         const bool doB = z >= 2;
-        float2 jcA[6], jcB[6];
-        v3 hA0, hA1, hB0, hB1, oldA0{}, oldA1{};
         u32x4 rrA{0u, 0u, 0u, 0u}, rrB{0u, 0u, 0u, 0u};
         if (active) {
-            C::load_pair(sp1, Nh, (uint32_t)((zn * L + y) * Lh + xh0), o_nxt0, o_nxt1);
-            load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
-            if (KIND == 1) C::load_pair(sp0, Nh, jA, oldA0, oldA1);
-            if (doB) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
+            if (z + 1 < L) {  // step z + 1: old parity 1 of plane z + 2, couplings of z + 1 (A) and z (B)
+                const int z2 = (z + 2 >= L) ? z + 2 - L : z + 2;
+                const uint32_t jA1 = jA + (uint32_t)(L * Lh);
+                C::load_pair(sp1, Nh, (uint32_t)((z2 * L + y) * Lh + xh0), o_nn0, o_nn1);
+                load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jA1, jcAn, hAn0, hAn1);
+                if (KIND == 1) C::load_pair(sp0, Nh, jA1, oldN0, oldN1);
+                if (z >= 1) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jA, jcBn, hBn0, hBn1);
+            }
             lds_put_pair(lds, lA[z & 1] + lrow_w, cstride, o_cur0, o_cur1);
-            if (KIND == 0) {
+            if (KIND != 1) {
                 rrA = philox4x32_10(u32x4{jA >> 1, tsweep, c2A, uid}, a.key0, a.key1);
                 if (doB) rrB = philox4x32_10(u32x4{jB >> 1, tsweep, c2B, uid}, a.key0, a.key1);
             }
@@ -439,6 +455,11 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         }
         o_prv0 = o_cur0; o_prv1 = o_cur1;
         o_cur0 = o_nxt0; o_cur1 = o_nxt1;
+        o_nxt0 = o_nn0; o_nxt1 = o_nn1;
+        oldA0 = oldN0; oldA1 = oldN1;
+#pragma unroll
+        for (int n = 0; n < 6; ++n) { jcA[n] = jcAn[n]; jcB[n] = jcBn[n]; }
+        hA0 = hAn0; hA1 = hAn1; hB0 = hBn0; hB1 = hBn1;
     }
 
     // seam: parity-1 sites of planes L - 1 and 0
@@ -451,7 +472,7 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         if (active) {
             load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
             load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
-            if (KIND == 0) {
+            if (KIND != 1) {
                 rrL = philox4x32_10(u32x4{jL >> 1, tsweep, c2B, uid}, a.key0, a.key1);
                 rr0 = philox4x32_10(u32x4{j0 >> 1, tsweep, c2B, uid}, a.key0, a.key1);
             }
@@ -558,6 +579,10 @@ hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, bool
     if (kind == 0) {
         if (energy) return launch_stream_e<STORE, 0, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
         return launch_stream_e<STORE, 0, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+    }
+    if (kind == 2) {
+        if (energy) return launch_stream_e<STORE, 2, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+        return launch_stream_e<STORE, 2, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
     }
     if (energy) return launch_stream_e<STORE, 1, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
     return launch_stream_e<STORE, 1, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);

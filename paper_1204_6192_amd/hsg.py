@@ -90,6 +90,8 @@ _SIG = {
     "hsg_set_state": [_vp, _u64, _u64, _vp],
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
+    "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "hsg_set_math": [_vp, _i32],
     "hsg_set_graphs": [_vp, _i32],
     "hsg_sync": [_vp, _vp],
     "hsg_debug_philox": [_vp, _vp, _vp, _i64, _vp],
@@ -267,6 +269,24 @@ class Lattice:
 
     def set_kernel(self, variant: int) -> None:
         check(lib.hsg_set_kernel(self.h, int(variant)))
+
+    def autotune(self, n_sweeps: int = 4, restore: bool = True):
+        """Time each kernel variant over n_sweeps real sweeps and keep the fastest.
+        With restore, the state is saved to a temporary device buffer and put back,
+        so the chain is unchanged; otherwise it advances by the trial sweeps.
+        Returns (variant, slots_per_item)."""
+        backup = None
+        if restore:
+            backup = torch.empty(self.sizes.state_bytes, dtype=torch.uint8, device=self.device)
+        v, c = C.c_int32(), C.c_int32()
+        check(lib.hsg_autotune(self.h, int(n_sweeps), None if backup is None else backup.data_ptr(),
+                               C.byref(v), C.byref(c), _stream(self.stream)))
+        del backup
+        return v.value, c.value
+
+    def set_math(self, mode: int) -> None:
+        """0: library transcendentals in the heat bath (default); 1: hardware ones."""
+        check(lib.hsg_set_math(self.h, int(mode)))
 
     def sync(self) -> None:
         check(lib.hsg_sync(self.h, _stream(self.stream)))

@@ -125,7 +125,7 @@ def _rms(a):
 
 
 def _trajectory(hsg, oracle_lib, inst, n_sweeps, storage="f32", spin_tol=TOL_SPIN,
-                shadow_factor=SHADOW_FACTOR):
+                shadow_factor=SHADOW_FACTOR, math=0):
     """GPU vs oracle over n_sweeps from the same seeded start.
 
     The chain amplifies any difference in the spins by roughly an order of
@@ -148,6 +148,7 @@ def _trajectory(hsg, oracle_lib, inst, n_sweeps, storage="f32", spin_tol=TOL_SPI
     """
     lat = _lat(hsg, inst.groups, inst.seed, storage=storage, n_hb=inst.n_hb, n_or=inst.n_or,
                pt_every=inst.pt_every)
+    lat.set_math(math)
     kw = dict(seed=inst.seed, n_hb=inst.n_hb, n_or=inst.n_or, pt_every=inst.pt_every,
               storage=storage)
     orcs = [oracle_lib.Oracle.from_group(g, **kw) for g in inst.groups]
@@ -220,6 +221,18 @@ def test_trajectory_bimodal_mix(hsg, oracle_lib):
     _trajectory(hsg, oracle_lib, inst, 10)
 
 
+@pytest.mark.parametrize("field", [False, True])
+def test_trajectory_hardware_math(hsg, oracle_lib, field):
+    """The heat bath with the hardware transcendentals (hsg_set_math(1)) against
+    the oracle, to the same bounds as the default arithmetic: its errors sit at
+    the float32 rounding level."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 43))
+    g = inputs.make_group(rng, 8, 2, 2, inputs.geometric_ladder(0.1, 0.3, 6),
+                          field=("gaussian", 0.2) if field else None)
+    inst = inputs.Instance(groups=[g], seed=inputs.PHILOX_KEY_BASE + 43, n_hb=2, n_or=2)
+    _trajectory(hsg, oracle_lib, inst, 10, math=1)
+
+
 def test_batched_L32_two_samples(hsg, oracle_lib):
     """The batched workload's lattice and ladder (L = 32, 2 x 32 temperatures) for two
     samples, checked in full for 2 sweeps; several tiles and every replica."""
@@ -256,6 +269,66 @@ def test_batched_full_size_sampled(hsg, oracle_lib):
         assert _rms(dd) <= SHADOW_FACTOR * r_rms and np.abs(dd).max() <= SHADOW_FACTOR * r_max
         assert np.array_equal(maps[d:d + 1], o.slot_at_temp)
         assert _rms(E[d:d + 1] - o.E) <= SHADOW_FACTOR * r_E + 2.0 ** -22 * np.abs(o.E).max()
+
+
+# one quantisation step of each spin codec, in the largest component: a single
+# half-sweep may round a value within float32 noise of a step boundary the other
+# way than the float64 oracle does
+CODE_STEP = {"f32": 0.0, "f16": 2.0 ** -11, "bf16": 2.0 ** -8, "qangle": 2.0 / 32767}
+
+
+@pytest.mark.parametrize("config", ["field", "uneven", "large"])
+def test_full_size_half_sweeps_sampled(hsg, oracle_lib, config):
+    """The field (L = 64, float16, random field), uneven (five sizes, bfloat16) and
+    large (L = 128, +-1 couplings as sign bits, quantised angles) workloads at full
+    size, in the launch configuration of the benchmark (z-slabs, row bands, the
+    multi-size table). Two heat-bath and two over-relaxation half-sweeps; before
+    each, the oracle takes the GPU's current spins of two sampled replicas (copy 0,
+    the two lowest rungs) of the last sample of each lattice size and performs the
+    same half-sweep. Every spin agrees to 1e-5, except where float32 and float64
+    round a spin to different codes of the compressed storage: at most one code
+    step, at under 1% of the sites."""
+    inst = inputs.make_instance(config)
+    lat = _lat(hsg, inst.groups, inst.seed, storage=inst.storage, n_hb=inst.n_hb,
+               n_or=inst.n_or, pt_every=inst.pt_every)
+    subs = []
+    for g in inst.groups:
+        d = g.n_samples - 1
+        subs.append(inputs.Group(L=g.L, n_samples=1, n_copies=1, temps=g.temps[:2],
+                                 J=g.J[d:d + 1], H=None if g.H is None else g.H[d:d + 1],
+                                 spins0=g.spins0[d:d + 1, :1, :2], coupling_kind=g.coupling_kind,
+                                 sample_uid_base=g.sample_uid_base + d))
+    orcs = [oracle_lib.Oracle.from_group(sg, seed=inst.seed, storage=inst.storage) for sg in subs]
+    step = CODE_STEP[inst.storage]
+
+    def sampled():  # copy 0, rungs 0 and 1 of the last sample of every group
+        flat = lat.get_spins().cpu().numpy()
+        out, off = [], 0
+        for g in inst.groups:
+            n = g.n_slots * 3 * g.N
+            out.append(flat[off:off + n].reshape(g.n_samples, g.n_copies, g.n_temps, 3, g.N)
+                       [-1:, :1, :2].copy())
+            off += n
+        return out
+
+    after = sampled()
+    for kind, parity in ((0, 0), (0, 1), (1, 0), (1, 1)):
+        before = after
+        lat.half_sweep(kind, parity)
+        after = sampled()
+        for k, (g, o) in enumerate(zip(inst.groups, orcs)):
+            o.spins = np.ascontiguousarray(before[k], dtype=np.float64)
+            if inst.storage != "f32":
+                o._apply_storage_to_all()
+            o.half_sweep(kind, parity)
+            d = np.abs(after[k] - o.spins).max(axis=3)
+            frac = float((d > 1e-5).mean())
+            print(f"{config} L={g.L} kind {kind} parity {parity}: max |ds| {d.max():.2e}, "
+                  f"fraction above 1e-5 {frac:.2e}", flush=True)
+            if step == 0.0:
+                assert d.max() < 1e-5
+            else:
+                assert d.max() < 1.5 * step + 1e-5 and frac < 1e-2
 
 
 def test_tuning_and_batch_composition_invariance(hsg):
@@ -456,8 +529,8 @@ def test_gpu_long_run_statistics_vs_oracle(hsg, oracle_lib):
         assert abs(z_all) < 3.0, (name, z_all)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "qangle"])
-def test_kernel_variants_bit_identical(hsg, storage):
+@pytest.mark.parametrize("storage,math", [("f32", 0), ("f16", 0), ("qangle", 0), ("f32", 1)])
+def test_kernel_variants_bit_identical(hsg, storage, math):
     """The gather kernel, the z-march kernel (L divisible by 4) and the z-march with
     both half-sweeps of a pair fused (whole planes, L <= 32) compute the same
     per-site arithmetic: spins and temperature maps agree bit for bit. L = 36
@@ -479,6 +552,7 @@ def test_kernel_variants_bit_identical(hsg, storage):
     for variant in (1, 2, 3):
         lat = _lat(hsg, groups, seed, storage=storage)
         lat.set_kernel(variant)
+        lat.set_math(math)
         lat.sweep(3)
         res.append((lat.get_spins().cpu(), lat.get_temp_map().cpu(), lat.get_energies().cpu(),
                     lat.measure_energy().cpu()))
@@ -487,6 +561,42 @@ def test_kernel_variants_bit_identical(hsg, storage):
         assert torch.equal(res[0][1], other[1])
         assert torch.allclose(res[0][2], other[2], rtol=1e-12, atol=1e-9)
         assert torch.equal(res[0][3], other[3])  # same spins, same recomputation
+
+
+def test_autotune_keeps_the_chain(hsg):
+    """The autotuner's trial sweeps are ordinary sweeps. With a backup buffer the
+    state (spins, maps, energies, counters) comes back unchanged and the chain
+    continues bit for bit as without tuning; without one the chain has advanced
+    by the trial sweeps, bit for bit as a plain run of as many sweeps."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 61))
+    groups, uid = [], 0
+    for L, D, T in ((6, 2, 3), (8, 2, 4), (12, 1, 3)):  # gather, fused pair, fused pair
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, T),
+                                        sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 61
+    ref = _lat(hsg, groups, seed)
+    a = _lat(hsg, groups, seed)
+    ref.sweep(2)
+    a.sweep(2)
+    v, c = a.autotune(n_sweeps=2, restore=True)
+    assert v in (1, 2, 3) and c >= 0
+    assert a.get_state()[0] == ref.get_state()[0]
+    assert torch.equal(a.get_spins(), ref.get_spins())
+    assert torch.equal(a.get_temp_map(), ref.get_temp_map())
+    assert torch.equal(a.get_energies(), ref.get_energies())
+    ref.sweep(3)
+    a.sweep(3)
+    assert torch.equal(a.get_spins(), ref.get_spins())
+    assert torch.equal(a.get_temp_map(), ref.get_temp_map())
+    t0 = a.get_state()[0]
+    a.autotune(n_sweeps=1, restore=False)
+    n_trial = a.get_state()[0] - t0
+    assert n_trial >= 2
+    ref.sweep(n_trial)
+    assert torch.equal(a.get_spins(), ref.get_spins())
+    assert torch.equal(a.get_temp_map(), ref.get_temp_map())
+    assert torch.equal(a.get_energies(), ref.get_energies())
 
 
 @pytest.mark.parametrize("pt_every", [1, 0, 3])
@@ -541,8 +651,15 @@ def test_hardware_transcendentals_accuracy(hsg):
     ry = hsg.debug_hw_math(y).astype(np.float64)
     err_rcp = (np.abs(ry[:, 4] * y - 1.0)).max()
     err_rsq = (np.abs(ry[:, 5] * np.sqrt(y.astype(np.float64)) - 1.0)).max()
+    # relative error of the hardware log just below 1 (where a heat-bath draw
+    # nearly parallel to the field needs it); informational
+    k = np.unique(np.concatenate([np.arange(1, 4097), rng.integers(1, 2 ** 23, 100000)]))
+    v = (1.0 - k * 2.0 ** -24).astype(np.float32)
+    lv = hsg.debug_hw_math(v)[:, 2].astype(np.float64)
+    rel_log1 = (np.abs(lv - np.log(v.astype(np.float64))) / np.abs(np.log(v.astype(np.float64)))).max()
     print(f"max abs error sin {err_sin:.2e} cos {err_cos:.2e} log {err_log:.2e}; max rel error "
-          f"exp {err_exp:.2e} rcp {err_rcp:.2e} rsq {err_rsq:.2e}", flush=True)
+          f"exp {err_exp:.2e} rcp {err_rcp:.2e} rsq {err_rsq:.2e} log(1 - k 2^-24) {rel_log1:.2e}",
+          flush=True)
     assert err_sin < 1e-6 and err_cos < 1e-6
     assert err_log < 2e-6
     assert err_exp < 1e-5
