@@ -388,18 +388,18 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
 
     v3 o_prv0{}, o_prv1{}, o_cur0{}, o_cur1{}, o_nxt0{}, o_nxt1{};  // old parity 1, planes z-1, z, z+1
     v3 a_m10{}, a_m11{}, a_m20{}, a_m21{};                          // new parity 0, planes z-1, z-2
-    // Global loads run one step ahead: what step z + 1 needs is issued at the
-    // top of step z and lands while step z computes.
+    // The spin loads run one step ahead: the old spins step z + 1 needs are
+    // issued at the top of step z and land while step z computes. Couplings come
+    // from L2 (shared by the sample's replicas) and are loaded within the step.
     v3 o_nn0{}, o_nn1{}, oldA0{}, oldA1{}, oldN0{}, oldN1{};
-    float2 jcA[6], jcB[6], jcAn[6], jcBn[6];
-    v3 hA0{}, hA1{}, hB0{}, hB1{}, hAn0{}, hAn1{}, hBn0{}, hBn1{};
+    float2 jcA[6], jcB[6];
+    v3 hA0{}, hA1{}, hB0{}, hB1{};
 #pragma unroll
-    for (int n = 0; n < 6; ++n) jcB[n] = jcBn[n] = make_float2(0.f, 0.f);
+    for (int n = 0; n < 6; ++n) jcB[n] = make_float2(0.f, 0.f);
     if (active) {
         C::load_pair(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), o_prv0, o_prv1);
         C::load_pair(sp1, Nh, (uint32_t)(y * Lh + xh0), o_cur0, o_cur1);
         C::load_pair(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), o_nxt0, o_nxt1);
-        load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, (uint32_t)(y * Lh + xh0), jcA, hA0, hA1);
         if (KIND == 1) C::load_pair(sp0, Nh, (uint32_t)(y * Lh + xh0), oldA0, oldA1);
     }
     double e = 0.0;
@@ -410,14 +410,14 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         const bool doB = z >= 2;
         u32x4 rrA{0u, 0u, 0u, 0u}, rrB{0u, 0u, 0u, 0u};
         if (active) {
-            if (z + 1 < L) {  // step z + 1: old parity 1 of plane z + 2, couplings of z + 1 (A) and z (B)
+            if (z + 1 < L) {  // for step z + 1: old parity 1 of plane z + 2, old parity 0 of plane z + 1
                 const int z2 = (z + 2 >= L) ? z + 2 - L : z + 2;
                 const uint32_t jA1 = jA + (uint32_t)(L * Lh);
                 C::load_pair(sp1, Nh, (uint32_t)((z2 * L + y) * Lh + xh0), o_nn0, o_nn1);
-                load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jA1, jcAn, hAn0, hAn1);
                 if (KIND == 1) C::load_pair(sp0, Nh, jA1, oldN0, oldN1);
-                if (z >= 1) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jA, jcBn, hBn0, hBn1);
             }
+            load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
+            if (doB) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
             lds_put_pair(lds, lA[z & 1] + lrow_w, cstride, o_cur0, o_cur1);
             if (KIND != 1) {
                 rrA = philox4x32_10(u32x4{jA >> 1, tsweep, c2A, uid}, a.key0, a.key1);
@@ -457,9 +457,6 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         o_cur0 = o_nxt0; o_cur1 = o_nxt1;
         o_nxt0 = o_nn0; o_nxt1 = o_nn1;
         oldA0 = oldN0; oldA1 = oldN1;
-#pragma unroll
-        for (int n = 0; n < 6; ++n) { jcA[n] = jcAn[n]; jcB[n] = jcBn[n]; }
-        hA0 = hAn0; hA1 = hAn1; hB0 = hBn0; hB1 = hBn1;
     }
 
     // seam: parity-1 sites of planes L - 1 and 0
