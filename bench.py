@@ -78,6 +78,26 @@ def time_kernel(lat, kind, n, torch):
     return start.elapsed_time(stop) / n * 1e-3  # seconds per pair
 
 
+def copy_bandwidth(torch, mib=1024, reps=10):
+    """Read+write GB/s of a plain device-to-device copy (the practical HBM ceiling
+    next to the published 8 TB/s)."""
+    n = mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        b.copy_(a)
+    stop.record()
+    stop.synchronize()
+    t = start.elapsed_time(stop) / reps * 1e-3
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n / t / 1e9
+
+
 def measured_traffic(build_id, workload):
     """HBM bytes per launch of the dominant kernel from the hardware counters, as
     recorded in a profile summary under profiles/ by a line
@@ -207,6 +227,8 @@ def main():
     eff_gbs = (inst.n_hb * b_hb + inst.n_or * b_or) / (dt / args.steps) / 1e9
 
     traffic, traffic_src = measured_traffic(hsg.build_id(), args.config)
+    copy_gbs = copy_bandwidth(torch)
+    log(f"device copy: {copy_gbs:.0f} GB/s read+write; OR pair at {gbs_or / copy_gbs:.1%} of it")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(inst, args.cpu_sweeps, log)
@@ -240,7 +262,8 @@ def main():
                      "traffic_source": traffic_src,
                      "launch_us": t_or * 1e6, "bytes_per_launch": b_or,
                      "hb_pair_us": t_hb * 1e6, "hb_gbs": b_hb / t_hb / 1e9,
-                     "hb_pair_us_hw_math": t_hb_hw * 1e6},
+                     "hb_pair_us_hw_math": t_hb_hw * 1e6,
+                     "device_copy_gbs": copy_gbs, "frac_of_copy": gbs_or / copy_gbs},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
