@@ -16,6 +16,11 @@ Functions and what pins them (details in the tests):
 * ``Oracle.sweep``      -- single spin in a field, open 1D chain, OR energy
                            conservation, infinite temperature, site-order
                            independence of a half-sweep;
+* ``Oracle.sweep`` with tiles (the tile-local chain) -- equal to the full-lattice
+                           chain for one whole-lattice tile (OR-only and HB-only
+                           mixes), tile-order independence, a plain-Python replay
+                           of the visiting order on a small lattice, and the
+                           closed forms above;
 * ``Oracle.pt_exchange``-- acceptance frequency against min(1, e^Delta);
 * ``Oracle.measure_overlap`` -- q^2 = 1 for identical aligned copies, O(3)
                            invariance, trace identity.
@@ -47,6 +52,10 @@ def build(force: bool = True) -> str:
 
 
 _lib = None
+
+
+class Tiles(C.Structure):
+    _fields_ = [("tx", C.c_int32), ("ty", C.c_int32), ("tz", C.c_int32), ("n_hit", C.c_int32)]
 
 
 class Cfg(C.Structure):
@@ -82,6 +91,9 @@ def lib():
         L.hsgo_energies.argtypes = [P(Cfg), dp, dp, dp, dp]
         L.hsgo_sweep.argtypes = [P(Cfg), dp, dp, dp, i32p, dp, dp, u64p, C.c_int, u64p]
         L.hsgo_overlap.argtypes = [P(Cfg), dp, i32p, dp]
+        L.hsgo_tile_sweep.argtypes = [P(Cfg), P(Tiles), dp, dp, dp, i32p, dp, dp, u64p, C.c_int,
+                                      u64p, i64p]
+        L.hsgo_tiles_valid.argtypes = [C.c_int, P(Tiles), C.c_int]
         L.hsgo_set_storage_mode.argtypes = [C.c_int]
         L.hsgo_store_roundtrip.argtypes = [C.c_int, dp]
         L.hsgo_round_f16.argtypes = [C.c_double]
@@ -199,7 +211,7 @@ class Oracle:
     """
 
     def __init__(self, L, n_samples, n_copies, temps, J, H, spins0, *, seed, n_hb=1, n_or=4,
-                 pt_every=1, sample_uid_base=0, storage="f32"):
+                 pt_every=1, sample_uid_base=0, storage="f32", tiles=None, n_hit=1):
         self.cfg = Cfg(L=L, n_samples=n_samples, n_copies=n_copies, n_temps=len(temps),
                        n_hb=n_hb, n_or=n_or, pt_every=pt_every,
                        sample_uid_base=sample_uid_base, seed=seed)
@@ -213,6 +225,13 @@ class Oracle:
         self.spins = np.ascontiguousarray(spins0, dtype=np.float64).reshape(
             n_samples, n_copies, len(temps), 3, self.N).copy()
         self.storage = storage
+        # tiles = (tx, ty, tz): the tile-local chain of the double checkerboard
+        # decomposition; None: the full-lattice checkerboard
+        self.tiles = None
+        if tiles is not None:
+            self.tiles = Tiles(tx=int(tiles[0]), ty=int(tiles[1]), tz=int(tiles[2]), n_hit=int(n_hit))
+            if not lib().hsgo_tiles_valid(L, C.byref(self.tiles), n_hb):
+                raise ValueError(f"tiles {tiles} x {n_hit} do not fit L = {L}")
         if STORAGE_MODES[storage] != 0:
             self._apply_storage_to_all()
         T = len(temps)
@@ -225,10 +244,11 @@ class Oracle:
         self.noise = (0.0, 0)  # sensitivity probe: (relative amplitude, stream seed)
 
     @classmethod
-    def from_group(cls, g, *, seed, n_hb=1, n_or=4, pt_every=1, storage="f32"):
+    def from_group(cls, g, *, seed, n_hb=1, n_or=4, pt_every=1, storage="f32", tiles=None,
+                   n_hit=1):
         return cls(g.L, g.n_samples, g.n_copies, g.temps, g.J, g.H, g.spins0, seed=seed,
                    n_hb=n_hb, n_or=n_or, pt_every=pt_every, sample_uid_base=g.sample_uid_base,
-                   storage=storage)
+                   storage=storage, tiles=tiles, n_hit=n_hit)
 
     def _apply_storage_to_all(self):
         mode = STORAGE_MODES[self.storage]
@@ -255,15 +275,29 @@ class Oracle:
             lib().hsgo_set_noise(eps, (seed * 1_000_003 + self.t * 7919 + self.pt_calls)
                                  & 0xFFFFFFFFFFFFFFFF)
 
-    def sweep(self, n_sweeps: int = 1) -> None:
+    def sweep(self, n_sweeps: int = 1, tile_order=None) -> None:
+        """n_sweeps sweeps of the full-lattice checkerboard chain, or of the
+        tile-local chain when the oracle was made with tiles (then tile_order
+        optionally permutes the visits of each coarse parity's tiles)."""
         lib().hsgo_set_storage_mode(STORAGE_MODES[self.storage])
         self._noise_on()
         t = np.array([self.t], dtype=np.uint64)
         Jp, Hp = self._args()
-        rc = lib().hsgo_sweep(C.byref(self.cfg), Jp, Hp, _p(self.spins, C.c_double),
-                              _p(self.slot_at_temp, C.c_int32), _p(self.beta, C.c_double),
-                              _p(self.E, C.c_double), _p(t, C.c_uint64), int(n_sweeps),
-                              _p(self.accepts, C.c_uint64))
+        if self.tiles is None:
+            rc = lib().hsgo_sweep(C.byref(self.cfg), Jp, Hp, _p(self.spins, C.c_double),
+                                  _p(self.slot_at_temp, C.c_int32), _p(self.beta, C.c_double),
+                                  _p(self.E, C.c_double), _p(t, C.c_uint64), int(n_sweeps),
+                                  _p(self.accepts, C.c_uint64))
+        else:
+            op = None
+            if tile_order is not None:
+                tile_order = np.ascontiguousarray(tile_order, dtype=np.int64)
+                op = _p(tile_order, C.c_int64)
+            rc = lib().hsgo_tile_sweep(C.byref(self.cfg), C.byref(self.tiles), Jp, Hp,
+                                       _p(self.spins, C.c_double),
+                                       _p(self.slot_at_temp, C.c_int32), _p(self.beta, C.c_double),
+                                       _p(self.E, C.c_double), _p(t, C.c_uint64), int(n_sweeps),
+                                       _p(self.accepts, C.c_uint64), op)
         lib().hsgo_set_storage_mode(0)
         lib().hsgo_set_noise(0.0, 0)
         if rc != 0:

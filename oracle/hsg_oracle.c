@@ -283,6 +283,37 @@ static double noise_uniform(void)
  * `order`, if not NULL, lists the visiting order of the N/2 sites of this parity
  * as indices into the canonical enumeration of that parity (for the test that
  * the result does not depend on the order). */
+/* One site's update in place: a heat-bath draw (kind 0) or an over-relaxation
+ * reflection (kind 1) from the current neighbours, then the storage hook. */
+static void update_site(const hsgo_cfg *c, const double *J, const double *H, double *s,
+                        int d, int o, int slot, double beta, int kind, int rep, int parity,
+                        uint32_t t, int64_t i)
+{
+    const int L = c->L;
+    const int64_t N = (int64_t)L * L * L;
+    int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
+    double h[3], sn[3], so[3];
+    local_field(L, J, H, s, x, y, z, h);
+    if (kind == HSGO_HB) {
+        uint32_t w[2];
+        hsgo_hb_words(c, d, o, slot, rep, parity, t, i, w);
+        hsgo_hb_draw(h, beta, w[0], w[1], sn);
+    } else {
+        for (int m = 0; m < 3; ++m) so[m] = s[m * N + i];
+        hsgo_or_reflect(so, h, sn);
+    }
+    if (g_noise_eps > 0.0)
+        for (int m = 0; m < 3; ++m) sn[m] *= 1.0 + g_noise_eps * noise_uniform();
+    hsgo_store_roundtrip(g_storage_mode, sn);
+    for (int m = 0; m < 3; ++m) s[m * N + i] = sn[m];
+}
+
+/* One half-sweep of one slot: every site of parity `parity` gets a heat-bath
+ * draw (kind 0) or an over-relaxation reflection (kind 1). Sites of one parity
+ * only see the other parity through H_eff, so the in-place update is exact.
+ * `order`, if not NULL, lists the visiting order of the N/2 sites of this parity
+ * as indices into the canonical enumeration of that parity (for the test that
+ * the result does not depend on the order). */
 static void half_sweep_slot(const hsgo_cfg *c, const double *J, const double *H,
                             double *s, int d, int o, int slot, double beta,
                             int kind, int rep, int parity, uint32_t t,
@@ -297,24 +328,8 @@ static void half_sweep_slot(const hsgo_cfg *c, const double *J, const double *H,
         for (int y = 0; y < L; ++y)
             for (int x = 0; x < L; ++x)
                 if (((x + y + z) & 1) == parity) sites[n++] = site(L, x, y, z);
-    for (int64_t q = 0; q < n; ++q) {
-        int64_t i = sites[order ? order[q] : q];
-        int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
-        double h[3], sn[3], so[3];
-        local_field(L, J, H, s, x, y, z, h);
-        if (kind == HSGO_HB) {
-            uint32_t w[2];
-            hsgo_hb_words(c, d, o, slot, rep, parity, t, i, w);
-            hsgo_hb_draw(h, beta, w[0], w[1], sn);
-        } else {
-            for (int m = 0; m < 3; ++m) so[m] = s[m * N + i];
-            hsgo_or_reflect(so, h, sn);
-        }
-        if (g_noise_eps > 0.0)
-            for (int m = 0; m < 3; ++m) sn[m] *= 1.0 + g_noise_eps * noise_uniform();
-        hsgo_store_roundtrip(g_storage_mode, sn);
-        for (int m = 0; m < 3; ++m) s[m * N + i] = sn[m];
-    }
+    for (int64_t q = 0; q < n; ++q)
+        update_site(c, J, H, s, d, o, slot, beta, kind, rep, parity, t, sites[order ? order[q] : q]);
     free(sites);
 }
 
@@ -421,6 +436,105 @@ int hsgo_sweep(const hsgo_cfg *c, const double *J, const double *H, double *spin
             hsgo_pt_pass(c, E, slot_at_temp, beta, tt, 1u, accepts);
         *t += 1;
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The tile-local chain of the double checkerboard decomposition (§3.1 and    */
+/* the numbered Monte Carlo procedure of §3.2).                               */
+/* ------------------------------------------------------------------------ */
+/* The lattice is cut into tiles of tx x ty x tz sites. Every edge divides L,
+ * and the number of tiles along each axis is 1 (the tile wraps around that
+ * axis) or even, so tiles of equal coarse parity (X + Y + Z) mod 2 of their
+ * tile coordinates never share a face. One sweep visits every tile of coarse
+ * parity 0, then every tile of coarse parity 1. On a visit, the tile's spins
+ * get n_hit repetitions of: n_or over-relaxation rounds, then n_hb heat-bath
+ * rounds, where a round updates all even sites of the tile and then all odd
+ * sites (global parity). Spins outside the tile (its halo) belong to tiles of
+ * the other coarse parity and stay fixed during the visit, so the visits of
+ * one coarse parity are independent of each other. Heat-bath round b of
+ * repetition r draws with repetition index r n_hb + b of the counter map.
+ * Then the exact energies and a tempering pass, as in hsgo_sweep.
+ * `tile_order`, if not NULL, gives the order in which the tiles of each coarse
+ * parity are visited (indices into the canonical enumeration of that parity's
+ * tiles; for the test that the order does not matter). */
+typedef struct {
+    int32_t tx, ty, tz, n_hit;
+} hsgo_tiles;
+
+int hsgo_tiles_valid(int L, const hsgo_tiles *tl, int n_hb)
+{
+    const int e[3] = {tl->tx, tl->ty, tl->tz};
+    for (int a = 0; a < 3; ++a) {
+        if (e[a] < 1 || L % e[a] != 0) return 0;
+        int b = L / e[a];
+        if (b != 1 && (b & 1)) return 0;
+    }
+    if (tl->n_hit < 1 || tl->n_hit * n_hb > 16) return 0;
+    return 1;
+}
+
+static void tile_round(const hsgo_cfg *c, const double *J, const double *H, double *s, int d,
+                       int o, int slot, double beta, int kind, int rep, uint32_t t, int x0,
+                       int y0, int z0, const hsgo_tiles *tl)
+{
+    for (int p = 0; p < 2; ++p)
+        for (int z = z0; z < z0 + tl->tz; ++z)
+            for (int y = y0; y < y0 + tl->ty; ++y)
+                for (int x = x0; x < x0 + tl->tx; ++x)
+                    if (((x + y + z) & 1) == p)
+                        update_site(c, J, H, s, d, o, slot, beta, kind, rep, p, t,
+                                    site(c->L, x, y, z));
+}
+
+int hsgo_tile_sweep(const hsgo_cfg *c, const hsgo_tiles *tl, const double *J, const double *H,
+                    double *spins, int32_t *slot_at_temp, const double *beta, double *E,
+                    uint64_t *t, int n_sweeps, uint64_t *accepts, const int64_t *tile_order)
+{
+    const int L = c->L;
+    const int64_t N = (int64_t)L * L * L;
+    if (!hsgo_tiles_valid(L, tl, c->n_hb)) return -2;
+    const int bx = L / tl->tx, by = L / tl->ty, bz = L / tl->tz;
+    const int64_t nt = (int64_t)bx * by * bz;
+    int64_t *tiles = (int64_t *)malloc(sizeof(int64_t) * (size_t)nt);
+    for (int it = 0; it < n_sweeps; ++it) {
+        uint32_t tt = (uint32_t)(*t);
+        for (int cp = 0; cp < 2; ++cp) {
+            /* canonical list of the tiles of coarse parity cp */
+            int64_t n = 0;
+            for (int Z = 0; Z < bz; ++Z)
+                for (int Y = 0; Y < by; ++Y)
+                    for (int X = 0; X < bx; ++X)
+                        if (((X + Y + Z) & 1) == cp) tiles[n++] = X + (int64_t)bx * (Y + (int64_t)by * Z);
+            for (int64_t q = 0; q < n; ++q) {
+                int64_t T = tiles[tile_order ? tile_order[q] : q];
+                int X = (int)(T % bx), Y = (int)((T / bx) % by), Z = (int)(T / ((int64_t)bx * by));
+                for (int d = 0; d < c->n_samples; ++d)
+                    for (int o = 0; o < c->n_copies; ++o)
+                        for (int sl = 0; sl < c->n_temps; ++sl) {
+                            int k = rung_of_slot(c, slot_at_temp, d, o, sl);
+                            if (k < 0) { free(tiles); return -1; }
+                            const double *Jd = J + (int64_t)d * 3 * N;
+                            const double *Hd = H ? H + (int64_t)d * 3 * N : NULL;
+                            double *sp = slot_ptr(c, spins, d, o, sl);
+                            for (int r = 0; r < tl->n_hit; ++r) {
+                                for (int m = 0; m < c->n_or; ++m)
+                                    tile_round(c, Jd, Hd, sp, d, o, sl, beta[k], HSGO_OR, 0, tt,
+                                               X * tl->tx, Y * tl->ty, Z * tl->tz, tl);
+                                for (int b = 0; b < c->n_hb; ++b)
+                                    tile_round(c, Jd, Hd, sp, d, o, sl, beta[k], HSGO_HB,
+                                               r * c->n_hb + b, tt, X * tl->tx, Y * tl->ty,
+                                               Z * tl->tz, tl);
+                            }
+                        }
+            }
+        }
+        hsgo_energies(c, J, H, spins, E);
+        if (c->pt_every > 0 && ((*t + 1) % (uint64_t)c->pt_every) == 0)
+            hsgo_pt_pass(c, E, slot_at_temp, beta, tt, 1u, accepts);
+        *t += 1;
+    }
+    free(tiles);
     return 0;
 }
 
