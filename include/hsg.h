@@ -200,6 +200,26 @@ hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
  * faster choice; over-relaxation is the same in both. */
 hsg_status hsg_set_math(hsg_lattice *h, int32_t mode);
 
+/* Markov chain of hsg_sweep. chain = 0 (default): the full-lattice
+ * checkerboard (every half-sweep updates one parity of the whole lattice:
+ * n_hb heat-bath pairs, then n_or over-relaxation pairs). chain = 1: the
+ * tile-local chain of the double checkerboard decomposition (the paper's
+ * implementation section and its numbered Monte Carlo procedure): the lattice
+ * is cut into tiles of L x tile_y x tile_z sites (0 = L, whole rows along x);
+ * every lattice size must have L % 4 == 0, tile edges dividing L and L / edge
+ * either 1 or even. A sweep visits the tiles of coarse parity
+ * (Y + Z) mod 2 = 0, then those of parity 1; on a visit the tile gets n_hit
+ * repetitions of n_or over-relaxation rounds followed by n_hb heat-bath rounds
+ * (a round: even sites, then odd sites), with the sites outside the tile held
+ * fixed; heat-bath round b of repetition r uses repetition index r n_hb + b of
+ * the counter map (n_hit n_hb <= 16). Then the exact energies and tempering.
+ * A different chain with the same stationary distribution; results do not
+ * depend on launch choices. Not part of the checkpoint state: set it again
+ * after resuming. Errors: HSG_E_INVALID for bad shapes, HSG_E_UNSUPPORTED when
+ * a tile does not fit one work-group (at most 1024 site pairs per parity and
+ * 64 KiB of staged spins per replica). */
+hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t tile_z, int32_t n_hit);
+
 /* Autotuner of the launch configuration (the batching row of the method: tile
  * shape and fusion per lattice size). Times n_sweeps (1..1000) whole sweeps of
  * each distinct kernel variant of hsg_set_kernel (and, where lattices use the

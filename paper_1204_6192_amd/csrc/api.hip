@@ -75,6 +75,9 @@ struct Group {
     // z-march geometry (L divisible by 4), see hsg::StreamArgs
     bool stream_ok;
     int32_t s_TY, s_RB, s_rows, s_ytiles, s_zslabs;
+    // tile-local chain geometry, see hsg::TileArgs (set by hsg_set_chain)
+    int32_t t_TY, t_TZ, t_BY, t_BZ, t_hy, t_hz, t_RY, t_RZ, t_P, t_RB, t_chunks, t_threads;
+    size_t t_lds;
 };
 
 // Work-group shape of the z-march for lattice size L (L % 4 == 0): the whole
@@ -238,6 +241,8 @@ struct hsg_lattice {
     int32_t slots_per_item = 0;
     int32_t kernel_variant = 0;  // 0 automatic (= 3), 1 gather, 2 z-march, 3 z-march with fused pairs
     bool hw_math = false;        // heat bath with the hardware transcendentals (kernel kind 2)
+    // Markov chain: 0 the full-lattice checkerboard, 1 the tile-local chain
+    int32_t chain = 0, tile_y = 0, tile_z = 0, n_hit = 1;
     bool have_energies = false;
     // hipGraph replay of whole sweeps (tempering every sweep or never)
     bool use_graphs = true;
@@ -479,8 +484,95 @@ bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign -
 // All launches of one sweep, kernels only (capturable): heat-bath pairs,
 // over-relaxation pairs with the energy fused into the last pass, tempering,
 // then the device sweep counter advances.
+// Exact energies of every replica into E (full recomputation), all groups.
+hsg_status run_energy(hsg_lattice *h, hipStream_t s)
+{
+    for (const Group &g : h->lay.g) {
+        hsg::EnergyArgs a{};
+        a.spins = h->state + g.o_spins;
+        a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+        a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+        a.partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+        a.Nh = g.Nh;
+        a.n_rep = g.n_rep;
+        a.L = g.L;
+        a.Lh = g.L / 2;
+        a.slots_per_sample = g.O * g.T;
+        a.n_pb = g.n_pb_site;
+        hipError_t e = hsg::launch_energy(a, h->storage, s);
+        if (e == hipSuccess)
+            e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
+        if (e != hipSuccess) return hip_fail(e, "energy launch");
+    }
+    return HSG_OK;
+}
+
+int32_t tiles_in_phase(const Group &g, int phase)
+{
+    if (g.t_BY > 1) return g.t_BZ * (g.t_BY / 2);
+    if (g.t_BZ > 1) return g.t_BZ / 2;
+    return phase == 0 ? 1 : 0;
+}
+
+// One sweep of the tile-local chain: the tiles of coarse parity 0, then 1.
+hsg_status run_tile_sweep(hsg_lattice *h, hipStream_t s)
+{
+    for (int phase = 0; phase < 2; ++phase)
+        for (const Group &g : h->lay.g) {
+            const int32_t nt = tiles_in_phase(g, phase);
+            if (nt == 0) continue;
+            hsg::TileArgs a{};
+            a.spins = h->state + g.o_spins;
+            a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+            a.Jbits = g.ckind == 1 ? reinterpret_cast<const uint8_t *>(h->coup + g.o_Jbits) : nullptr;
+            a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+            a.temp_of_slot = reinterpret_cast<const int32_t *>(h->state + g.o_tos);
+            a.beta32 = reinterpret_cast<const float *>(h->coup + g.o_b32);
+            a.tptr = dev_counter(h);
+            a.Nh = g.Nh;
+            a.L = g.L;
+            a.Lh = g.L / 2;
+            a.TY = g.t_TY;
+            a.TZ = g.t_TZ;
+            a.BY = g.t_BY;
+            a.BZ = g.t_BZ;
+            a.hy = g.t_hy;
+            a.hz = g.t_hz;
+            a.RY = g.t_RY;
+            a.RZ = g.t_RZ;
+            a.P = g.t_P;
+            a.RB = g.t_RB;
+            a.n_chunks = g.t_chunks;
+            a.phase = phase;
+            a.n_tiles_phase = nt;
+            const int64_t nb = (int64_t)g.D * nt * g.t_chunks;
+            if (nb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
+            a.n_blocks = (int32_t)nb;
+            a.n_or = h->n_or;
+            a.n_hb = h->n_hb;
+            a.n_hit = h->n_hit;
+            a.slots_per_sample = g.O * g.T;
+            a.T = g.T;
+            a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+            a.key1 = (uint32_t)(h->seed >> 32);
+            a.uid_base = g.uid_base;
+            const hipError_t e = hsg::launch_tile_visit(a, h->storage, g.field, g.ckind == 1, h->hw_math,
+                                                        (unsigned)g.t_threads, g.t_lds, s);
+            if (e != hipSuccess) return hip_fail(e, "tile launch");
+        }
+    return run_energy(h, s);
+}
+
 hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
 {
+    if (h->chain == 1) {
+        hsg_status st = run_tile_sweep(h, s);
+        if (st == HSG_OK && pt) st = run_pt(h, 0u, 1u, s);
+        if (st != HSG_OK) return st;
+        const hipError_t e = hsg::launch_advance(dev_counter(h), s);
+        if (e != hipSuccess) return hip_fail(e, "counter launch");
+        return HSG_OK;
+    }
     const int last_kind = h->n_or > 0 ? 1 : 0;
     for (int r = 0; r < h->n_hb; ++r) {
         hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s);
@@ -978,6 +1070,58 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
     if (st != HSG_OK) return st;
     if (variant_out) *variant_out = h->kernel_variant;
     if (slots_out) *slots_out = h->slots_per_item;
+    return HSG_OK;
+}
+
+hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t tile_z, int32_t n_hit)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (chain != 0 && chain != 1) return fail(HSG_E_INVALID, "chain = %d, need 0 or 1", chain);
+    if (chain == 0) {
+        h->chain = 0;
+        drop_graphs(h);
+        return HSG_OK;
+    }
+    if (tile_y < 0 || tile_z < 0) return fail(HSG_E_INVALID, "tile edges must be >= 0");
+    if (n_hit < 1 || n_hit * h->n_hb > 16)
+        return fail(HSG_E_INVALID, "n_hit = %d: need n_hit >= 1 and n_hit * n_hb <= 16", n_hit);
+    std::vector<Group> gs = h->lay.g;
+    for (size_t k = 0; k < gs.size(); ++k) {
+        Group &g = gs[k];
+        const int L = g.L;
+        if (L % 4 != 0) return fail(HSG_E_UNSUPPORTED, "group %zu: the tile chain needs L %% 4 == 0 (L = %d)", k, L);
+        const int ty = tile_y == 0 ? L : tile_y, tz = tile_z == 0 ? L : tile_z;
+        if (ty > L || tz > L || L % ty != 0 || L % tz != 0)
+            return fail(HSG_E_INVALID, "group %zu: tile edges %d, %d must divide L = %d", k, ty, tz, L);
+        const int by = L / ty, bz = L / tz;
+        if ((by != 1 && (by & 1)) || (bz != 1 && (bz & 1)))
+            return fail(HSG_E_INVALID, "group %zu: L / tile edge must be 1 or even (L = %d, tiles %d, %d)", k, L, ty, tz);
+        g.t_TY = ty;
+        g.t_TZ = tz;
+        g.t_BY = by;
+        g.t_BZ = bz;
+        g.t_hy = by > 1 ? 1 : 0;
+        g.t_hz = bz > 1 ? 1 : 0;
+        g.t_RY = ty + 2 * g.t_hy;
+        g.t_RZ = tz + 2 * g.t_hz;
+        g.t_P = tz * ty * (L / 4);
+        const size_t per_rep = (size_t)2 * 3 * g.t_RZ * g.t_RY * (L / 2) * sizeof(float);
+        if (g.t_P > 1024 || per_rep > 64 * 1024)
+            return fail(HSG_E_UNSUPPORTED, "group %zu: tile %d x %d x %d is too large for one work-group", k, L, ty, tz);
+        // replicas per work-group: up to 1024 threads and 64 KiB of LDS
+        int rb = std::min<int64_t>(1024 / g.t_P, (int64_t)(64 * 1024 / per_rep));
+        rb = std::max(1, std::min(rb, g.O * g.T));
+        g.t_RB = rb;
+        g.t_chunks = (g.O * g.T + rb - 1) / rb;
+        g.t_threads = (g.t_P * rb + 63) / 64 * 64;
+        g.t_lds = per_rep * rb;
+    }
+    h->lay.g = gs;
+    h->chain = 1;
+    h->tile_y = tile_y;
+    h->tile_z = tile_z;
+    h->n_hit = n_hit;
+    drop_graphs(h);
     return HSG_OK;
 }
 

@@ -56,6 +56,30 @@ struct StreamArgs {
     uint32_t rep, parity;
     uint32_t key0, key1, uid_base;
 };
+// Tile-local chain: one launch visits every tile of coarse parity `phase` of
+// one group. Tiles are L x TY x TZ sites; BY = L / TY, BZ = L / TZ tiles per
+// axis; hy, hz = 1 when that axis is tiled (one halo row / plane), else 0;
+// RY = TY + 2 hy, RZ = TZ + 2 hz staged rows and planes; P = TZ TY L / 4 site
+// pairs per parity of a tile; RB replicas of one sample per work-group, in
+// n_chunks chunks per sample. Blocks: [sample][tile of the phase][chunk].
+struct TileArgs {
+    void *spins;
+    const float *J6;
+    const uint8_t *Jbits;
+    const float *Hp;
+    const int32_t *temp_of_slot;
+    const float *beta32;
+    const uint32_t *tptr;
+    int64_t Nh;
+    int32_t L, Lh, TY, TZ, BY, BZ, hy, hz, RY, RZ, P, RB, n_chunks;
+    int32_t phase, n_tiles_phase, n_blocks;
+    int32_t n_or, n_hb, n_hit;
+    int32_t slots_per_sample, T;
+    uint32_t key0, key1, uid_base;
+};
+hipError_t launch_tile_visit(const TileArgs &a, int storage, bool field, bool jb, bool hw, unsigned threads,
+                             size_t lds, hipStream_t s);
+
 // Up to kMaxStreamGroups lattice-size groups in one launch: group k owns the
 // blocks [block_start[k], block_start[k + 1]).
 constexpr int kMaxStreamGroups = 8;

@@ -285,47 +285,6 @@ __device__ __forceinline__ double update_pair(const float *lds, int lo, int cstr
     return e;
 }
 
-__device__ __forceinline__ void lds_put_pair(float *lds, int w, int cstride, v3 a, v3 b)
-{
-    *reinterpret_cast<float2 *>(&lds[w]) = make_float2(a.x, b.x);
-    *reinterpret_cast<float2 *>(&lds[w + cstride]) = make_float2(a.y, b.y);
-    *reinterpret_cast<float2 *>(&lds[w + 2 * cstride]) = make_float2(a.z, b.z);
-}
-
-__device__ __forceinline__ void lds_get_pair(const float *lds, int w, int cstride, v3 &a, v3 &b)
-{
-    const float2 x = *reinterpret_cast<const float2 *>(&lds[w]);
-    const float2 y = *reinterpret_cast<const float2 *>(&lds[w + cstride]);
-    const float2 z = *reinterpret_cast<const float2 *>(&lds[w + 2 * cstride]);
-    a = v3{x.x, y.x, z.x};
-    b = v3{x.y, y.y, z.y};
-}
-
-template <bool JB, bool FIELD>
-__device__ __forceinline__ void load_couplings(const float *Jb, const uint8_t *Jbb, const float *Hb, bool jbits,
-                                               bool field, uint32_t Nh, uint32_t j0, float2 (&jc)[6], v3 &hs0,
-                                               v3 &hs1)
-{
-    if (JB && jbits) {
-        const uint32_t bits = *reinterpret_cast<const uint16_t *>(Jbb + j0);
-#pragma unroll
-        for (int n = 0; n < 6; ++n)
-            jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
-    } else {
-#pragma unroll
-        for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
-    }
-    hs0 = v3{0.f, 0.f, 0.f};
-    hs1 = v3{0.f, 0.f, 0.f};
-    if (FIELD && field) {
-        const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
-        const float2 hy = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
-        const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
-        hs0 = v3{hx.x, hy.x, hz.x};
-        hs1 = v3{hx.y, hy.y, hz.y};
-    }
-}
-
 // Both half-sweeps of a pair (parity 0, then parity 1, of the same kind) in one
 // z-march over whole planes (TY = L). At step z, stage A updates the parity-0
 // sites of plane z from the old parity-1 planes z - 1, z, z + 1; stage B then

@@ -1,0 +1,303 @@
+// tile_chain.hip -- the tile-local chain of the double checkerboard decomposition.
+//
+// The lattice is cut into tiles of L x TY x TZ sites: whole rows along x (so
+// every row of a tile is one contiguous run of each parity array), TY rows and
+// TZ planes. Tiles carry the coarse parity (Y + Z) mod 2 of their tile
+// coordinates; with L / TY and L / TZ each 1 or even, tiles of one coarse
+// parity never share a face. One launch visits every tile of one coarse
+// parity of every replica of a group. A work-group stages RB replicas of one
+// sample's tile, with a one-site halo in y and z, in LDS (both parities), then
+// runs n_hit repetitions of n_or over-relaxation rounds and n_hb heat-bath
+// rounds, a round being the even sites of the tile, then the odd sites (the
+// numbered procedure of the paper's implementation section, with the tile
+// loaded once per visit). The halo belongs to tiles of the other coarse parity,
+// which no work-group of this launch changes. Finally the tile's own sites are
+// written back. A thread owns one pair of neighbouring sites (x/2 = 2m, 2m + 1)
+// of each parity in one replica and keeps their couplings (and field) in
+// registers for the whole visit.
+//
+// What LDS holds per codec: float32 spins as they are; float16 / bfloat16 the
+// decoded (exactly representable) components of the stored code, renormalised
+// whenever read, so the final store writes exactly the code of the last update;
+// quantised angles the decoded unit vector (the octahedral projection divides by
+// the L1 norm, so re-encoding it gives back its code).
+#include "device.h"
+#include "kernels.h"
+
+namespace hsg {
+
+template <int STORE>
+struct TileRep;
+
+template <>
+struct TileRep<0> {
+    __device__ static __forceinline__ v3 after_update(v3 s) { return s; }
+    __device__ static __forceinline__ v3 read(v3 v) { return v; }
+    __device__ static __forceinline__ void load_pair(const float *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
+    {
+        Codec<0>::load_pair(p, cs, j0, a, b);
+    }
+};
+
+template <>
+struct TileRep<1> {
+    __device__ static __forceinline__ v3 after_update(v3 s)
+    {
+        return v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
+                  __half2float(__float2half_rn(s.z))};
+    }
+    __device__ static __forceinline__ v3 read(v3 v) { return normalise_rsq(v); }
+    __device__ static __forceinline__ void load_pair(const __half *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
+    {
+        const __half2 x = *reinterpret_cast<const __half2 *>(p + j0);
+        const __half2 y = *reinterpret_cast<const __half2 *>(p + cs + j0);
+        const __half2 z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
+        a = v3{__low2float(x), __low2float(y), __low2float(z)};
+        b = v3{__high2float(x), __high2float(y), __high2float(z)};
+    }
+};
+
+template <>
+struct TileRep<2> {
+    __device__ static __forceinline__ v3 after_update(v3 s)
+    {
+        return v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
+                  bf16_to_f32(f32_to_bf16_rne(s.z))};
+    }
+    __device__ static __forceinline__ v3 read(v3 v) { return normalise_rsq(v); }
+    __device__ static __forceinline__ void load_pair(const uint16_t *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
+    {
+        const uint32_t x = *reinterpret_cast<const uint32_t *>(p + j0);
+        const uint32_t y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
+        const uint32_t z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
+        a = v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)};
+        b = v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u), __uint_as_float(z & 0xFFFF0000u)};
+    }
+};
+
+template <>
+struct TileRep<3> {
+    __device__ static __forceinline__ v3 after_update(v3 s) { return oct_decode(oct_encode(s)); }
+    __device__ static __forceinline__ v3 read(v3 v) { return v; }
+    __device__ static __forceinline__ void load_pair(const uint32_t *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
+    {
+        Codec<3>::load_pair(p, cs, j0, a, b);
+    }
+};
+
+// Tile coordinates (Y, Z) of the q-th tile of coarse parity `phase`, in the
+// order Z, then Y.
+__device__ __forceinline__ void phase_tile(int q, int phase, int BY, int &Y, int &Z)
+{
+    if (BY > 1) {
+        const int per = BY / 2;
+        Z = q / per;
+        Y = 2 * (q - Z * per) + ((Z + phase) & 1);
+    } else {
+        Y = 0;
+        Z = 2 * q + phase;
+    }
+}
+
+template <int STORE, int KIND>
+__device__ __forceinline__ void pair_update(const v3 (&nb0)[6], const v3 (&nb1)[6], const float2 (&jc)[6], v3 hs0,
+                                            v3 hs1, v3 old0, v3 old1, u32x4 rr, float beta, bool hw, v3 &s0,
+                                            v3 &s1)
+{
+    v3 h0 = hs0, h1 = hs1;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        acc3(h0, jc[n].x, nb0[n]);
+        acc3(h1, jc[n].y, nb1[n]);
+    }
+    if (KIND == 1) {
+        s0 = over_relax(old0, h0);
+        s1 = over_relax(old1, h1);
+    } else if (hw) {
+        s0 = heat_bath<true>(h0, beta, rr.x, rr.y);
+        s1 = heat_bath<true>(h1, beta, rr.z, rr.w);
+    } else {
+        s0 = heat_bath<false>(h0, beta, rr.x, rr.y);
+        s1 = heat_bath<false>(h1, beta, rr.z, rr.w);
+    }
+}
+
+template <int STORE, bool FIELD, bool JB, bool HW>
+__global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
+{
+    extern __shared__ float lds[];  // [RB][parity][3][RZ][RY][Lh]
+    using C = Codec<STORE>;
+    using R = TileRep<STORE>;
+    using T = typename C::T;
+    const int b = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+    const int chunk = b % a.n_chunks;
+    const int rest = b / a.n_chunks;
+    const int q = rest % a.n_tiles_phase;
+    const int d = rest / a.n_tiles_phase;  // sample
+    int Y, Z;
+    phase_tile(q, a.phase, a.BY, Y, Z);
+    const int y0 = Y * a.TY, z0 = Z * a.TZ;
+    const int L = a.L, Lh = a.Lh, RY = a.RY, RZ = a.RZ;
+    const uint32_t Nh = (uint32_t)a.Nh;
+    const int cs = RZ * RY * Lh;  // floats per component of one parity of one replica
+    const int tid = threadIdx.x;
+    const int P = a.P;  // site pairs per parity of the tile
+    const int rb = tid / P;
+    const int qp = tid - rb * P;
+    const int sis = chunk * a.RB + rb;  // replica within the sample
+    const bool active = rb < a.RB && sis < a.slots_per_sample;
+    const int64_t r = (int64_t)d * a.slots_per_sample + (active ? sis : 0);
+    T *base = (T *)a.spins + r * 2 * C::kPlanes * (int64_t)Nh;
+
+    // stage the tile and its halo, both parities, of every replica of the block
+    const int Lq = Lh / 2;  // site pairs per row and parity
+    const int n_pairs = a.RB * 2 * RZ * RY * Lq;
+    for (int e = tid; e < n_pairs; e += blockDim.x) {
+        int k = e;
+        const int xp = k % Lq;
+        k /= Lq;
+        const int ly = k % RY;
+        k /= RY;
+        const int lz = k % RZ;
+        k /= RZ;
+        const int par = k & 1;
+        const int rr = k >> 1;
+        if (chunk * a.RB + rr >= a.slots_per_sample) continue;
+        int y = y0 - a.hy + ly, z = z0 - a.hz + lz;
+        y = y < 0 ? y + L : (y >= L ? y - L : y);
+        z = z < 0 ? z + L : (z >= L ? z - L : z);
+        const int64_t rep = (int64_t)d * a.slots_per_sample + chunk * a.RB + rr;
+        const T *src = (const T *)a.spins + (rep * 2 + par) * C::kPlanes * (int64_t)Nh;
+        v3 s0, s1;
+        R::load_pair(src, Nh, (uint32_t)((z * L + y) * Lh + 2 * xp), s0, s1);
+        lds_put_pair(lds, ((rr * 2 + par) * 3 * RZ + lz) * RY * Lh + ly * Lh + 2 * xp, cs, s0, s1);
+    }
+
+    // my pair, its couplings and field (both parities)
+    const int xh0 = 2 * (qp % Lq);
+    const int lyi = (qp / Lq) % a.TY, lzi = qp / (Lq * a.TY);
+    const int y = y0 + lyi, z = z0 + lzi;
+    const int ly = lyi + a.hy, lz = lzi + a.hz;
+    const int lym = ly == 0 ? RY - 1 : ly - 1, lyp = ly + 1 == RY ? 0 : ly + 1;  // wrap only without halo
+    const int lzm = lz == 0 ? RZ - 1 : lz - 1, lzp = lz + 1 == RZ ? 0 : lz + 1;
+    const uint32_t j0 = (uint32_t)((z * L + y) * Lh + xh0);
+    float2 jc[2][6];
+    v3 hs[2][2];
+    float beta = 0.0f;
+    uint32_t c2 = 0, uid = a.uid_base + (uint32_t)d;
+    if (active) {
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const float *Jb = a.J6 + ((int64_t)d * 2 + par) * 6 * (int64_t)Nh;
+            const uint8_t *Jbb = JB ? a.Jbits + ((int64_t)d * 2 + par) * (int64_t)Nh : nullptr;
+            const float *Hb = FIELD ? a.Hp + ((int64_t)d * 2 + par) * 3 * (int64_t)Nh : nullptr;
+            load_couplings<JB, FIELD>(Jb, Jbb, Hb, JB, FIELD, Nh, j0, jc[par], hs[par][0], hs[par][1]);
+        }
+        beta = a.beta32[a.temp_of_slot[r]];
+        const int o = sis / a.T, ts = sis - o * a.T;
+        c2 = (uint32_t)ts | ((uint32_t)o << 8);
+    } else {
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+#pragma unroll
+            for (int n = 0; n < 6; ++n) jc[par][n] = make_float2(0.f, 0.f);
+            hs[par][0] = hs[par][1] = v3{0.f, 0.f, 0.f};
+        }
+    }
+    const uint32_t tsweep = *a.tptr;
+    __syncthreads();
+
+    auto at = [&](int par, int pz, int py, int xh) { return ((rb * 2 + par) * 3 * RZ + pz) * RY * Lh + py * Lh + xh; };
+    auto rd = [&](int w) { return R::read(v3{lds[w], lds[w + cs], lds[w + 2 * cs]}); };
+    auto half_round = [&](int kind, int p, uint32_t rep) {
+        if (active) {
+            const int qo = 1 - p;
+            const int o = (y + z + p) & 1;  // x = 2 x/2 + o on this row
+            const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
+            const v3 c0 = rd(at(qo, lz, ly, xh0)), c1 = rd(at(qo, lz, ly, xh0 + 1)), ex = rd(at(qo, lz, ly, xe));
+            const v3 ym0 = rd(at(qo, lz, lym, xh0)), ym1 = rd(at(qo, lz, lym, xh0 + 1));
+            const v3 yp0 = rd(at(qo, lz, lyp, xh0)), yp1 = rd(at(qo, lz, lyp, xh0 + 1));
+            const v3 zm0 = rd(at(qo, lzm, ly, xh0)), zm1 = rd(at(qo, lzm, ly, xh0 + 1));
+            const v3 zp0 = rd(at(qo, lzp, ly, xh0)), zp1 = rd(at(qo, lzp, ly, xh0 + 1));
+            v3 nb0[6], nb1[6];  // neighbours in the order +x, -x, +y, -y, +z, -z
+            if (o) {
+                nb0[0] = c1; nb0[1] = c0;
+                nb1[0] = ex; nb1[1] = c1;
+            } else {
+                nb0[0] = c0; nb0[1] = ex;
+                nb1[0] = c1; nb1[1] = c0;
+            }
+            nb0[2] = yp0; nb1[2] = yp1;
+            nb0[3] = ym0; nb1[3] = ym1;
+            nb0[4] = zp0; nb1[4] = zp1;
+            nb0[5] = zm0; nb1[5] = zm1;
+            const int w = at(p, lz, ly, xh0);
+            v3 s0, s1;
+            if (kind == 1) {
+                const v3 old0 = rd(w), old1 = rd(w + 1);
+                pair_update<STORE, 1>(nb0, nb1, jc[p], hs[p][0], hs[p][1], old0, old1, u32x4{0u, 0u, 0u, 0u}, beta,
+                                      false, s0, s1);
+            } else {
+                const u32x4 rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2 | (rep << 12) | ((uint32_t)p << 16), uid},
+                                               a.key0, a.key1);
+                pair_update<STORE, 0>(nb0, nb1, jc[p], hs[p][0], hs[p][1], v3{}, v3{}, rr, beta, HW, s0, s1);
+            }
+            lds_put_pair(lds, w, cs, R::after_update(s0), R::after_update(s1));
+        }
+        __syncthreads();
+    };
+
+    for (int h = 0; h < a.n_hit; ++h) {
+        for (int m = 0; m < a.n_or; ++m) {
+            half_round(1, 0, 0u);
+            half_round(1, 1, 0u);
+        }
+        for (int bb = 0; bb < a.n_hb; ++bb) {
+            const uint32_t rep = (uint32_t)(h * a.n_hb + bb);
+            half_round(0, 0, rep);
+            half_round(0, 1, rep);
+        }
+    }
+
+    // write back my two sites of each parity
+    if (active) {
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            v3 s0, s1;
+            lds_get_pair(lds, at(par, lz, ly, xh0), cs, s0, s1);
+            C::store_pair(base + (int64_t)par * C::kPlanes * Nh, Nh, j0, s0, s1);
+        }
+    }
+}
+
+template <int STORE>
+static hipError_t launch_tile_s(const TileArgs &a, bool field, bool jb, bool hw, unsigned threads, size_t lds,
+                                hipStream_t s)
+{
+    const dim3 grid((unsigned)a.n_blocks), block(threads);
+#define HSG_T(F, J, H) hipLaunchKernelGGL((k_tile_visit<STORE, F, J, H>), grid, block, lds, s, a)
+    if (hw) {
+        if (field) { if (jb) HSG_T(true, true, true); else HSG_T(true, false, true); }
+        else { if (jb) HSG_T(false, true, true); else HSG_T(false, false, true); }
+    } else {
+        if (field) { if (jb) HSG_T(true, true, false); else HSG_T(true, false, false); }
+        else { if (jb) HSG_T(false, true, false); else HSG_T(false, false, false); }
+    }
+#undef HSG_T
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_visit(const TileArgs &a, int storage, bool field, bool jb, bool hw, unsigned threads,
+                             size_t lds, hipStream_t s)
+{
+    if (threads == 0 || threads > 1024 || a.n_blocks <= 0) return hipErrorInvalidValue;
+    switch (storage) {
+    case 0: return launch_tile_s<0>(a, field, jb, hw, threads, lds, s);
+    case 1: return launch_tile_s<1>(a, field, jb, hw, threads, lds, s);
+    case 2: return launch_tile_s<2>(a, field, jb, hw, threads, lds, s);
+    case 3: return launch_tile_s<3>(a, field, jb, hw, threads, lds, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace hsg

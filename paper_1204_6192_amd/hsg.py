@@ -91,6 +91,7 @@ _SIG = {
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "hsg_set_chain": [_vp, _i32, _i32, _i32, _i32],
     "hsg_set_math": [_vp, _i32],
     "hsg_set_graphs": [_vp, _i32],
     "hsg_sync": [_vp, _vp],
@@ -283,6 +284,11 @@ class Lattice:
                                C.byref(v), C.byref(c), _stream(self.stream)))
         del backup
         return v.value, c.value
+
+    def set_chain(self, chain: int, tile_y: int = 0, tile_z: int = 0, n_hit: int = 1) -> None:
+        """0: full-lattice checkerboard (default); 1: the tile-local chain with tiles
+        of L x tile_y x tile_z sites (0 = L) and n_hit repetitions per visit."""
+        check(lib.hsg_set_chain(self.h, int(chain), int(tile_y), int(tile_z), int(n_hit)))
 
     def set_math(self, mode: int) -> None:
         """0: library transcendentals in the heat bath (default); 1: hardware ones."""

@@ -125,7 +125,7 @@ def _rms(a):
 
 
 def _trajectory(hsg, oracle_lib, inst, n_sweeps, storage="f32", spin_tol=TOL_SPIN,
-                shadow_factor=SHADOW_FACTOR, math=0):
+                shadow_factor=SHADOW_FACTOR, math=0, tiles=None):
     """GPU vs oracle over n_sweeps from the same seeded start.
 
     The chain amplifies any difference in the spins by roughly an order of
@@ -151,8 +151,14 @@ def _trajectory(hsg, oracle_lib, inst, n_sweeps, storage="f32", spin_tol=TOL_SPI
     lat.set_math(math)
     kw = dict(seed=inst.seed, n_hb=inst.n_hb, n_or=inst.n_or, pt_every=inst.pt_every,
               storage=storage)
-    orcs = [oracle_lib.Oracle.from_group(g, **kw) for g in inst.groups]
-    refs = [_references(oracle_lib, g, kw, N_REFS, k + 1) for k, g in enumerate(inst.groups)]
+    kws = [dict(kw) for _ in inst.groups]
+    if tiles is not None:  # (tile_y, tile_z, n_hit) of the tile-local chain, 0 = L
+        ty, tz, n_hit = tiles
+        lat.set_chain(1, ty, tz, n_hit)
+        for g, k in zip(inst.groups, kws):
+            k.update(tiles=(g.L, ty or g.L, tz or g.L), n_hit=n_hit)
+    orcs = [oracle_lib.Oracle.from_group(g, **k) for g, k in zip(inst.groups, kws)]
+    refs = [_references(oracle_lib, g, k, N_REFS, i + 1) for i, (g, k) in enumerate(zip(inst.groups, kws))]
     maps_track = [True] * len(inst.groups)
     for t in range(n_sweeps):
         lat.sweep(1)
@@ -231,6 +237,61 @@ def test_trajectory_hardware_math(hsg, oracle_lib, field):
                           field=("gaussian", 0.2) if field else None)
     inst = inputs.Instance(groups=[g], seed=inputs.PHILOX_KEY_BASE + 43, n_hb=2, n_or=2)
     _trajectory(hsg, oracle_lib, inst, 10, math=1)
+
+
+# ---------------------------------------------------------------- tile-local chain
+@pytest.mark.parametrize("tiles,n_hb,n_or", [((4, 4, 1), 1, 4), ((2, 4, 2), 1, 2), ((0, 4, 1), 2, 3)])
+def test_tile_chain_trajectory(hsg, oracle_lib, tiles, n_hb, n_or):
+    """The tile-local chain against the oracle's: tiles of L x 4 x 4, 2 x 4 with
+    two repetitions per visit, and whole planes (y untiled) with two heat-bath
+    rounds; a field on half the cases."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 44))
+    g = inputs.make_group(rng, 8, 2, 2, inputs.geometric_ladder(0.1, 0.3, 5),
+                          field=("gaussian", 0.2) if n_or == 2 else None)
+    inst = inputs.Instance(groups=[g], seed=inputs.PHILOX_KEY_BASE + 44, n_hb=n_hb, n_or=n_or)
+    _trajectory(hsg, oracle_lib, inst, 8, tiles=tiles)
+
+
+def test_tile_chain_uneven_groups_and_storage(hsg, oracle_lib):
+    """Three lattice sizes in one handle (tiles of L x 2 x 2 in every size: 2, 4 and 6
+    tiles per axis) with float16 storage, against the oracle's codec emulation."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 45))
+    groups, uid = [], 0
+    for L, D in ((4, 2), (8, 1), (12, 1)):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, 4),
+                                        sample_uid_base=uid))
+        uid += D
+    inst = inputs.Instance(groups=groups, seed=inputs.PHILOX_KEY_BASE + 45, n_hb=1, n_or=2)
+    _trajectory(hsg, oracle_lib, inst, 6, storage="f16", spin_tol=None, tiles=(2, 2, 1))
+
+
+@pytest.mark.parametrize("n_hb,n_or", [(0, 3), (2, 0)])
+def test_tile_chain_whole_lattice_tile_bit_identical(hsg, n_hb, n_or):
+    """One tile covering the lattice, with a single kind of update, is the
+    full-lattice chain: the tile kernel reproduces the z-march kernels' spins and
+    temperature maps bit for bit (same per-site arithmetic and neighbour order)."""
+    inst = inputs.make_instance("batched", scale_samples=2, L_override=8)
+    a = _lat(hsg, inst.groups, inst.seed, n_hb=n_hb, n_or=n_or)
+    b = _lat(hsg, inst.groups, inst.seed, n_hb=n_hb, n_or=n_or)
+    b.set_chain(1, 0, 0, 1)
+    a.sweep(4)
+    b.sweep(4)
+    assert torch.equal(a.get_spins(), b.get_spins())
+    assert torch.equal(a.get_temp_map(), b.get_temp_map())
+    assert torch.allclose(a.get_energies(), b.get_energies(), rtol=1e-12, atol=1e-9)
+
+
+def test_tile_chain_rejects_bad_shapes(hsg):
+    inst = inputs.make_instance("tiny")
+    lat = _lat(hsg, inst.groups, inst.seed)
+    for ty, tz, n_hit in ((3, 4, 1), (8, 16, 1), (4, 4, 0), (4, 4, 17)):
+        with pytest.raises(RuntimeError):
+            lat.set_chain(1, ty, tz, n_hit)
+    # L = 8 with tiles 8 x 8 x (8 / 4 = 2 tiles): fine; and back to the full lattice
+    lat.set_chain(1, 0, 4, 1)
+    lat.sweep(1)
+    lat.set_chain(0)
+    lat.sweep(1)
 
 
 def test_batched_L32_two_samples(hsg, oracle_lib):
