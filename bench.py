@@ -156,6 +156,9 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=40)
+    ap.add_argument("--tiles", type=str, default=None,
+                    help="run the tile-local chain instead of the full-lattice one: TY,TZ,NHIT "
+                         "(tiles of L x TY x TZ sites, 0 = L; NHIT repetitions per visit)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a plain copy "
                          "kernel of known size, to scale hardware byte counters)")
@@ -180,6 +183,11 @@ def main():
         f"storage {inst.storage}; inputs in {time.perf_counter() - t_gen:.1f} s")
     lat = hsg.Lattice(inst.groups, storage=inst.storage, n_hb=inst.n_hb, n_or=inst.n_or,
                       pt_every=inst.pt_every, seed=inst.seed)
+    n_hit = 1
+    if args.tiles:
+        ty, tz, n_hit = (int(v) for v in args.tiles.split(","))
+        lat.set_chain(1, ty, tz, n_hit)
+        log(f"tile-local chain: tiles of L x {ty or 'L'} x {tz or 'L'}, {n_hit} repetition(s) per visit")
     torch.cuda.synchronize()
 
     if args.calibrate_copy_mib > 0:
@@ -208,7 +216,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lat.sync()
-    updates = args.steps * (inst.n_hb + inst.n_or) * lat.n_spins
+    updates = args.steps * n_hit * (inst.n_hb + inst.n_or) * lat.n_spins
     ns_update = dt / updates * 1e9
     log(f"{args.steps} sweeps in {dt:.3f} s: {ns_update * 1e3:.2f} ps/update")
 
@@ -239,6 +247,9 @@ def main():
            "t_range": [float(inst.groups[0].temps[0]), float(inst.groups[0].temps[-1])],
            "couplings": "bimodal" if inst.groups[0].coupling_kind else "gaussian",
            "field": inst.groups[0].H is not None, "storage": inst.storage,
+           "chain": ("full-lattice checkerboard" if not args.tiles else
+                     f"tile-local, tiles L x {args.tiles.split(',')[0]} x {args.tiles.split(',')[1]} "
+                     f"(0 = L), {n_hit} x ({inst.n_or} OR + {inst.n_hb} HB) per visit"),
            "sweep": f"{inst.n_hb} HB + {inst.n_or} OR + PT every {inst.pt_every}"
                     + (f" + overlap every {overlap_every}" if overlap_every else ""),
            "field_amp": None if inst.groups[0].H is None else float(
@@ -266,6 +277,11 @@ def main():
                      "device_copy_gbs": copy_gbs, "frac_of_copy": gbs_or / copy_gbs},
         "cpu_baseline": cpu,
     }
+    if args.tiles:
+        # the tile-local chain's kernel is VALU-bound; the HBM roofline above is the
+        # full-lattice chain's over-relaxation pair, so it is not this run's
+        out["roofline"] = None
+        out["effective_gbs"] = None
     print(json.dumps(out), flush=True)
 
 
