@@ -21,6 +21,10 @@ Functions and what pins them (details in the tests):
                            mixes), tile-order independence, a plain-Python replay
                            of the visiting order on a small lattice, and the
                            closed forms above;
+* ``Oracle.measure_kmodes`` -- an FFT of the product fields, the k = 0 overlap,
+                           the chirality of a conical spiral in closed form,
+                           O(3) behaviour (proper rotations keep, reflections
+                           flip the chiral part);
 * ``Oracle.pt_exchange``-- acceptance frequency against min(1, e^Delta);
 * ``Oracle.measure_overlap`` -- q^2 = 1 for identical aligned copies, O(3)
                            invariance, trace identity.
@@ -94,6 +98,7 @@ def lib():
         L.hsgo_tile_sweep.argtypes = [P(Cfg), P(Tiles), dp, dp, dp, i32p, dp, dp, u64p, C.c_int,
                                       u64p, i64p]
         L.hsgo_tiles_valid.argtypes = [C.c_int, P(Tiles), C.c_int]
+        L.hsgo_kmodes.argtypes = [P(Cfg), dp, i32p, dp]
         L.hsgo_set_storage_mode.argtypes = [C.c_int]
         L.hsgo_store_roundtrip.argtypes = [C.c_int, dp]
         L.hsgo_round_f16.argtypes = [C.c_double]
@@ -340,6 +345,15 @@ class Oracle:
         q = np.zeros((self.cfg.n_samples, self.cfg.n_temps, 10), dtype=np.float64)
         lib().hsgo_overlap(C.byref(self.cfg), _p(self.spins, C.c_double),
                            _p(self.slot_at_temp, C.c_int32), _p(q, C.c_double))
+        return q
+
+    def measure_kmodes(self) -> np.ndarray:
+        """[n_samples][n_temps][84]: q^{mu nu}(k) and the chiral overlaps
+        q_c^alpha(k) between copies 0 and 1 at each rung, for k = 0 and the three
+        smallest wave vectors (layout in hsg_oracle.c)."""
+        q = np.zeros((self.cfg.n_samples, self.cfg.n_temps, 84), dtype=np.float64)
+        lib().hsgo_kmodes(C.byref(self.cfg), _p(self.spins, C.c_double),
+                          _p(self.slot_at_temp, C.c_int32), _p(q, C.c_double))
         return q
 
     def hb_words(self, d, o, slot, rep, parity, i):

@@ -538,6 +538,85 @@ int hsgo_tile_sweep(const hsgo_cfg *c, const hsgo_tiles *tl, const double *J, co
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Wave-vector dependent and chiral overlaps (the analysis quantities of §2).  */
+/* ------------------------------------------------------------------------ */
+/* For every sample d and rung k, between copy 0 (1) and copy 1 (2) at that rung:
+ *   q^{mu nu}(k) = (1/N) sum_i s_i^mu(1) s_i^nu(2) exp(i k.R_i) for k = 0 and
+ *   k = (2 pi / L) e_a, a = x, y, z (the wave-vector dependent overlap of §2);
+ *   kappa_i^alpha = s_{i+alpha} . (s_i x s_{i-alpha}) for alpha = x, y, z, each
+ *   copy (the local chirality of three spins on a line), and
+ *   q_c^alpha(k) = (1/N) sum_i kappa_i^alpha(1) kappa_i^alpha(2) exp(i k.R_i)
+ *   (the chiral overlap, Eq. (12)) at the same four wave vectors.
+ * out[(d T + k) 84 + m]:
+ *   m = 0..8: q^{mu nu}(0), index 3 mu + nu;
+ *   m = 9 + 18 a + 2 (3 mu + nu) + {0, 1}: Re, Im q^{mu nu}(k_a), a = 0, 1, 2 (x, y, z);
+ *   m = 63 + 7 alpha: q_c^alpha(0);
+ *   m = 63 + 7 alpha + 1 + 2 a + {0, 1}: Re, Im q_c^alpha(k_a).
+ * Sums in float64 in the canonical site order. */
+#define HSGO_KMODES 84
+#define HSGO_TWO_PI 6.283185307179586476925286766559
+
+void hsgo_kmodes(const hsgo_cfg *c, const double *spins, const int32_t *slot_at_temp,
+                 double *out)
+{
+    const int L = c->L;
+    const int64_t N = (int64_t)L * L * L;
+    const double w0 = HSGO_TWO_PI / (double)L;
+    for (int d = 0; d < c->n_samples; ++d)
+        for (int k = 0; k < c->n_temps; ++k) {
+            const int32_t s1 = slot_at_temp[((int64_t)d * c->n_copies + 0) * c->n_temps + k];
+            const int32_t s2 = slot_at_temp[((int64_t)d * c->n_copies + 1) * c->n_temps + k];
+            const double *a = slot_ptr(c, (double *)spins, d, 0, s1);
+            const double *b = slot_ptr(c, (double *)spins, d, 1, s2);
+            double acc[HSGO_KMODES];
+            for (int m = 0; m < HSGO_KMODES; ++m) acc[m] = 0.0;
+            for (int z = 0; z < L; ++z)
+                for (int y = 0; y < L; ++y)
+                    for (int x = 0; x < L; ++x) {
+                        const int64_t i = site(L, x, y, z);
+                        const int R[3] = {x, y, z};
+                        double cph[3], sph[3];
+                        for (int ax = 0; ax < 3; ++ax) {
+                            cph[ax] = cos(w0 * R[ax]);
+                            sph[ax] = sin(w0 * R[ax]);
+                        }
+                        for (int mu = 0; mu < 3; ++mu)
+                            for (int nu = 0; nu < 3; ++nu) {
+                                const double f = a[mu * N + i] * b[nu * N + i];
+                                acc[3 * mu + nu] += f;
+                                for (int ax = 0; ax < 3; ++ax) {
+                                    acc[9 + 18 * ax + 2 * (3 * mu + nu)] += f * cph[ax];
+                                    acc[9 + 18 * ax + 2 * (3 * mu + nu) + 1] += f * sph[ax];
+                                }
+                            }
+                        for (int al = 0; al < 3; ++al) {
+                            const int dx = al == 0, dy = al == 1, dz = al == 2;
+                            const int64_t ip = site(L, x + dx, y + dy, z + dz);
+                            const int64_t im = site(L, x - dx, y - dy, z - dz);
+                            double kap[2];
+                            for (int cp = 0; cp < 2; ++cp) {
+                                const double *s = cp ? b : a;
+                                const double u[3] = {s[ip], s[N + ip], s[2 * N + ip]};
+                                const double v[3] = {s[i], s[N + i], s[2 * N + i]};
+                                const double w[3] = {s[im], s[N + im], s[2 * N + im]};
+                                const double cr[3] = {v[1] * w[2] - v[2] * w[1], v[2] * w[0] - v[0] * w[2],
+                                                      v[0] * w[1] - v[1] * w[0]};
+                                kap[cp] = u[0] * cr[0] + u[1] * cr[1] + u[2] * cr[2];
+                            }
+                            const double g = kap[0] * kap[1];
+                            acc[63 + 7 * al] += g;
+                            for (int ax = 0; ax < 3; ++ax) {
+                                acc[63 + 7 * al + 1 + 2 * ax] += g * cph[ax];
+                                acc[63 + 7 * al + 1 + 2 * ax + 1] += g * sph[ax];
+                            }
+                        }
+                    }
+            double *o = out + ((int64_t)d * c->n_temps + k) * HSGO_KMODES;
+            for (int m = 0; m < HSGO_KMODES; ++m) o[m] = acc[m] / (double)N;
+        }
+}
+
 /* Edwards-Anderson overlap, Eq. (5), between copies 0 and 1 at every rung:
  * q[d][k][3 mu + nu] = (1/N) sum_i s_i^mu(copy 0) s_i^nu(copy 1), q[d][k][9] =
  * sum over mu, nu of q^2. */
