@@ -158,6 +158,23 @@ hsg_status hsg_get_energies(const hsg_lattice *h, double *d_E, hsg_stream_t stre
  * q^2 = sum of the nine squares. Requires n_copies >= 2 in every group. */
 hsg_status hsg_measure_overlap(hsg_lattice *h, double *d_q, hsg_stream_t stream);
 
+/* Wave-vector dependent spin-glass overlap and chiral overlap (the analysis
+ * quantities of the paper's model section: the overlap q^{mu nu}(k) entering
+ * chi_SG(k) and the correlation length, Eqs. (6)-(8), and the chiral overlap
+ * of Eq. (12) built from kappa_i^alpha = s_{i+alpha} . (s_i x s_{i-alpha})),
+ * between copies 0 and 1 at each rung, for k = 0 and k = (2 pi / L) e_a,
+ * a = x, y, z. Output d_q (device, caller-owned, float64) is
+ * [group][sample][rung][84]:
+ *   0..8          q^{mu nu}(0), index 3 mu + nu;
+ *   9 + 18 a + 2 (3 mu + nu) + {0, 1}   Re, Im q^{mu nu}(k_a);
+ *   63 + 7 alpha  q_c^alpha(0);
+ *   63 + 7 alpha + 1 + 2 a + {0, 1}     Re, Im q_c^alpha(k_a);
+ * each with the factor 1/N, exp(+i k.R_i), R_i = (x, y, z) of site i.
+ * chi_SG(k) = N sum_{mu nu} |q^{mu nu}(k)|^2 and chi_CG^alpha(k) = N
+ * |q_c^alpha(k)|^2 follow per configuration. Needs n_copies >= 2 and L <= 1024
+ * (HSG_E_INVALID / HSG_E_UNSUPPORTED). Uses the scratch buffer; stream-ordered. */
+hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream);
+
 /* Decode the spins into the canonical float32 layout (renormalised). */
 hsg_status hsg_get_spins(const hsg_lattice *h, float *d_spins, hsg_stream_t stream);
 

@@ -154,6 +154,18 @@ struct OverlapArgs {
 };
 hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s);
 
+// Wave-vector dependent and chiral overlaps: partials [D T][n_pb][84], q [D T][84];
+// block pb covers canonical sites [pb chunk, (pb + 1) chunk).
+struct KmodeArgs {
+    const void *spins;
+    const int32_t *slot_at_temp;
+    double *partials;
+    double *q;
+    int64_t Nh;
+    int32_t L, D, O, T, n_pb, chunk;
+};
+hipError_t launch_kmodes(const KmodeArgs &a, int storage, hipStream_t s);
+
 hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
                                      int32_t T, hipStream_t s);
 hipError_t launch_invert_maps(const int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,

@@ -529,6 +529,168 @@ hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- k modes
+// Wave-vector dependent overlap q^{mu nu}(k) and chiral overlap q_c^alpha(k)
+// between copies 0 and 1 at each rung, for k = 0 and k = (2 pi / L) e_a. The
+// 84 outputs per (sample, rung) are split into three groups of accumulators
+// (G = 0: q(0) and q(k_x), 27 values; G = 1: q(k_y), q(k_z), 36; G = 2: the
+// chiral overlaps, 21), one grid column each. The phases exp(i 2 pi R / L) come
+// from a per-block table in float64. Products, chiralities and sums are float64.
+template <int G>
+struct KGroup;
+template <>
+struct KGroup<0> {
+    static constexpr int first = 0, count = 27;
+};
+template <>
+struct KGroup<1> {
+    static constexpr int first = 27, count = 36;
+};
+template <>
+struct KGroup<2> {
+    static constexpr int first = 63, count = 21;
+};
+
+template <int STORE>
+__device__ __forceinline__ v3 load_site(const typename Codec<STORE>::T *rep, int64_t Nh, int L, int x, int y, int z)
+{
+    x = x < 0 ? x + L : (x >= L ? x - L : x);
+    y = y < 0 ? y + L : (y >= L ? y - L : y);
+    z = z < 0 ? z + L : (z >= L ? z - L : z);
+    const int p = (x + y + z) & 1;
+    const int64_t j = ((int64_t)z * L + y) * (L / 2) + (x >> 1);
+    return Codec<STORE>::load(rep + (int64_t)p * Codec<STORE>::kPlanes * Nh, Nh, j);
+}
+
+__device__ __forceinline__ double chirality(v3 u, v3 v, v3 w)  // u . (v x w)
+{
+    const double vx = v.x, vy = v.y, vz = v.z, wx = w.x, wy = w.y, wz = w.z;
+    return (double)u.x * (vy * wz - vz * wy) + (double)u.y * (vz * wx - vx * wz) + (double)u.z * (vx * wy - vy * wx);
+}
+
+template <int STORE, int G>
+__global__ __launch_bounds__(kBlock) void k_kmodes(KmodeArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    constexpr int K = KGroup<G>::count;
+    __shared__ double red[4][K];
+    __shared__ double cph[1024], sph[1024];
+    const int L = a.L;
+    for (int r = threadIdx.x; r < L; r += kBlock) {
+        double sv, cv;
+        sincospi(2.0 * (double)r / (double)L, &sv, &cv);
+        cph[r] = cv;
+        sph[r] = sv;
+    }
+    __syncthreads();
+    const int64_t dk = blockIdx.x / a.n_pb;  // d * T + k
+    const int pb = (int)(blockIdx.x - dk * a.n_pb);
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int64_t Nh = a.Nh, N = 2 * Nh;
+    const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
+    const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
+    const T *A = (const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh;
+    const T *B = (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh;
+    double acc[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) acc[m] = 0.0;
+    const int64_t i_end = ((int64_t)(pb + 1) * a.chunk < N) ? (int64_t)(pb + 1) * a.chunk : N;
+    for (int64_t i = (int64_t)pb * a.chunk + threadIdx.x; i < i_end; i += kBlock) {
+        const int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
+        const v3 sa0 = load_site<STORE>(A, Nh, L, x, y, z), sb0 = load_site<STORE>(B, Nh, L, x, y, z);
+        if (G < 2) {
+            const double xa[3] = {sa0.x, sa0.y, sa0.z}, ya[3] = {sb0.x, sb0.y, sb0.z};
+            const int R0 = G == 0 ? x : y, R1 = G == 0 ? x : z;
+            const double c0 = cph[R0], s0 = sph[R0], c1 = cph[R1], s1 = sph[R1];
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const double f = xa[m] * ya[n];
+                    const int mn = 3 * m + n;
+                    if (G == 0) {
+                        acc[mn] += f;
+                        acc[9 + 2 * mn] += f * c0;
+                        acc[9 + 2 * mn + 1] += f * s0;
+                    } else {
+                        acc[2 * mn] += f * c0;
+                        acc[2 * mn + 1] += f * s0;
+                        acc[18 + 2 * mn] += f * c1;
+                        acc[18 + 2 * mn + 1] += f * s1;
+                    }
+                }
+        } else {
+            const double cx = cph[x], sx = sph[x], cy = cph[y], sy = sph[y], cz = cph[z], sz = sph[z];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const int dx = al == 0, dy = al == 1, dz = al == 2;
+                const double ka = chirality(load_site<STORE>(A, Nh, L, x + dx, y + dy, z + dz), sa0,
+                                            load_site<STORE>(A, Nh, L, x - dx, y - dy, z - dz));
+                const double kb = chirality(load_site<STORE>(B, Nh, L, x + dx, y + dy, z + dz), sb0,
+                                            load_site<STORE>(B, Nh, L, x - dx, y - dy, z - dz));
+                const double g = ka * kb;
+                acc[7 * al] += g;
+                acc[7 * al + 1] += g * cx;
+                acc[7 * al + 2] += g * sx;
+                acc[7 * al + 3] += g * cy;
+                acc[7 * al + 4] += g * sy;
+                acc[7 * al + 5] += g * cz;
+                acc[7 * al + 6] += g * sz;
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) red[wave][m] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < K)
+        a.partials[(dk * a.n_pb + pb) * 84 + KGroup<G>::first + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// One block per (sample, rung): output m adds the n_pb partials in order.
+__global__ __launch_bounds__(128) void k_kmodes_finish(KmodeArgs a)
+{
+    const int64_t dk = blockIdx.x;
+    const int m = threadIdx.x;
+    if (m >= 84) return;
+    double v = 0.0;
+    for (int pb = 0; pb < a.n_pb; ++pb) v += a.partials[(dk * a.n_pb + pb) * 84 + m];
+    a.q[dk * 84 + m] = v / (double)(2 * a.Nh);
+}
+
+template <int STORE>
+static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
+{
+    const dim3 grid((unsigned)((int64_t)a.D * a.T * a.n_pb)), block(kBlock);
+    hipLaunchKernelGGL((k_kmodes<STORE, 0>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_kmodes<STORE, 1>), grid, block, 0, s, a);
+    hipLaunchKernelGGL((k_kmodes<STORE, 2>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_kmodes(const KmodeArgs &a, int storage, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)a.D * a.T * a.n_pb;
+    if (blocks == 0) return hipSuccess;
+    if (a.L > 1024 || blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    hipError_t e;
+    switch (storage) {
+    case 0: e = launch_kmodes_s<0>(a, s); break;
+    case 1: e = launch_kmodes_s<1>(a, s); break;
+    case 2: e = launch_kmodes_s<2>(a, s); break;
+    case 3: e = launch_kmodes_s<3>(a, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_kmodes_finish, dim3((unsigned)((int64_t)a.D * a.T)), dim3(128), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- maps
 __global__ __launch_bounds__(256) void k_fill_identity(int32_t *sat, int32_t *tos, int64_t n_lad, int32_t T)
 {

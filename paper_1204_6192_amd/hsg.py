@@ -91,6 +91,7 @@ _SIG = {
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "hsg_measure_kmodes": [_vp, _vp, _vp],
     "hsg_set_chain": [_vp, _i32, _i32, _i32, _i32],
     "hsg_set_math": [_vp, _i32],
     "hsg_set_graphs": [_vp, _i32],
@@ -228,6 +229,16 @@ class Lattice:
                                                           device=self.device)
         assert q.dtype == self.torch.float64 and q.numel() == n and q.is_contiguous()
         check(lib.hsg_measure_overlap(self.h, _ptr(q), _stream(self.stream)))
+        return q
+
+    def measure_kmodes(self, out=None):
+        """[sum over groups of n_samples * n_temps * 84] float64: q^{mu nu}(k) and
+        q_c^alpha(k) for k = 0 and the three smallest wave vectors (layout in
+        hsg_measure_kmodes)."""
+        n = sum(g.n_samples * g.n_temps * 84 for g in self.groups)
+        q = out if out is not None else self.torch.empty(n, dtype=self.torch.float64,
+                                                          device=self.device)
+        check(lib.hsg_measure_kmodes(self.h, _ptr(q), _stream(self.stream)))
         return q
 
     def get_spins(self):

@@ -239,6 +239,65 @@ def test_trajectory_hardware_math(hsg, oracle_lib, field):
     _trajectory(hsg, oracle_lib, inst, 10, math=1)
 
 
+# ---------------------------------------------------------------- k modes
+def _oracle_on_gpu_state(oracle_lib, lat, k, g, seed, storage):
+    """An oracle holding the GPU's current (decoded) spins and temperature maps of
+    group k."""
+    o = oracle_lib.Oracle.from_group(g, seed=seed)
+    o.spins = np.ascontiguousarray(_gpu_spins(lat, k), dtype=np.float64)
+    o.slot_at_temp = np.ascontiguousarray(_maps(lat, k).reshape(o.slot_at_temp.shape), dtype=np.int32)
+    return o
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_kmodes_against_oracle(hsg, oracle_lib, storage):
+    """q^{mu nu}(k) and the chiral overlaps for k = 0 and the three smallest wave
+    vectors, three lattice sizes in one handle (L = 6 with odd L/2), after a few
+    sweeps with tempering: the oracle evaluates the same configurations."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 47))
+    groups, uid = [], 0
+    for L, D in ((6, 2), (8, 1), (12, 1)):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.5, 3),
+                                        sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 47
+    lat = _lat(hsg, groups, seed, storage=storage)
+    lat.sweep(5)
+    q = lat.measure_kmodes().cpu().numpy()
+    off = 0
+    for k, g in enumerate(groups):
+        n = g.n_samples * g.n_temps * 84
+        o = _oracle_on_gpu_state(oracle_lib, lat, k, g, seed, storage)
+        want = o.measure_kmodes().reshape(-1)
+        got = q[off:off + n]
+        err = np.abs(got - want).max()
+        print(f"L={g.L}: max |dq| {err:.2e}, max |q| {np.abs(want).max():.2e}", flush=True)
+        assert err < 1e-12
+        off += n
+
+
+def test_kmodes_full_size_sampled(hsg, oracle_lib):
+    """The batched workload at full size (64 samples, 32 rungs) after one sweep:
+    every output of two samples against the oracle on the GPU's configurations."""
+    inst = inputs.make_instance("batched")
+    g = inst.groups[0]
+    lat = _lat(hsg, inst.groups, inst.seed)
+    lat.sweep(1)
+    q = lat.measure_kmodes().cpu().numpy().reshape(g.n_samples, g.n_temps, 84)
+    s = _gpu_spins(lat)
+    maps = _maps(lat).reshape(g.n_samples, g.n_copies, g.n_temps)
+    for d in (0, 41):
+        sub = inputs.Group(L=g.L, n_samples=1, n_copies=g.n_copies, temps=g.temps, J=g.J[d:d + 1],
+                           H=None, spins0=s[d:d + 1], sample_uid_base=g.sample_uid_base + d)
+        o = oracle_lib.Oracle.from_group(sub, seed=inst.seed)
+        o.spins = np.ascontiguousarray(s[d:d + 1], dtype=np.float64)
+        o.slot_at_temp = np.ascontiguousarray(maps[d:d + 1], dtype=np.int32)
+        want = o.measure_kmodes()[0]
+        err = np.abs(q[d] - want).max()
+        print(f"sample {d}: max |dq| {err:.2e}", flush=True)
+        assert err < 1e-12
+
+
 # ---------------------------------------------------------------- tile-local chain
 @pytest.mark.parametrize("tiles,n_hb,n_or", [((4, 4, 1), 1, 4), ((2, 4, 2), 1, 2), ((0, 4, 1), 2, 3)])
 def test_tile_chain_trajectory(hsg, oracle_lib, tiles, n_hb, n_or):
