@@ -25,6 +25,9 @@ Functions and what pins them (details in the tests):
                            the chirality of a conical spiral in closed form,
                            O(3) behaviour (proper rotations keep, reflections
                            flip the chiral part);
+* ``Oracle.measure_pair_overlaps`` -- an FFT of the local-overlap field, the
+                           trace of q^{mu nu}(k) for the pair (0, 1), the
+                           expansion of the four-replica sums on small lattices;
 * ``Oracle.pt_exchange``-- acceptance frequency against min(1, e^Delta);
 * ``Oracle.measure_overlap`` -- q^2 = 1 for identical aligned copies, O(3)
                            invariance, trace identity.
@@ -99,6 +102,7 @@ def lib():
                                       u64p, i64p]
         L.hsgo_tiles_valid.argtypes = [C.c_int, P(Tiles), C.c_int]
         L.hsgo_kmodes.argtypes = [P(Cfg), dp, i32p, dp]
+        L.hsgo_pair_overlaps.argtypes = [P(Cfg), dp, i32p, dp]
         L.hsgo_set_storage_mode.argtypes = [C.c_int]
         L.hsgo_store_roundtrip.argtypes = [C.c_int, dp]
         L.hsgo_round_f16.argtypes = [C.c_double]
@@ -354,6 +358,16 @@ class Oracle:
         q = np.zeros((self.cfg.n_samples, self.cfg.n_temps, 84), dtype=np.float64)
         lib().hsgo_kmodes(C.byref(self.cfg), _p(self.spins, C.c_double),
                           _p(self.slot_at_temp, C.c_int32), _p(q, C.c_double))
+        return q
+
+    def measure_pair_overlaps(self) -> np.ndarray:
+        """[n_samples][n_temps][P][7], P = O (O - 1) / 2 copy pairs: the local-overlap
+        Fourier sums A_ab(k) behind the four-replica estimators (layout in
+        hsg_oracle.c)."""
+        O = self.cfg.n_copies
+        q = np.zeros((self.cfg.n_samples, self.cfg.n_temps, O * (O - 1) // 2, 7), dtype=np.float64)
+        lib().hsgo_pair_overlaps(C.byref(self.cfg), _p(self.spins, C.c_double),
+                                 _p(self.slot_at_temp, C.c_int32), _p(q, C.c_double))
         return q
 
     def hb_words(self, d, o, slot, rep, parity, i):

@@ -617,6 +617,51 @@ void hsgo_kmodes(const hsgo_cfg *c, const double *spins, const int32_t *slot_at_
         }
 }
 
+/* Local-overlap Fourier sums for the connected susceptibility with more than two
+ * copies (the four-replica estimators, Eqs. (9)-(11)): summing the estimators'
+ * integrands over mu and nu leaves products of local overlaps s_i(a) . s_i(b),
+ * so every chi_1, chi_2, chi_3 of Eq. (9) is a product of
+ *   A_ab(k) = (1/N) sum_i (s_i(a) . s_i(b)) exp(i k.R_i)
+ * over copy pairs (a, b) at the same rung: chi_1 = N^2 |A_12|^2, chi_2 =
+ * N^2 A_13 conj(A_14), chi_3 = N^2 A_13 conj(A_24) (copies numbered from 1).
+ * For every sample d, rung k and pair a < b (in the order (0,1), (0,2), ...,
+ * (0,O-1), (1,2), ...), out[((d T + k) P + pair) 7 + m] with P = O (O - 1) / 2:
+ *   m = 0: A_ab(0); m = 1 + 2 ax + {0, 1}: Re, Im A_ab(k_ax), ax = x, y, z. */
+void hsgo_pair_overlaps(const hsgo_cfg *c, const double *spins, const int32_t *slot_at_temp,
+                        double *out)
+{
+    const int L = c->L, O = c->n_copies;
+    const int64_t N = (int64_t)L * L * L;
+    const int P = O * (O - 1) / 2;
+    const double w0 = HSGO_TWO_PI / (double)L;
+    for (int d = 0; d < c->n_samples; ++d)
+        for (int k = 0; k < c->n_temps; ++k) {
+            int pair = 0;
+            for (int a = 0; a < O; ++a)
+                for (int b = a + 1; b < O; ++b, ++pair) {
+                    const int32_t sa = slot_at_temp[((int64_t)d * O + a) * c->n_temps + k];
+                    const int32_t sb = slot_at_temp[((int64_t)d * O + b) * c->n_temps + k];
+                    const double *u = slot_ptr(c, (double *)spins, d, a, sa);
+                    const double *v = slot_ptr(c, (double *)spins, d, b, sb);
+                    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+                    for (int z = 0; z < L; ++z)
+                        for (int y = 0; y < L; ++y)
+                            for (int x = 0; x < L; ++x) {
+                                const int64_t i = site(L, x, y, z);
+                                const double f = u[i] * v[i] + u[N + i] * v[N + i] + u[2 * N + i] * v[2 * N + i];
+                                const int R[3] = {x, y, z};
+                                acc[0] += f;
+                                for (int ax = 0; ax < 3; ++ax) {
+                                    acc[1 + 2 * ax] += f * cos(w0 * R[ax]);
+                                    acc[2 + 2 * ax] += f * sin(w0 * R[ax]);
+                                }
+                            }
+                    double *o = out + (((int64_t)d * c->n_temps + k) * P + pair) * 7;
+                    for (int m = 0; m < 7; ++m) o[m] = acc[m] / (double)N;
+                }
+        }
+}
+
 /* Edwards-Anderson overlap, Eq. (5), between copies 0 and 1 at every rung:
  * q[d][k][3 mu + nu] = (1/N) sum_i s_i^mu(copy 0) s_i^nu(copy 1), q[d][k][9] =
  * sum over mu, nu of q^2. */

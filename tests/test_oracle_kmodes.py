@@ -134,3 +134,79 @@ def test_chiral_modes_are_the_fourier_transform(oracle_lib):
             want = np.conj(F[idx])
             assert abs(q[base + 1 + 2 * ax] - want.real) < 1e-13
             assert abs(q[base + 2 + 2 * ax] - want.imag) < 1e-13
+
+
+def _oracle4(oracle_lib, L, spins, T=1):
+    N = L ** 3
+    return oracle_lib.Oracle(L, 1, 4, np.geomspace(0.2, 0.4, T), np.zeros((1, 3, N)), None, spins,
+                             seed=1, n_hb=1, n_or=1, pt_every=0)
+
+
+def test_pair_overlaps_are_the_fourier_transform_and_the_trace(oracle_lib):
+    """A_ab(k) against numpy's FFT of the local-overlap field s_i(a) . s_i(b), and
+    A_01(k) against the trace of q^{mu nu}(k) for the same two copies."""
+    L = 6
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal((1, 4, 1, 3, L ** 3))
+    spins = v / np.linalg.norm(v, axis=3, keepdims=True)
+    o = _oracle4(oracle_lib, L, spins)
+    A = o.measure_pair_overlaps()[0, 0]
+    pairs = [(a, b) for a in range(4) for b in range(a + 1, 4)]
+    assert A.shape == (6, 7)
+    for p, (a, b) in enumerate(pairs):
+        f = np.einsum("mi,mi->i", spins[0, a, 0], spins[0, b, 0]).reshape(L, L, L)
+        F = np.fft.fftn(f) / L ** 3
+        assert abs(A[p, 0] - F[0, 0, 0].real) < 1e-14
+        for ax, idx in enumerate(((0, 0, 1), (0, 1, 0), (1, 0, 0))):
+            assert abs(A[p, 1 + 2 * ax] - F[idx].real) < 1e-13
+            assert abs(A[p, 2 + 2 * ax] + F[idx].imag) < 1e-13  # exp(+ikR): conjugate
+    two = oracle_lib.Oracle(L, 1, 2, [0.3], np.zeros((1, 3, L ** 3)), None, spins[:, :2].copy(), seed=1,
+                            n_hb=1, n_or=1, pt_every=0)
+    q = two.measure_kmodes()[0, 0]
+    assert abs(A[0, 0] - (q[0] + q[4] + q[8])) < 1e-14
+    for ax in range(3):
+        for part in range(2):
+            tr = sum(q[9 + 18 * ax + 2 * (3 * m + m) + part] for m in range(3))
+            assert abs(A[0, 1 + 2 * ax + part] - tr) < 1e-14
+
+
+def test_four_replica_sums_expand_into_pair_overlaps(oracle_lib):
+    """The four-replica sums chi_1, chi_2, chi_3 of Eq. (9), evaluated by brute
+    force over i, j, mu, nu on L = 2 and 4, equal N^2 A_12 conj(A_12),
+    N^2 A_13 conj(A_14) and N^2 A_13 conj(A_24) (copies numbered from 1)."""
+    rng = np.random.default_rng(8)
+    for L in (2, 4):
+        N = L ** 3
+        v = rng.standard_normal((1, 4, 1, 3, N))
+        spins = v / np.linalg.norm(v, axis=3, keepdims=True)
+        A = _oracle4(oracle_lib, L, spins).measure_pair_overlaps()[0, 0]
+        pid = {(a, b): p for p, (a, b) in enumerate((a, b) for a in range(4) for b in range(a + 1, 4))}
+
+        def cA(a, b, ax):  # complex A_ab(k_ax), ax = -1 for k = 0
+            r = A[pid[(a, b)]]
+            return complex(r[0], 0.0) if ax < 0 else complex(r[1 + 2 * ax], r[2 + 2 * ax])
+
+        s = [spins[0, c, 0] for c in range(4)]  # [mu][i]
+        idx = np.arange(N)
+        R = np.stack([idx % L, (idx // L) % L, idx // (L * L)])
+        for ax in (-1, 0, 1, 2):
+            ph = np.ones(N, dtype=complex) if ax < 0 else np.exp(1j * 2 * np.pi * R[ax] / L)
+
+            E = ph[:, None] * np.conj(ph)[None, :]  # e^{ik(R_i - R_j)}
+
+            def brute(c1, c2, c3, c4):
+                """sum over i, j, mu, nu of s_i^mu(c1) s_j^nu(c2) s_i^mu(c3) s_j^nu(c4) e^{ik(R_i-R_j)},
+                term by term as written."""
+                tot = 0j
+                for mu in range(3):
+                    for nu in range(3):
+                        t = (s[c1][mu][:, None] * s[c2][nu][None, :] * s[c3][mu][:, None]
+                             * s[c4][nu][None, :])
+                        tot += np.sum(t * E)
+                return tot
+
+            chi1, chi2, chi3 = brute(0, 0, 1, 1), brute(0, 0, 2, 3), brute(0, 1, 2, 3)
+            a12, a13, a14, a24 = cA(0, 1, ax), cA(0, 2, ax), cA(0, 3, ax), cA(1, 3, ax)
+            assert abs(chi1 - N ** 2 * a12 * np.conj(a12)) < 1e-9 * N ** 2
+            assert abs(chi2 - N ** 2 * a13 * np.conj(a14)) < 1e-9 * N ** 2
+            assert abs(chi3 - N ** 2 * a13 * np.conj(a24)) < 1e-9 * N ** 2
