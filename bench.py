@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=40)
+    ap.add_argument("--copies", type=int, default=2,
+                    help="copies per sample R_O (4 for the four-replica estimators in a field)")
     ap.add_argument("--tiles", type=str, default=None,
                     help="run the tile-local chain instead of the full-lattice one: TY,TZ,NHIT "
                          "(tiles of L x TY x TZ sites, 0 = L; NHIT repetitions per visit)")
@@ -175,7 +177,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_gen = time.perf_counter()
-    inst = inputs.make_instance(args.config, storage=args.storage, field_amp=args.field_amp)
+    inst = inputs.make_instance(args.config, storage=args.storage, field_amp=args.field_amp,
+                                copies=args.copies)
     overlap_every = args.overlap_every
     if overlap_every is None:
         overlap_every = 1 if args.config == "large" else 0

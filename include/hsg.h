@@ -175,6 +175,18 @@ hsg_status hsg_measure_overlap(hsg_lattice *h, double *d_q, hsg_stream_t stream)
  * (HSG_E_INVALID / HSG_E_UNSUPPORTED). Uses the scratch buffer; stream-ordered. */
 hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream);
 
+/* Local-overlap Fourier sums of every pair of copies (the four-replica
+ * estimators of the connected susceptibility in a field, Eqs. (9)-(11)):
+ * summed over mu and nu, each chi_1, chi_2, chi_3 of Eq. (9) is a product of
+ *   A_ab(k) = (1/N) sum_i (s_i(a) . s_i(b)) exp(i k.R_i)
+ * at one rung: chi_1 = N^2 |A_12|^2, chi_2 = N^2 A_13 conj(A_14),
+ * chi_3 = N^2 A_13 conj(A_24) (copies numbered from 1). Output d_q (device,
+ * caller-owned, float64) is [group][sample][rung][pair][7], pairs a < b in the
+ * order (0,1), (0,2), ..., (0,O-1), (1,2), ...; per pair: A_ab(0), then Re, Im
+ * of A_ab((2 pi / L) e_a) for a = x, y, z. Needs n_copies >= 2 and L <= 1024.
+ * Uses the scratch buffer; stream-ordered. */
+hsg_status hsg_measure_pair_overlaps(hsg_lattice *h, double *d_q, hsg_stream_t stream);
+
 /* Decode the spins into the canonical float32 layout (renormalised). */
 hsg_status hsg_get_spins(const hsg_lattice *h, float *d_spins, hsg_stream_t stream);
 

@@ -214,9 +214,11 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
         const uint64_t k_full = (uint64_t)g.D * g.T * g.q_pb * 84 * 8;  // k modes, same blocks
+        const uint64_t p_full = (uint64_t)g.D * g.T * g.q_pb * 7 * (g.O * (g.O - 1) / 2) * 8;  // copy pairs
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
         if (q_full > need) need = q_full;
         if (k_full > need) need = k_full;
+        if (p_full > need) need = p_full;
         sc = align_up(sc + need);
         rep0 += g.n_rep;
         spins += g.n_rep * g.N;
@@ -891,6 +893,34 @@ hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream)
         const hipError_t e = hsg::launch_kmodes(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_kmodes");
         off += (int64_t)g.D * g.T * 84;
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_measure_pair_overlaps(hsg_lattice *h, double *d_q, hsg_stream_t stream)
+{
+    if (h == nullptr || d_q == nullptr) return fail(HSG_E_INVALID, "handle and d_q are required");
+    for (const Group &g : h->lay.g) {
+        if (g.O < 2) return fail(HSG_E_INVALID, "pair overlaps need n_copies >= 2 in every group");
+        if (g.L > 1024) return fail(HSG_E_UNSUPPORTED, "pair overlaps need L <= 1024");
+    }
+    int64_t off = 0;
+    for (const Group &g : h->lay.g) {
+        hsg::PairOvArgs a{};
+        a.spins = h->state + g.o_spins;
+        a.slot_at_temp = reinterpret_cast<const int32_t *>(h->state + g.o_sat);
+        a.partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+        a.q = d_q + off;
+        a.Nh = g.Nh;
+        a.L = g.L;
+        a.D = g.D;
+        a.O = g.O;
+        a.T = g.T;
+        a.n_pb = g.q_pb;
+        a.chunk = 2 * g.q_chunk;
+        const hipError_t e = hsg::launch_pair_overlaps(a, h->storage, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "measure_pair_overlaps");
+        off += (int64_t)g.D * g.T * 7 * (g.O * (g.O - 1) / 2);
     }
     return HSG_OK;
 }

@@ -166,6 +166,18 @@ struct KmodeArgs {
 };
 hipError_t launch_kmodes(const KmodeArgs &a, int storage, hipStream_t s);
 
+// Copy-pair local-overlap sums: partials [D T][n_pb][7 P], q [D T][P][7],
+// P = O (O - 1) / 2 pairs a < b in the order (0,1), (0,2), ..., (1,2), ...
+struct PairOvArgs {
+    const void *spins;
+    const int32_t *slot_at_temp;
+    double *partials;
+    double *q;
+    int64_t Nh;
+    int32_t L, D, O, T, n_pb, chunk;
+};
+hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s);
+
 hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
                                      int32_t T, hipStream_t s);
 hipError_t launch_invert_maps(const int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,

@@ -691,6 +691,111 @@ hipError_t launch_kmodes(const KmodeArgs &a, int storage, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- copy-pair overlaps
+// A_ab(k) = (1/N) sum_i (s_i(a) . s_i(b)) exp(i k.R_i) for every copy pair a < b at
+// each rung, k = 0 and (2 pi / L) e_a: the building blocks of the four-replica
+// estimators. Grid column c takes pairs [4 c, 4 c + 4) (28 float64
+// accumulators per thread).
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_pair_overlaps(PairOvArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    __shared__ double red[4][28];
+    __shared__ double cph[1024], sph[1024];
+    const int L = a.L;
+    for (int r = threadIdx.x; r < L; r += kBlock) {
+        double sv, cv;
+        sincospi(2.0 * (double)r / (double)L, &sv, &cv);
+        cph[r] = cv;
+        sph[r] = sv;
+    }
+    __syncthreads();
+    const int64_t dk = blockIdx.x / a.n_pb;
+    const int pb = (int)(blockIdx.x - dk * a.n_pb);
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int O = a.O, P = O * (O - 1) / 2;
+    const int p0 = 4 * (int)blockIdx.y;
+    const int np = P - p0 < 4 ? P - p0 : 4;
+    const int64_t Nh = a.Nh, N = 2 * Nh;
+    const T *U[4], *V[4];
+    {
+        int q = 0, p = 0;
+        for (int ca = 0; ca < O; ++ca)
+            for (int cb = ca + 1; cb < O; ++cb, ++p)
+                if (p >= p0 && q < np) {
+                    const int32_t sa = a.slot_at_temp[((int64_t)d * O + ca) * a.T + k];
+                    const int32_t sb = a.slot_at_temp[((int64_t)d * O + cb) * a.T + k];
+                    U[q] = (const T *)a.spins + (((int64_t)d * O + ca) * a.T + sa) * 2 * C::kPlanes * Nh;
+                    V[q] = (const T *)a.spins + (((int64_t)d * O + cb) * a.T + sb) * 2 * C::kPlanes * Nh;
+                    ++q;
+                }
+        for (; q < 4; ++q) U[q] = V[q] = nullptr;
+    }
+    double acc[28];
+#pragma unroll
+    for (int m = 0; m < 28; ++m) acc[m] = 0.0;
+    const int64_t i_end = ((int64_t)(pb + 1) * a.chunk < N) ? (int64_t)(pb + 1) * a.chunk : N;
+    for (int64_t i = (int64_t)pb * a.chunk + threadIdx.x; i < i_end; i += kBlock) {
+        const int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
+        const int p = (x + y + z) & 1;
+        const int64_t j = ((int64_t)z * L + y) * (L / 2) + (x >> 1);
+        const double ph[7] = {1.0, cph[x], sph[x], cph[y], sph[y], cph[z], sph[z]};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < np) {
+                const v3 u = C::load(U[q] + (int64_t)p * C::kPlanes * Nh, Nh, j);
+                const v3 v = C::load(V[q] + (int64_t)p * C::kPlanes * Nh, Nh, j);
+                const double f = (double)u.x * v.x + (double)u.y * v.y + (double)u.z * v.z;
+#pragma unroll
+                for (int m = 0; m < 7; ++m) acc[7 * q + m] += f * ph[m];
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < 28; ++m) {
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) red[wave][m] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7 * np)
+        a.partials[(dk * a.n_pb + pb) * (int64_t)(7 * P) + 7 * p0 + threadIdx.x] =
+            (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+// One block per (sample, rung): output m adds the n_pb partials in order.
+__global__ __launch_bounds__(256) void k_pair_overlaps_finish(PairOvArgs a)
+{
+    const int64_t dk = blockIdx.x;
+    const int n = 7 * (a.O * (a.O - 1) / 2);
+    for (int m = threadIdx.x; m < n; m += blockDim.x) {
+        double v = 0.0;
+        for (int pb = 0; pb < a.n_pb; ++pb) v += a.partials[(dk * a.n_pb + pb) * (int64_t)n + m];
+        a.q[dk * n + m] = v / (double)(2 * a.Nh);
+    }
+}
+
+hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)a.D * a.T * a.n_pb;
+    const int P = a.O * (a.O - 1) / 2;
+    if (blocks == 0 || P == 0) return hipSuccess;
+    if (a.L > 1024 || blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks, (unsigned)((P + 3) / 4)), block(kBlock);
+    switch (storage) {
+    case 0: hipLaunchKernelGGL(k_pair_overlaps<0>, grid, block, 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_pair_overlaps<1>, grid, block, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_pair_overlaps<2>, grid, block, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(k_pair_overlaps<3>, grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pair_overlaps_finish, dim3((unsigned)((int64_t)a.D * a.T)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- maps
 __global__ __launch_bounds__(256) void k_fill_identity(int32_t *sat, int32_t *tos, int64_t n_lad, int32_t T)
 {

@@ -91,6 +91,7 @@ _SIG = {
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "hsg_measure_pair_overlaps": [_vp, _vp, _vp],
     "hsg_measure_kmodes": [_vp, _vp, _vp],
     "hsg_set_chain": [_vp, _i32, _i32, _i32, _i32],
     "hsg_set_math": [_vp, _i32],
@@ -239,6 +240,17 @@ class Lattice:
         q = out if out is not None else self.torch.empty(n, dtype=self.torch.float64,
                                                           device=self.device)
         check(lib.hsg_measure_kmodes(self.h, _ptr(q), _stream(self.stream)))
+        return q
+
+    def measure_pair_overlaps(self, out=None):
+        """[sum over groups of n_samples * n_temps * P * 7] float64, P = O (O - 1) / 2:
+        the local-overlap Fourier sums of every copy pair (layout in
+        hsg_measure_pair_overlaps)."""
+        n = sum(g.n_samples * g.n_temps * 7 * (g.n_copies * (g.n_copies - 1) // 2)
+                for g in self.groups)
+        q = out if out is not None else self.torch.empty(n, dtype=self.torch.float64,
+                                                          device=self.device)
+        check(lib.hsg_measure_pair_overlaps(self.h, _ptr(q), _stream(self.stream)))
         return q
 
     def get_spins(self):

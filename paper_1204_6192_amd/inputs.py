@@ -169,8 +169,10 @@ CONFIGS = {
 
 def make_instance(name: str, *, scale_samples: Optional[int] = None,
                   L_override: Optional[int] = None, storage: Optional[str] = None,
-                  field_amp: Optional[float] = None, seed_offset: int = 0) -> Instance:
-    """Build a named workload. ``scale_samples`` caps samples per group (for tests)."""
+                  field_amp: Optional[float] = None, seed_offset: int = 0,
+                  copies: int = 2) -> Instance:
+    """Build a named workload. ``scale_samples`` caps samples per group (for tests);
+    ``copies`` is R_O (4 for the four-replica estimators in a field)."""
     cfg = CONFIGS[name]
     k = cfg["k"]
     rng = np.random.Generator(np.random.Philox(INSTANCE_SEED_BASE + k + seed_offset))
@@ -183,7 +185,7 @@ def make_instance(name: str, *, scale_samples: Optional[int] = None,
         n_s = gd["n_samples"] if scale_samples is None else min(gd["n_samples"], scale_samples)
         L = gd["L"] if L_override is None else L_override
         temps = geometric_ladder(*gd["t"])
-        groups.append(make_group(rng, L, n_s, 2, temps, couplings=cfg["couplings"],
+        groups.append(make_group(rng, L, n_s, copies, temps, couplings=cfg["couplings"],
                                  field=field, sample_uid_base=uid))
         uid += n_s
     return Instance(groups=groups, seed=PHILOX_KEY_BASE + k, storage=storage or cfg["storage"],

@@ -298,6 +298,38 @@ def test_kmodes_full_size_sampled(hsg, oracle_lib):
         assert err < 1e-12
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_pair_overlaps_four_copies_against_oracle(hsg, oracle_lib, storage):
+    """Four copies per sample (the four-replica estimators), three lattice sizes in
+    one handle, a random field, after sweeps with tempering on every copy's
+    ladder: A_ab(k) of all six pairs against the oracle on the same
+    configurations."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 48))
+    groups, uid = [], 0
+    for L, D in ((6, 1), (8, 2), (12, 1)):
+        groups.append(inputs.make_group(rng, L, D, 4, inputs.geometric_ladder(0.1, 0.5, 3),
+                                        field=("gaussian", 0.2), sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 48
+    lat = _lat(hsg, groups, seed, storage=storage)
+    lat.sweep(4)
+    q = lat.measure_pair_overlaps().cpu().numpy()
+    off = 0
+    for k, g in enumerate(groups):
+        n = g.n_samples * g.n_temps * 6 * 7
+        o = _oracle_on_gpu_state(oracle_lib, lat, k, g, seed, storage)
+        want = o.measure_pair_overlaps().reshape(-1)
+        err = np.abs(q[off:off + n] - want).max()
+        print(f"L={g.L}: max |dA| {err:.2e}, max |A| {np.abs(want).max():.2e}", flush=True)
+        assert err < 1e-12
+        off += n
+    # the pair (0, 1) is the trace of q^{mu nu}(k) from the k-mode measurement
+    qk = lat.measure_kmodes().cpu().numpy()
+    A = q[:groups[0].n_samples * 3 * 42].reshape(-1, 6, 7)
+    K = qk[:groups[0].n_samples * 3 * 84].reshape(-1, 84)
+    assert np.allclose(A[:, 0, 0], K[:, 0] + K[:, 4] + K[:, 8], atol=1e-13)
+
+
 # ---------------------------------------------------------------- tile-local chain
 @pytest.mark.parametrize("tiles,n_hb,n_or", [((4, 4, 1), 1, 4), ((2, 4, 2), 1, 2), ((0, 4, 1), 2, 3)])
 def test_tile_chain_trajectory(hsg, oracle_lib, tiles, n_hb, n_or):
