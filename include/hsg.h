@@ -264,6 +264,22 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
 hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_t *variant,
                         int32_t *slots_per_item, hsg_stream_t stream);
 
+/* Run statistics (the paper's U_L, C_L and tempering diagnostics). With
+ * hsg_set_stats(h, 1), every following sweep ends (after tempering) with: for
+ * every ladder and rung k, the energy E of the configuration now at rung k is
+ * added to sums of E and E^2; and a replica that reaches the lowest rung after
+ * having reached the highest since its last visit to the lowest completes one
+ * round trip. U_L(T_k) = sum E / n and C_L(T_k) = (sum E^2 / n - U_L^2) / T_k^2
+ * per ladder, with n the sweeps counted. hsg_reset_stats clears them (also done
+ * at init). hsg_get_stats copies d_sums [group][sample][copy][rung][2] (E, E^2;
+ * float64, device) and d_trips [group][sample][copy][slot] (uint32, device);
+ * either may be NULL; *n_sweeps (host) receives the sweeps accumulated.
+ * The statistics live in the state buffer. */
+hsg_status hsg_set_stats(hsg_lattice *h, int32_t enable);
+hsg_status hsg_reset_stats(hsg_lattice *h, hsg_stream_t stream);
+hsg_status hsg_get_stats(const hsg_lattice *h, double *d_sums, uint32_t *d_trips, uint64_t *n_sweeps,
+                         hsg_stream_t stream);
+
 /* Replay whole sweeps as captured HIP graphs (default on; used when tempering
  * runs every sweep or never). Results do not depend on it. */
 hsg_status hsg_set_graphs(hsg_lattice *h, int32_t enable);

@@ -66,6 +66,7 @@ struct Group {
     int64_t can_site0;  // element offset of the group in the canonical J and H arrays
     // byte offsets
     uint64_t o_spins, o_sat, o_tos, o_E, o_acc;  // state
+    uint64_t o_ssum, o_sflag, o_strips;          // run statistics
     uint64_t o_J6, o_b64, o_b32, o_Jbits;        // couplings
     uint64_t o_H;                                // field
     uint64_t o_scr;                              // scratch
@@ -195,6 +196,13 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         st = align_up(st + (uint64_t)g.n_rep * 8);
         g.o_acc = st;
         st = align_up(st + (uint64_t)g.D * g.O * (g.T > 1 ? g.T - 1 : 1) * 8);
+        // run statistics: sums of E and E^2 per (ladder, rung), flag and round trips per slot
+        g.o_ssum = st;
+        st = align_up(st + (uint64_t)g.n_rep * 2 * 8);
+        g.o_sflag = st;
+        st = align_up(st + (uint64_t)g.n_rep * 4);
+        g.o_strips = st;
+        st = align_up(st + (uint64_t)g.n_rep * 4);
         // couplings and ladder
         g.o_J6 = cp;
         cp = align_up(cp + (uint64_t)g.D * 2 * 6 * g.Nh * 4);
@@ -245,6 +253,8 @@ struct hsg_lattice {
     int32_t slots_per_item = 0;
     int32_t kernel_variant = 0;  // 0 automatic (= 3), 1 gather, 2 z-march, 3 z-march with fused pairs
     bool hw_math = false;        // heat bath with the hardware transcendentals (kernel kind 2)
+    bool stats = false;   // accumulate run statistics after every sweep
+    uint64_t n_stats = 0;  // sweeps accumulated since the last reset
     // Markov chain: 0 the full-lattice checkerboard, 1 the tile-local chain
     int32_t chain = 0, tile_y = 0, tile_z = 0, n_hit = 1;
     bool have_energies = false;
@@ -488,6 +498,29 @@ bool aligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & (kAlign -
 // All launches of one sweep, kernels only (capturable): heat-bath pairs,
 // over-relaxation pairs with the energy fused into the last pass, tempering,
 // then the device sweep counter advances.
+hsg::StatsArgs stats_args(const hsg_lattice *h, const Group &g)
+{
+    hsg::StatsArgs a{};
+    a.slot_at_temp = reinterpret_cast<const int32_t *>(h->state + g.o_sat);
+    a.E = reinterpret_cast<const double *>(h->state + g.o_E);
+    a.sum = reinterpret_cast<double *>(h->state + g.o_ssum);
+    a.flag = reinterpret_cast<int32_t *>(h->state + g.o_sflag);
+    a.trips = reinterpret_cast<uint32_t *>(h->state + g.o_strips);
+    a.D = g.D;
+    a.O = g.O;
+    a.T = g.T;
+    return a;
+}
+
+hsg_status run_stats(hsg_lattice *h, bool clear, hipStream_t s)
+{
+    for (const Group &g : h->lay.g) {
+        const hipError_t e = hsg::launch_stats(stats_args(h, g), clear, s);
+        if (e != hipSuccess) return hip_fail(e, "statistics launch");
+    }
+    return HSG_OK;
+}
+
 // Exact energies of every replica into E (full recomputation), all groups.
 hsg_status run_energy(hsg_lattice *h, hipStream_t s)
 {
@@ -572,6 +605,7 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
     if (h->chain == 1) {
         hsg_status st = run_tile_sweep(h, s);
         if (st == HSG_OK && pt) st = run_pt(h, 0u, 1u, s);
+        if (st == HSG_OK && h->stats) st = run_stats(h, false, s);
         if (st != HSG_OK) return st;
         const hipError_t e = hsg::launch_advance(dev_counter(h), s);
         if (e != hipSuccess) return hip_fail(e, "counter launch");
@@ -588,6 +622,10 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
     }
     if (pt) {
         hsg_status st = run_pt(h, 0u, 1u, s);
+        if (st != HSG_OK) return st;
+    }
+    if (h->stats) {
+        hsg_status st = run_stats(h, false, s);
         if (st != HSG_OK) return st;
     }
     const hipError_t e = hsg::launch_advance(dev_counter(h), s);
@@ -731,6 +769,7 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
             e = hipMemsetAsync(h->state + g.o_E, 0, (size_t)g.n_rep * 8, s);
         if (e == hipSuccess)
             e = hipMemsetAsync(h->state + g.o_acc, 0, (size_t)g.D * g.O * (g.T > 1 ? g.T - 1 : 1) * 8, s);
+        if (e == hipSuccess) e = hsg::launch_stats(stats_args(h, g), true, s);
         if (e != hipSuccess) {
             delete h;
             return hip_fail(e, "init");
@@ -777,6 +816,7 @@ hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream)
         }
     }
     h->have_energies = n_sweeps > 0 || h->have_energies;
+    if (h->stats) h->n_stats += (uint64_t)n_sweeps;
     return HSG_OK;
 }
 
@@ -1182,6 +1222,41 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
     h->tile_z = tile_z;
     h->n_hit = n_hit;
     drop_graphs(h);
+    return HSG_OK;
+}
+
+hsg_status hsg_set_stats(hsg_lattice *h, int32_t enable)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    h->stats = enable != 0;
+    drop_graphs(h);
+    return HSG_OK;
+}
+
+hsg_status hsg_reset_stats(hsg_lattice *h, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    hsg_status st = run_stats(h, true, S(stream));
+    if (st == HSG_OK) h->n_stats = 0;
+    return st;
+}
+
+hsg_status hsg_get_stats(const hsg_lattice *h, double *d_sums, uint32_t *d_trips, uint64_t *n_sweeps,
+                         hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    hipStream_t s = S(stream);
+    for (const Group &g : h->lay.g) {
+        hipError_t e = hipSuccess;
+        if (d_sums)
+            e = hipMemcpyAsync(d_sums + g.rep0 * 2, h->state + g.o_ssum, (size_t)g.n_rep * 16,
+                               hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && d_trips)
+            e = hipMemcpyAsync(d_trips + g.rep0, h->state + g.o_strips, (size_t)g.n_rep * 4,
+                               hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "get_stats");
+    }
+    if (n_sweeps) *n_sweeps = h->n_stats;
     return HSG_OK;
 }
 

@@ -116,6 +116,17 @@ struct PtArgs {
 };
 hipError_t launch_pt(const PtArgs &a, hipStream_t s);
 
+// Run statistics: sum [D][O][T][2] (E, E^2 by rung), flag and trips [D][O][T] by slot.
+struct StatsArgs {
+    const int32_t *slot_at_temp;
+    const double *E;
+    double *sum;
+    int32_t *flag;
+    uint32_t *trips;
+    int32_t D, O, T;
+};
+hipError_t launch_stats(const StatsArgs &a, bool clear, hipStream_t s);
+
 struct PackArgs {
     void *spins_int;
     float *spins_can;  // canonical [r][3][N]

@@ -227,6 +227,55 @@ hipError_t launch_pt(const PtArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- run statistics
+// After a sweep: per ladder, the energy of the configuration at each rung is
+// added to float64 sums of E and E^2 (for U_L and C_L), and a replica that
+// reaches the lowest rung after visiting the highest since its last visit to
+// the lowest completes a round trip. flag per slot: 0 none yet, 1 at the lowest
+// rung since, 2 reached the highest rung after that.
+__global__ __launch_bounds__(64) void k_stats(StatsArgs a)
+{
+    const int64_t lad = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (lad >= (int64_t)a.D * a.O) return;
+    const int32_t *sat = a.slot_at_temp + lad * a.T;
+    const double *E = a.E + lad * a.T;
+    double *sum = a.sum + lad * a.T * 2;
+    for (int k = 0; k < a.T; ++k) {
+        const double e = E[sat[k]];
+        sum[2 * k] += e;
+        sum[2 * k + 1] += e * e;
+    }
+    if (a.T < 2) return;
+    int32_t *flag = a.flag + lad * a.T;
+    uint32_t *trips = a.trips + lad * a.T;
+    const int32_t lo = sat[0], hi = sat[a.T - 1];
+    if (flag[lo] == 2) trips[lo] += 1u;
+    flag[lo] = 1;
+    if (flag[hi] == 1) flag[hi] = 2;
+}
+
+__global__ __launch_bounds__(256) void k_stats_clear(StatsArgs a)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = (int64_t)a.D * a.O * a.T;
+    if (g >= n) return;
+    a.sum[2 * g] = 0.0;
+    a.sum[2 * g + 1] = 0.0;
+    a.flag[g] = 0;
+    a.trips[g] = 0u;
+}
+
+hipError_t launch_stats(const StatsArgs &a, bool clear, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.D * a.O;
+    if (n == 0) return hipSuccess;
+    if (clear)
+        hipLaunchKernelGGL(k_stats_clear, dim3((unsigned)((n * a.T + 255) / 256)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_stats, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- layouts
 __device__ __forceinline__ Site site_of(int64_t i, int32_t L)
 {

@@ -93,6 +93,9 @@ _SIG = {
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
     "hsg_measure_pair_overlaps": [_vp, _vp, _vp],
     "hsg_measure_kmodes": [_vp, _vp, _vp],
+    "hsg_set_stats": [_vp, _i32],
+    "hsg_reset_stats": [_vp, _vp],
+    "hsg_get_stats": [_vp, _vp, _vp, _vp, _vp],
     "hsg_set_chain": [_vp, _i32, _i32, _i32, _i32],
     "hsg_set_math": [_vp, _i32],
     "hsg_set_graphs": [_vp, _i32],
@@ -312,6 +315,22 @@ class Lattice:
         """0: full-lattice checkerboard (default); 1: the tile-local chain with tiles
         of L x tile_y x tile_z sites (0 = L) and n_hit repetitions per visit."""
         check(lib.hsg_set_chain(self.h, int(chain), int(tile_y), int(tile_z), int(n_hit)))
+
+    def set_stats(self, enable: bool = True) -> None:
+        """Accumulate per-rung sums of E, E^2 and tempering round trips after every sweep."""
+        check(lib.hsg_set_stats(self.h, int(bool(enable))))
+
+    def reset_stats(self) -> None:
+        check(lib.hsg_reset_stats(self.h, _stream(self.stream)))
+
+    def get_stats(self):
+        """(sums [n_replicas, 2] float64 by (sample, copy, rung): E, E^2;
+        round trips [n_replicas] int32 by (sample, copy, slot); sweeps counted)."""
+        sums = self.torch.empty((self.n_replicas, 2), dtype=self.torch.float64, device=self.device)
+        trips = self.torch.empty(self.n_replicas, dtype=self.torch.int32, device=self.device)
+        n = C.c_uint64()
+        check(lib.hsg_get_stats(self.h, _ptr(sums), _ptr(trips), C.byref(n), _stream(self.stream)))
+        return sums, trips, int(n.value)
 
     def set_math(self, mode: int) -> None:
         """0: library transcendentals in the heat bath (default); 1: hardware ones."""

@@ -330,6 +330,49 @@ def test_pair_overlaps_four_copies_against_oracle(hsg, oracle_lib, storage):
     assert np.allclose(A[:, 0, 0], K[:, 0] + K[:, 4] + K[:, 8], atol=1e-13)
 
 
+# ---------------------------------------------------------------- run statistics
+@pytest.mark.parametrize("tiles", [None, (4, 4, 1)])
+def test_run_statistics_replayed_on_the_host(hsg, tiles):
+    """Sums of E and E^2 per rung and tempering round trips, accumulated on the
+    GPU after every sweep (replayed graphs), against the same bookkeeping done
+    on the host from the maps and energies read after each sweep; then reset."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 49))
+    T = 4
+    g = inputs.make_group(rng, 4, 2, 2, inputs.geometric_ladder(0.8, 1.0, T))  # close rungs: swaps
+    lat = _lat(hsg, [g], inputs.PHILOX_KEY_BASE + 49)
+    if tiles:
+        lat.set_chain(1, *tiles)
+    lat.set_stats(True)
+    R = g.n_slots
+    sums = np.zeros((R, 2))
+    flag = np.zeros(R, dtype=np.int64)
+    trips = np.zeros(R, dtype=np.int64)
+    n_lad = g.n_samples * g.n_copies
+    for t in range(120):
+        lat.sweep(1)
+        sat = lat.get_temp_map().cpu().numpy().reshape(n_lad, T)
+        E = lat.get_energies().cpu().numpy().reshape(n_lad, T)
+        for lad in range(n_lad):
+            for k in range(T):
+                e = E[lad, sat[lad, k]]
+                sums[lad * T + k] += (e, e * e)
+            lo, hi = lad * T + sat[lad, 0], lad * T + sat[lad, T - 1]
+            if flag[lo] == 2:
+                trips[lo] += 1
+            flag[lo] = 1
+            if flag[hi] == 1:
+                flag[hi] = 2
+    gs, gt, n = lat.get_stats()
+    assert n == 120
+    assert np.allclose(gs.cpu().numpy(), sums, rtol=1e-13, atol=1e-9)
+    assert np.array_equal(gt.cpu().numpy(), trips)
+    print(f"round trips per replica: {trips.tolist()}", flush=True)
+    assert trips.sum() > 0  # hot ladder: replicas do travel
+    lat.reset_stats()
+    gs, gt, n = lat.get_stats()
+    assert n == 0 and float(gs.abs().max()) == 0.0 and int(gt.abs().max()) == 0
+
+
 # ---------------------------------------------------------------- tile-local chain
 @pytest.mark.parametrize("tiles,n_hb,n_or", [((4, 4, 1), 1, 4), ((2, 4, 2), 1, 2), ((0, 4, 1), 2, 3)])
 def test_tile_chain_trajectory(hsg, oracle_lib, tiles, n_hb, n_or):
