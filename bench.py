@@ -78,6 +78,34 @@ def time_kernel(lat, kind, n, torch):
     return start.elapsed_time(stop) / n * 1e-3  # seconds per pair
 
 
+def time_analysis(lat, inst, torch, reps=5):
+    """Mean time of one call of each measurement (HIP events on the current
+    stream), with the HBM bytes they must read (every spin of copies 0 and 1, or
+    of all copies for the pair sums, once; six neighbours of each come from
+    cache)."""
+    out = {}
+    bs = STORE_BYTES[inst.storage]
+    spins01 = sum(g.n_samples * min(g.n_copies, 2) * g.n_temps * g.N for g in inst.groups) * bs
+    spins_all = sum(g.n_slots * g.N for g in inst.groups) * bs
+    stream = torch.cuda.current_stream()
+    for name, fn, nbytes in (("overlap", lat.measure_overlap, spins01),
+                             ("kmodes", lat.measure_kmodes, spins01),
+                             ("pair_overlaps", lat.measure_pair_overlaps, spins_all),
+                             ("energy", lat.measure_energy, spins_all)):
+        fn()
+        torch.cuda.synchronize()
+        start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        for _ in range(reps):
+            fn()
+        stop.record(stream)
+        stop.synchronize()
+        t = start.elapsed_time(stop) / reps * 1e-3
+        out[f"{name}_us"] = t * 1e6
+        out[f"{name}_gbs"] = nbytes / t / 1e9
+    return out
+
+
 def copy_bandwidth(torch, mib=1024, reps=10):
     """Read+write GB/s of a plain device-to-device copy (the practical HBM ceiling
     next to the published 8 TB/s)."""
@@ -237,6 +265,8 @@ def main():
         f"HB pair: {t_hb * 1e6:.1f} us, {b_hb / 1e9:.3f} GB -> {b_hb / t_hb / 1e9:.0f} GB/s")
     eff_gbs = (inst.n_hb * b_hb + inst.n_or * b_or) / (dt / args.steps) / 1e9
 
+    analysis = time_analysis(lat, inst, torch)
+    log("analysis: " + ", ".join(f"{k} {v:.1f}" for k, v in analysis.items()))
     traffic, traffic_src = measured_traffic(hsg.build_id(), args.config)
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy: {copy_gbs:.0f} GB/s read+write; OR pair at {gbs_or / copy_gbs:.1%} of it")
@@ -279,6 +309,7 @@ def main():
                      "hb_pair_us_hw_math": t_hb_hw * 1e6,
                      "device_copy_gbs": copy_gbs, "frac_of_copy": gbs_or / copy_gbs},
         "cpu_baseline": cpu,
+        "analysis": analysis,
     }
     if args.tiles:
         # the tile-local chain's kernel is VALU-bound; the HBM roofline above is the

@@ -16,74 +16,64 @@
 // of each parity in one replica and keeps their couplings (and field) in
 // registers for the whole visit.
 //
-// What LDS holds per codec: float32 spins as they are; float16 / bfloat16 the
-// decoded (exactly representable) components of the stored code, renormalised
-// whenever read, so the final store writes exactly the code of the last update;
-// quantised angles the decoded unit vector (the octahedral projection divides by
-// the L1 norm, so re-encoding it gives back its code).
+// What LDS holds: every spin as a load returns it (decoded and renormalised).
+// The final store must write exactly the code of each site's last update:
+// float32 spins are their own code; quantised angles are held decoded, and the
+// octahedral projection divides by the L1 norm, so re-encoding gives the code
+// back; for float16 / bfloat16 the renormalised value would not re-encode to
+// its code, so each thread keeps the exact decoded components of its own four
+// sites in registers and stores those.
 #include "device.h"
 #include "kernels.h"
 
 namespace hsg {
 
+// raw(s): the exact decoded value of the code an update stores (float16 /
+// bfloat16: the representable components, not renormalised; the others: what a
+// load returns). shared(raw): what LDS holds for every reader (decoded and
+// renormalised, as a load returns it).
 template <int STORE>
-struct TileRep;
-
-template <>
-struct TileRep<0> {
-    __device__ static __forceinline__ v3 after_update(v3 s) { return s; }
-    __device__ static __forceinline__ v3 read(v3 v) { return v; }
-    __device__ static __forceinline__ void load_pair(const float *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
+struct TileRep {
+    static constexpr bool kRaw = STORE == 1 || STORE == 2;  // own sites' codes kept in registers
+    __device__ static __forceinline__ v3 raw(v3 s)
     {
-        Codec<0>::load_pair(p, cs, j0, a, b);
+        if constexpr (STORE == 0) return s;
+        else if constexpr (STORE == 1)
+            return v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
+                      __half2float(__float2half_rn(s.z))};
+        else if constexpr (STORE == 2)
+            return v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
+                      bf16_to_f32(f32_to_bf16_rne(s.z))};
+        else return oct_decode(oct_encode(s));
+    }
+    __device__ static __forceinline__ v3 shared(v3 r)
+    {
+        if constexpr (kRaw) return normalise_rsq(r);
+        else return r;
     }
 };
 
-template <>
-struct TileRep<1> {
-    __device__ static __forceinline__ v3 after_update(v3 s)
-    {
-        return v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
-                  __half2float(__float2half_rn(s.z))};
-    }
-    __device__ static __forceinline__ v3 read(v3 v) { return normalise_rsq(v); }
-    __device__ static __forceinline__ void load_pair(const __half *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
-    {
+// The raw components of a float16 / bfloat16 pair as stored (no renormalisation).
+template <int STORE>
+__device__ __forceinline__ void load_raw_pair(const typename Codec<STORE>::T *p, uint32_t cs, uint32_t j0, v3 &a,
+                                              v3 &b)
+{
+    if constexpr (STORE == 1) {
         const __half2 x = *reinterpret_cast<const __half2 *>(p + j0);
         const __half2 y = *reinterpret_cast<const __half2 *>(p + cs + j0);
         const __half2 z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
         a = v3{__low2float(x), __low2float(y), __low2float(z)};
         b = v3{__high2float(x), __high2float(y), __high2float(z)};
-    }
-};
-
-template <>
-struct TileRep<2> {
-    __device__ static __forceinline__ v3 after_update(v3 s)
-    {
-        return v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
-                  bf16_to_f32(f32_to_bf16_rne(s.z))};
-    }
-    __device__ static __forceinline__ v3 read(v3 v) { return normalise_rsq(v); }
-    __device__ static __forceinline__ void load_pair(const uint16_t *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
-    {
+    } else if constexpr (STORE == 2) {
         const uint32_t x = *reinterpret_cast<const uint32_t *>(p + j0);
         const uint32_t y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
         const uint32_t z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
         a = v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)};
         b = v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u), __uint_as_float(z & 0xFFFF0000u)};
+    } else {
+        Codec<STORE>::load_pair(p, cs, j0, a, b);
     }
-};
-
-template <>
-struct TileRep<3> {
-    __device__ static __forceinline__ v3 after_update(v3 s) { return oct_decode(oct_encode(s)); }
-    __device__ static __forceinline__ v3 read(v3 v) { return v; }
-    __device__ static __forceinline__ void load_pair(const uint32_t *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
-    {
-        Codec<3>::load_pair(p, cs, j0, a, b);
-    }
-};
+}
 
 // Tile coordinates (Y, Z) of the q-th tile of coarse parity `phase`, in the
 // order Z, then Y.
@@ -169,7 +159,7 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
         const int64_t rep = (int64_t)d * a.slots_per_sample + chunk * a.RB + rr;
         const T *src = (const T *)a.spins + (rep * 2 + par) * C::kPlanes * (int64_t)Nh;
         v3 s0, s1;
-        R::load_pair(src, Nh, (uint32_t)((z * L + y) * Lh + 2 * xp), s0, s1);
+        C::load_pair(src, Nh, (uint32_t)((z * L + y) * Lh + 2 * xp), s0, s1);
         lds_put_pair(lds, ((rr * 2 + par) * 3 * RZ + lz) * RY * Lh + ly * Lh + 2 * xp, cs, s0, s1);
     }
 
@@ -204,11 +194,17 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
             hs[par][0] = hs[par][1] = v3{0.f, 0.f, 0.f};
         }
     }
+    v3 own_raw[2][2];  // float16 / bfloat16: exact components of my sites' current codes
+    if (R::kRaw && active) {
+#pragma unroll
+        for (int par = 0; par < 2; ++par)
+            load_raw_pair<STORE>(base + (int64_t)par * C::kPlanes * Nh, Nh, j0, own_raw[par][0], own_raw[par][1]);
+    }
     const uint32_t tsweep = *a.tptr;
     __syncthreads();
 
     auto at = [&](int par, int pz, int py, int xh) { return ((rb * 2 + par) * 3 * RZ + pz) * RY * Lh + py * Lh + xh; };
-    auto rd = [&](int w) { return R::read(v3{lds[w], lds[w + cs], lds[w + 2 * cs]}); };
+    auto rd = [&](int w) { return v3{lds[w], lds[w + cs], lds[w + 2 * cs]}; };
     auto half_round = [&](int kind, int p, uint32_t rep) {
         if (active) {
             const int qo = 1 - p;
@@ -242,7 +238,12 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
                                                a.key0, a.key1);
                 pair_update<STORE, 0>(nb0, nb1, jc[p], hs[p][0], hs[p][1], v3{}, v3{}, rr, beta, HW, s0, s1);
             }
-            lds_put_pair(lds, w, cs, R::after_update(s0), R::after_update(s1));
+            const v3 r0 = R::raw(s0), r1 = R::raw(s1);
+            if (R::kRaw) {
+                own_raw[p][0] = r0;
+                own_raw[p][1] = r1;
+            }
+            lds_put_pair(lds, w, cs, R::shared(r0), R::shared(r1));
         }
         __syncthreads();
     };
@@ -264,7 +265,12 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
             v3 s0, s1;
-            lds_get_pair(lds, at(par, lz, ly, xh0), cs, s0, s1);
+            if (R::kRaw) {
+                s0 = own_raw[par][0];
+                s1 = own_raw[par][1];
+            } else {
+                lds_get_pair(lds, at(par, lz, ly, xh0), cs, s0, s1);
+            }
             C::store_pair(base + (int64_t)par * C::kPlanes * Nh, Nh, j0, s0, s1);
         }
     }
