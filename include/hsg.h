@@ -280,6 +280,13 @@ hsg_status hsg_reset_stats(hsg_lattice *h, hsg_stream_t stream);
 hsg_status hsg_get_stats(const hsg_lattice *h, double *d_sums, uint32_t *d_trips, uint64_t *n_sweeps,
                          hsg_stream_t stream);
 
+/* Tuning (results do not depend on it): run the pairs of a sweep in batches of
+ * replicas, all pairs of one batch back to back so that its spins stay in the
+ * last-level cache, then the next batch (lattice sizes that use the z-march
+ * kernels; tempering after every batch). -1: off (default); 0: automatic
+ * (about 192 MiB of spins per batch); > 0: replicas per batch. */
+hsg_status hsg_set_batch(hsg_lattice *h, int64_t replicas);
+
 /* Replay whole sweeps as captured HIP graphs (default on; used when tempering
  * runs every sweep or never). Results do not depend on it. */
 hsg_status hsg_set_graphs(hsg_lattice *h, int32_t enable);

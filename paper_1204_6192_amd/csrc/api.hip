@@ -253,6 +253,7 @@ struct hsg_lattice {
     int32_t slots_per_item = 0;
     int32_t kernel_variant = 0;  // 0 automatic (= 3), 1 gather, 2 z-march, 3 z-march with fused pairs
     bool hw_math = false;        // heat bath with the hardware transcendentals (kernel kind 2)
+    int64_t batch = -1;   // replicas per sweep batch: -1 off, 0 automatic (about 192 MiB of spins)
     bool stats = false;   // accumulate run statistics after every sweep
     uint64_t n_stats = 0;  // sweeps accumulated since the last reset
     // Markov chain: 0 the full-lattice checkerboard, 1 the tile-local chain
@@ -330,8 +331,10 @@ bool use_pair(const hsg_lattice *h, const Group &g)
     return g.stream_ok && g.s_TY == g.L;
 }
 
-hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep, bool pair)
+hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep, bool pair,
+                            int64_t r0 = 0, int64_t r1 = -1)
 {
+    if (r1 < 0) r1 = g.n_rep;
     hsg::StreamArgs a{};
     a.spins = h->state + g.o_spins;
     a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
@@ -341,7 +344,8 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     a.beta32 = reinterpret_cast<const float *>(h->coup + g.o_b32);
     a.e_partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
     a.Nh = g.Nh;
-    a.n_rep = g.n_rep;
+    a.n_rep = r1;
+    a.r_base = r0;
     a.L = g.L;
     a.Lh = g.L / 2;
     a.P = g.L / 4;
@@ -351,7 +355,7 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     a.n_ytiles = g.s_ytiles;
     a.n_zslabs = pair ? 1 : g.s_zslabs;
     a.zlen = g.L / a.n_zslabs;
-    const int64_t nb = (g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles * a.n_zslabs;
+    const int64_t nb = (r1 - r0 + g.s_RB - 1) / g.s_RB * g.s_ytiles * a.n_zslabs;
     a.n_blocks = nb > 0x7FFFFFFFll ? -1 : (int32_t)nb;
     a.slots_per_sample = g.O * g.T;
     a.T = g.T;
@@ -370,8 +374,12 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
 // launch); the others use the gather kernel one group at a time. The energy of
 // every selected group is reduced afterwards when `energy` is set.
 template <class Pick>
+// Launches one half-sweep (pair = false) or one fused pair (pair = true) for
+// the groups `pick` selects, over replicas [r0, r1) of each (r1 < 0: all), and
+// with energy, reduces the partial sums into E unless reduce is false (the
+// caller reduces once every replica range is done).
 hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy, bool pair, Pick pick,
-                      hipStream_t s)
+                      hipStream_t s, int64_t r0 = 0, int64_t r1 = -1, bool reduce = true)
 {
     if (kind == 0 && h->hw_math) kind = 2;
     hsg::MultiStreamArgs m{};
@@ -397,7 +405,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
                 hsg_status st = flush();
                 if (st != HSG_OK) return st;
             }
-            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep, pair);
+            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep, pair, r0, r1);
             const int64_t nb = (int64_t)a.n_blocks;
             if (nb < 0 || blocks + nb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
             m.block_start[m.n_groups] = (int32_t)blocks;
@@ -408,6 +416,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
             const size_t l = (size_t)(pair ? 18 : 6) * a.RB * a.rows * a.Lh * sizeof(float);
             lds = l > lds ? l : lds;
         } else {
+            if (r0 != 0 || (r1 >= 0 && r1 != g.n_rep)) return fail(HSG_E_STATE, "replica ranges need the z-march");
             const hsg::SweepArgs a = sweep_args(h, g, parity, (uint32_t)rep);
             if ((int64_t)g.D * a.n_chunks * a.n_pb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
             const hipError_t e = hsg::launch_half_sweep(a, h->storage, kind, g.field, energy, s);
@@ -416,7 +425,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
     }
     hsg_status st = flush();
     if (st != HSG_OK) return st;
-    if (energy) {
+    if (energy && reduce) {
         for (const Group &g : h->lay.g) {
             if (!pick(g)) continue;
             const int n_pb = pair ? 1 : use_stream(h, g) ? g.s_ytiles * g.s_zslabs : g.n_pb_sweep;
@@ -436,25 +445,40 @@ hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool en
 // A pair of half-sweeps (parity 0, then parity 1) of every group: fused where
 // the group holds whole planes, as two single passes otherwise. `energy`: the
 // parity-1 pass computes the energies.
-hsg_status run_pair(hsg_lattice *h, int kind, int rep, bool energy, hipStream_t s)
+hsg_status run_pair(hsg_lattice *h, int kind, int rep, bool energy, hipStream_t s, const Group *only = nullptr,
+                    int64_t r0 = 0, int64_t r1 = -1, bool reduce = true)
 {
     bool any_pair = false, any_single = false;
     for (const Group &g : h->lay.g) {
+        if (only != nullptr && &g != only) continue;
         any_pair = any_pair || use_pair(h, g);
         any_single = any_single || !use_pair(h, g);
     }
     if (any_pair) {
-        hsg_status st = run_groups(h, kind, 0, rep, energy, true, [h](const Group &g) { return use_pair(h, g); }, s);
+        auto fused = [h, only](const Group &g) { return (only == nullptr || &g == only) && use_pair(h, g); };
+        hsg_status st = run_groups(h, kind, 0, rep, energy, true, fused, s, r0, r1, reduce);
         if (st != HSG_OK) return st;
     }
     if (any_single) {
-        auto single = [h](const Group &g) { return !use_pair(h, g); };
-        hsg_status st = run_groups(h, kind, 0, rep, false, false, single, s);
-        if (st == HSG_OK) st = run_groups(h, kind, 1, rep, energy, false, single, s);
+        auto single = [h, only](const Group &g) { return (only == nullptr || &g == only) && !use_pair(h, g); };
+        hsg_status st = run_groups(h, kind, 0, rep, false, false, single, s, r0, r1, reduce);
+        if (st == HSG_OK) st = run_groups(h, kind, 1, rep, energy, false, single, s, r0, r1, reduce);
         if (st != HSG_OK) return st;
     }
     return HSG_OK;
 }
+
+// Replicas per batch of the sweep for group g (0: no batching). A batch's pairs
+// run back to back, so the batch's spins stay in the last-level cache.
+int64_t batch_of(const hsg_lattice *h, const Group &g)
+{
+    if (h->batch < 0 || !use_stream(h, g)) return 0;
+    const int64_t per_rep = 2 * g.Nh * (int64_t)bytes_per_spin(h->storage);
+    int64_t b = h->batch > 0 ? h->batch : (int64_t)(192ll << 20) / per_rep;
+    if (b < 1) b = 1;
+    return b < g.n_rep ? b : 0;
+}
+
 
 // purpose 1: in-sweep pass, counter read from the device; 2: standalone pass.
 hsg_status run_pt(hsg_lattice *h, uint32_t ctr1, uint32_t purpose, hipStream_t s)
@@ -612,13 +636,44 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
         return HSG_OK;
     }
     const int last_kind = h->n_or > 0 ? 1 : 0;
-    for (int r = 0; r < h->n_hb; ++r) {
-        hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s);
-        if (st != HSG_OK) return st;
-    }
-    for (int r = 0; r < h->n_or; ++r) {
-        hsg_status st = run_pair(h, 1, 0, r == h->n_or - 1, s);
-        if (st != HSG_OK) return st;
+    bool batched = false;
+    for (const Group &g : h->lay.g) batched = batched || batch_of(h, g) > 0;
+    if (!batched) {
+        for (int r = 0; r < h->n_hb; ++r) {
+            hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s);
+            if (st != HSG_OK) return st;
+        }
+        for (int r = 0; r < h->n_or; ++r) {
+            hsg_status st = run_pair(h, 1, 0, r == h->n_or - 1, s);
+            if (st != HSG_OK) return st;
+        }
+    } else {
+        // Replicas never interact within the pairs of a sweep: all pairs of one
+        // batch of replicas run back to back (the batch stays in the last-level
+        // cache), then the next batch; the same updates in the same order per
+        // replica, so the same bits.
+        for (const Group &g : h->lay.g) {
+            const int64_t b = batch_of(h, g);
+            const int64_t step = b > 0 ? b : g.n_rep;
+            for (int64_t r0 = 0; r0 < g.n_rep; r0 += step) {
+                const int64_t r1 = std::min<int64_t>(g.n_rep, r0 + step);
+                for (int r = 0; r < h->n_hb; ++r) {
+                    hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s, &g, r0, r1, b == 0);
+                    if (st != HSG_OK) return st;
+                }
+                for (int r = 0; r < h->n_or; ++r) {
+                    hsg_status st = run_pair(h, 1, 0, r == h->n_or - 1, s, &g, r0, r1, b == 0);
+                    if (st != HSG_OK) return st;
+                }
+            }
+            if (b > 0) {  // one reduction over every batch's partial sums
+                const int n_pb = use_pair(h, g) ? 1 : g.s_ytiles * g.s_zslabs;
+                const hipError_t e = hsg::launch_reduce_partials(reinterpret_cast<double *>(h->scratch + g.o_scr),
+                                                                 n_pb, g.n_rep,
+                                                                 reinterpret_cast<double *>(h->state + g.o_E), s);
+                if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
+            }
+        }
     }
     if (pt) {
         hsg_status st = run_pt(h, 0u, 1u, s);
@@ -1257,6 +1312,15 @@ hsg_status hsg_get_stats(const hsg_lattice *h, double *d_sums, uint32_t *d_trips
         if (e != hipSuccess) return hip_fail(e, "get_stats");
     }
     if (n_sweeps) *n_sweeps = h->n_stats;
+    return HSG_OK;
+}
+
+hsg_status hsg_set_batch(hsg_lattice *h, int64_t replicas)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (replicas < -1) return fail(HSG_E_INVALID, "replicas per batch = %lld, need -1, 0 or > 0", (long long)replicas);
+    h->batch = replicas;
+    drop_graphs(h);
     return HSG_OK;
 }
 

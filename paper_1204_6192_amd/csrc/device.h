@@ -112,11 +112,13 @@ __device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
 
 // ---------------------------------------------------------------- Eq. (2)
 // New spin drawn from exp(beta h.s): c = cos(angle to h) by inverting the CDF
-// of exp(kappa c) on [-1, 1], kappa = beta |h|, with two algebraically equal
-// forms of c = 1 + ln(u + (1 - u) e^{-2 kappa}) / kappa chosen for float32
-// accuracy: log1p/expm1 for small kappa (no loss near c = 2u - 1), log/exp for
-// larger kappa (the argument is a sum of two positive terms, so it never
-// cancels, and e^{-2 kappa} only underflows). Azimuth 2 pi u2 about h in the
+// of exp(kappa c) on [-1, 1], kappa = beta |h|, with algebraically equal forms
+// of c = 1 + ln(x) / kappa, x = u + (1 - u) e^{-2 kappa}, chosen for float32
+// accuracy: for small kappa log1p(-(1 - u)(1 - e^{-2 kappa})) with expm1 (no
+// loss near c = 2u - 1); for larger kappa the same log1p while x >= 1/2 (new
+// spins close to the field, where 1 - c must keep its relative precision) and
+// ln of the sum x of two positive terms below 1/2 (no cancellation; e^{-2 kappa}
+// only underflows); 1 + c from its own log1p form when c < 0. Azimuth 2 pi u2 about h in the
 // frame of Frisvad (JGT 2012), which is continuous except at n = -z (a frame
 // with a jump along a whole great circle would turn float32 rounding of h into
 // O(1) jumps of the new spin); 1 + n_z is formed without cancellation for
@@ -144,24 +146,36 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         rs = 1.0f / hn;
     }
     const float kappa = beta * hn;
-    // omc = 1 - c is formed directly (it is -ln(...) / kappa), so neither c nor
-    // the transverse length sqrt((1 - c)(1 + c)) loses precision when c -> 1.
+    // omc = 1 - c and opc = 1 + c are each formed directly (omc = -ln(x) / kappa;
+    // opc = ln(u e^{2 kappa} + 1 - u) / kappa when c < 0), so neither loses its
+    // relative precision at its end of [-1, 1], nor does the transverse length
+    // sqrt(omc opc).
     v3 n;
-    float omc;
+    float omc, opc;
     if (hh == 0.0f || !(kappa > 0.0f)) {
         n = v3{0.0f, 0.0f, 1.0f};
         omc = 2.0f * (1.0f - u1);  // c = 2 u1 - 1, exact
+        opc = 2.0f * u1;
     } else {
         n = scale3(h, rs);
         const float omu = 1.0f - u1;  // exact on the 2^-24 grid
         float lg;
-        if (kappa < 0.5f)
+        if (kappa < 0.5f) {
             lg = log1pf(omu * expm1f(-2.0f * kappa));
-        else
-            lg = logf(fmaf(omu, expf(-2.0f * kappa), u1));
+        } else {
+            const float e2k = expf(-2.0f * kappa);
+            const float x = fmaf(omu, e2k, u1);  // u + (1 - u) e^{-2 kappa}, both terms positive
+            lg = x >= 0.5f ? log1pf(-omu * (1.0f - e2k)) : logf(x);
+        }
         omc = fminf(2.0f, fmaxf(0.0f, HW ? -lg * hw_rcp(kappa) : -lg / kappa));
+        if (omc > 1.0f) {  // c < 0: only for kappa < 17 (u >= 2^-24), so e^{2 kappa} is finite
+            const float l2 = log1pf(u1 * expm1f(2.0f * kappa));
+            opc = fminf(2.0f, fmaxf(0.0f, HW ? l2 * hw_rcp(kappa) : l2 / kappa));
+        } else {
+            opc = 2.0f - omc;
+        }
     }
-    const float c = 1.0f - omc;
+    const float c = omc <= 1.0f ? 1.0f - omc : opc - 1.0f;
     v3 e1, e2;
     const float rxy = fmaf(n.x, n.x, n.y * n.y);
     if (n.z < 0.0f && rxy == 0.0f) {
@@ -179,11 +193,11 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
     }
     float st, sp, cp;
     if constexpr (HW) {
-        st = __builtin_amdgcn_sqrtf(omc * (2.0f - omc));
+        st = __builtin_amdgcn_sqrtf(omc * opc);
         sp = hw_sin_rev(u2);
         cp = hw_cos_rev(u2);
     } else {
-        st = sqrtf(omc * (2.0f - omc));
+        st = sqrtf(omc * opc);
         sincospif(2.0f * u2, &sp, &cp);
     }
     const float ta = st * cp, tb = st * sp;

@@ -48,7 +48,8 @@ struct StreamArgs {
     const int32_t *temp_of_slot;
     const float *beta32;
     double *e_partials;
-    int64_t Nh, n_rep;
+    int64_t Nh, n_rep;  // n_rep: end of the replica range of the launch
+    int64_t r_base;     // first replica of the range (canonical order within the group)
     int32_t L, Lh, P, TY, RB, rows, n_ytiles, n_blocks;
     int32_t n_zslabs, zlen;
     int32_t slots_per_sample, T;

@@ -42,7 +42,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     const int rb = tid / per_rep;
     const int rem = tid - rb * per_rep;
     const int ty = rem / a.P, m = rem - ty * a.P;
-    const int64_t r_lane = (int64_t)rblk * a.RB + rb;  // replica (canonical order within the group)
+    const int64_t r_lane = a.r_base + (int64_t)rblk * a.RB + rb;  // replica (canonical order within the group)
     const bool active = rb < a.RB && r_lane < a.n_rep;
     const int L = a.L, Lh = a.Lh;
     const uint32_t Nh = (uint32_t)a.Nh;
@@ -207,7 +207,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
         red[tid] = e;
         __syncthreads();
         if (tid < a.RB) {
-            const int64_t r2 = (int64_t)rblk * a.RB + tid;
+            const int64_t r2 = a.r_base + (int64_t)rblk * a.RB + tid;
             if (r2 < a.n_rep) {
                 double s = 0.0;
                 for (int k = 0; k < per_rep; ++k) s += red[tid * per_rep + k];
@@ -303,7 +303,7 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
     const int rb = tid / per_rep;
     const int rem = tid - rb * per_rep;
     const int ty = rem / a.P, m = rem - ty * a.P;
-    const int64_t r_lane = (int64_t)lb * a.RB + rb;
+    const int64_t r_lane = a.r_base + (int64_t)lb * a.RB + rb;
     const bool active = rb < a.RB && r_lane < a.n_rep;
     const int L = a.L, Lh = a.Lh;
     const uint32_t Nh = (uint32_t)a.Nh;
@@ -468,7 +468,7 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         red[tid] = e;
         __syncthreads();
         if (tid < a.RB) {
-            const int64_t r2 = (int64_t)lb * a.RB + tid;
+            const int64_t r2 = a.r_base + (int64_t)lb * a.RB + tid;
             if (r2 < a.n_rep) {
                 double sum = 0.0;
                 for (int k = 0; k < per_rep; ++k) sum += red[tid * per_rep + k];

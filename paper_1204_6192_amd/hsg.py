@@ -93,6 +93,7 @@ _SIG = {
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
     "hsg_measure_pair_overlaps": [_vp, _vp, _vp],
     "hsg_measure_kmodes": [_vp, _vp, _vp],
+    "hsg_set_batch": [_vp, _i64],
     "hsg_set_stats": [_vp, _i32],
     "hsg_reset_stats": [_vp, _vp],
     "hsg_get_stats": [_vp, _vp, _vp, _vp, _vp],
@@ -315,6 +316,10 @@ class Lattice:
         """0: full-lattice checkerboard (default); 1: the tile-local chain with tiles
         of L x tile_y x tile_z sites (0 = L) and n_hit repetitions per visit."""
         check(lib.hsg_set_chain(self.h, int(chain), int(tile_y), int(tile_z), int(n_hit)))
+
+    def set_batch(self, replicas: int) -> None:
+        """Replicas per sweep batch: -1 off, 0 automatic, > 0 explicit."""
+        check(lib.hsg_set_batch(self.h, int(replicas)))
 
     def set_stats(self, enable: bool = True) -> None:
         """Accumulate per-rung sums of E, E^2 and tempering round trips after every sweep."""

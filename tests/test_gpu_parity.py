@@ -715,13 +715,17 @@ def test_gpu_over_relaxation_energy_drift(hsg):
 
 def test_gpu_long_run_statistics_vs_oracle(hsg, oracle_lib):
     """Long runs of the GPU and the oracle from the same start (eight disorder
-    samples of the tiny workload's lattice and ladder, 500 sweeps): per-rung mean
+    samples of L = 8, 2 x 8 temperatures in [0.2, 0.6], 500 sweeps): per-rung mean
     energy and overlap q^2 over sweeps 100..500 agree. Errors from 10 time blocks
     per sample and run, summed over samples. The 16 per-rung z-scores must lie
     within 3.5 sigma (a 3-sigma family-wise level for 8 rungs per observable) and
-    the rung-averaged z-score of each observable within 3 sigma."""
+    the rung-averaged z-score of each observable within 3 sigma. The ladder is
+    where these error bars hold: pairs of oracle runs that differ only in their
+    seed give z-scores of rms 1.0 here, but rms 1.3 (E) and 1.6 (q^2), with
+    values beyond 4, on [0.1, 0.3], where q^2 on L = 8 stays correlated over
+    hundreds of sweeps; the glassy range is covered by the per-spin tests."""
     rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 50))
-    g = inputs.make_group(rng, 8, 8, 2, inputs.geometric_ladder(0.10, 0.30, 8))
+    g = inputs.make_group(rng, 8, 8, 2, inputs.geometric_ladder(0.20, 0.60, 8))
     seed = inputs.PHILOX_KEY_BASE + 50
     lat = _lat(hsg, [g], seed)
     o = oracle_lib.Oracle.from_group(g, seed=seed)
@@ -823,6 +827,30 @@ def test_autotune_keeps_the_chain(hsg):
     assert torch.equal(a.get_temp_map(), ref.get_temp_map())
     # the fused energies of the last trial sweep were summed in another grouping
     assert torch.allclose(a.get_energies(), ref.get_energies(), rtol=1e-12, atol=1e-9)
+
+
+def test_replica_batches_bit_identical(hsg):
+    """Sweeps run in batches of replicas (all pairs of a batch back to back) give
+    the same spins, maps and energies as unbatched sweeps: fused-pair lattices
+    (L = 8, 16), a single-pass z-march lattice (L = 36) and a gather-kernel one
+    (L = 6, never batched), batch sizes that do and do not divide the replica
+    count, with graphs."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 62))
+    groups, uid = [], 0
+    for L, D, T in ((8, 3, 5), (16, 2, 3), (36, 1, 2), (6, 2, 2)):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, T),
+                                        sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 62
+    ref = _lat(hsg, groups, seed)
+    ref.sweep(4)
+    for batch in (1, 3, 7, 0):
+        lat = _lat(hsg, groups, seed)
+        lat.set_batch(batch)
+        lat.sweep(4)
+        assert torch.equal(lat.get_spins(), ref.get_spins()), batch
+        assert torch.equal(lat.get_temp_map(), ref.get_temp_map()), batch
+        assert torch.equal(lat.get_energies(), ref.get_energies()), batch
 
 
 @pytest.mark.parametrize("pt_every", [1, 0, 3])
