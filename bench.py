@@ -8,10 +8,12 @@ Default workload: L = 32, 64 disorder samples x 2 copies x 32 temperatures
 4096 replicas, 134,217,728 spins. Inputs are seeded and synthetic.
 
 Prints one JSON line: ns per spin update (t / (steps x 5 x spins), the paper's
-per-update time), the roofline of the dominant kernel (the over-relaxation pair,
-HBM-bound; one fused launch for lattices up to L = 32) from HIP events on the
+per-update time), the roofline of the dominant kernel from HIP events on the
 library's stream, and the float64 oracle timed on a bounded sample of the same
-workload on host cores.
+workload on host cores. The dominant kernel is the over-relaxation work: for
+lattices up to L = 32 two over-relaxation pairs run as one z-march (four
+half-sweeps per read and write of the spins); larger lattices run each pair
+separately. Both lie below the roofline ridge, so their roofline is HBM's.
 """
 
 import argparse
@@ -24,6 +26,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# Published FP32 vector peak of the MI355X (TFLOP/s, an FMA counting two flops).
+PEAK_FP32_TFLOPS = 157.3
+# FP32 flops one over-relaxation update needs as written (Eq. (3)): the local
+# field 18 FMA (36); h.h and s.h 5 each; 2 (s.h) / (h.h) 2; the reflection 3 FMA
+# (6); the compensated renormalisation 36 (three squares with their rounding
+# errors 9, two error-free sums 12, the deviation from 1 6, the second-order
+# correction 3, the rescaling 6).
+OR_FLOPS_PER_UPDATE = 36 + 5 + 5 + 2 + 6 + 36
 METRIC = "ns per spin update (HB+OR) & achieved HBM GB/s, FP32 vs batched+compressed"
 STORE_BYTES = {"f32": 12, "f16": 6, "bf16": 6, "qangle": 4}
 
@@ -35,6 +45,19 @@ def log(*a):
 def fused(g):
     """Both half-sweeps of a pair run as one z-march when the plane fits a work-group."""
     return g.L % 4 == 0 and g.L * g.L // 4 <= 256
+
+
+def or_bytes_two_pairs(groups, storage):
+    """HBM bytes two over-relaxation pairs fused into one z-march must move: every
+    stored spin read and written once (2 b_s per site), the couplings (and field)
+    once per sample per half-sweep."""
+    bs = STORE_BYTES[storage]
+    total = 0.0
+    for g in groups:
+        coupling = 1 if g.coupling_kind == 1 else 6 * 4
+        shared = coupling + (12 if g.H is not None else 0)
+        total += g.n_slots * g.N * 2.0 * bs + 2 * g.n_samples * g.N * shared
+    return total
 
 
 def algorithmic_bytes(groups, storage, kind):
@@ -64,18 +87,20 @@ def algorithmic_bytes(groups, storage, kind):
 
 def time_kernel(lat, kind, n, torch):
     """Average duration of one pair of half-sweeps (one fused launch for lattices
-    up to L = 32), from HIP events on the stream the library launches on (torch's
-    current stream)."""
+    up to L = 32; kind 3: two over-relaxation pairs as inside a sweep, one launch
+    where they fuse), from HIP events on the stream the library launches on
+    (torch's current stream)."""
     stream = torch.cuda.current_stream()
-    lat.pair_sweep(kind)
+    call = (lambda: lat.or_pairs(2)) if kind == 3 else (lambda: lat.pair_sweep(kind))
+    call()
     torch.cuda.synchronize()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for _ in range(n):
-        lat.pair_sweep(kind)
+        call()
     stop.record(stream)
     stop.synchronize()
-    return start.elapsed_time(stop) / n * 1e-3  # seconds per pair
+    return start.elapsed_time(stop) / n * 1e-3  # seconds per call
 
 
 def time_analysis(lat, inst, torch, reps=5):
@@ -168,6 +193,38 @@ def cpu_baseline(inst, sweeps, log_fn):
                       f"{sweeps} sweeps, {updates} updates, {dt:.1f} s"}
 
 
+def roofline(inst, quad, t_or, b_or, t_quad, b_quad, t_hb, b_hb, t_hb_hw, traffic, traffic_src,
+             copy_gbs):
+    """HBM roofline of the dominant kernel: the over-relaxation work, two pairs in
+    one z-march for lattices up to L = 32 (else one pair per launch). Its
+    arithmetic intensity (OR_FLOPS_PER_UPDATE flops per update against the
+    algorithmic bytes) lies below the ridge of the published peaks (157.3 TFLOP/s
+    / 8 TB/s), so the roofline that bounds it is HBM's: achieved = algorithmic
+    bytes per launch / mean launch time from HIP events, peak = 8 TB/s."""
+    updates = sum(g.n_slots * g.N for g in inst.groups)  # per pair of half-sweeps
+    if quad:
+        t, nbytes, nupd = t_quad, b_quad, 2 * updates
+        kernel = "k_or_quad_stream (two over-relaxation pairs, one launch)"
+    else:
+        t, nbytes, nupd = t_or, b_or, updates
+        kernel = ("k_pair_stream (over-relaxation pair, one launch)" if all(fused(g) for g in inst.groups)
+                  else "over-relaxation pair (z-march launches)")
+    gbs = nbytes / t / 1e9
+    flops = nupd * OR_FLOPS_PER_UPDATE
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "traffic": traffic,
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+            "traffic_vs_algorithmic": None if traffic is None else traffic / nbytes,
+            "traffic_source": traffic_src, "launch_us": t * 1e6, "bytes_per_launch": nbytes,
+            "updates_per_launch": nupd, "frac_of_copy": gbs / copy_gbs, "device_copy_gbs": copy_gbs,
+            "flops_per_update": OR_FLOPS_PER_UPDATE, "flop_per_byte": flops / nbytes,
+            "ridge_flop_per_byte": PEAK_FP32_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9),
+            "tflops": flops / t / 1e12,
+            "or_pair_us": t_or * 1e6, "or_pair_gbs": b_or / t_or / 1e9,
+            "or_pair_hbm_frac": b_or / t_or / 1e9 / PEAK_HBM_GBS,
+            "hb_pair_us": t_hb * 1e6, "hb_gbs": b_hb / t_hb / 1e9, "hb_pair_us_hw_math": t_hb_hw * 1e6}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,11 +308,15 @@ def main():
     ns_update = dt / updates * 1e9
     log(f"{args.steps} sweeps in {dt:.3f} s: {ns_update * 1e3:.2f} ps/update")
 
-    # dominant kernel: the over-relaxation pair (4 of the 5 pairs of a sweep)
+    # the kernels of a sweep: heat-bath pair, over-relaxation pair, and two
+    # over-relaxation pairs in one z-march where every lattice fuses them
+    quad = inst.n_or >= 2 and all(fused(g) for g in inst.groups)
     t_or = time_kernel(lat, 1, args.kernel_launches, torch)
     t_hb = time_kernel(lat, 0, max(4, args.kernel_launches // 4), torch)
+    t_quad = time_kernel(lat, 3, max(4, args.kernel_launches // 2), torch) if quad else None
     b_or = algorithmic_bytes(inst.groups, inst.storage, 1)
     b_hb = algorithmic_bytes(inst.groups, inst.storage, 0)
+    b_quad = or_bytes_two_pairs(inst.groups, inst.storage)
     lat.set_math(1)
     t_hb_hw = time_kernel(lat, 0, max(4, args.kernel_launches // 4), torch)
     lat.set_math(0)
@@ -263,7 +324,13 @@ def main():
     log(f"HB pair with hardware transcendentals: {t_hb_hw * 1e6:.1f} us")
     log(f"OR pair: {t_or * 1e6:.1f} us, {b_or / 1e9:.3f} GB -> {gbs_or:.0f} GB/s; "
         f"HB pair: {t_hb * 1e6:.1f} us, {b_hb / 1e9:.3f} GB -> {b_hb / t_hb / 1e9:.0f} GB/s")
-    eff_gbs = (inst.n_hb * b_hb + inst.n_or * b_or) / (dt / args.steps) / 1e9
+    if quad:
+        log(f"two OR pairs in one z-march: {t_quad * 1e6:.1f} us, {b_quad / 1e9:.3f} GB -> "
+            f"{b_quad / t_quad / 1e9:.0f} GB/s")
+        b_sweep_or = (inst.n_or // 2) * b_quad + (inst.n_or % 2) * b_or
+    else:
+        b_sweep_or = inst.n_or * b_or
+    eff_gbs = (inst.n_hb * b_hb + b_sweep_or) / (dt / args.steps) / 1e9
 
     analysis = time_analysis(lat, inst, torch)
     log("analysis: " + ", ".join(f"{k} {v:.1f}" for k, v in analysis.items()))
@@ -295,19 +362,8 @@ def main():
         "build_id": hsg.build_id(),
         "data": "synthetic", "config": cfg,
         "effective_gbs": eff_gbs,
-        "roofline": {"bound": "hbm",
-                     "kernel": ("k_pair_stream (over-relaxation pair, one launch)"
-                                if all(fused(g) for g in inst.groups) else
-                                "over-relaxation pair (z-march launches)"),
-                     "achieved": gbs_or, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": gbs_or / PEAK_HBM_GBS, "traffic": traffic,
-                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-                     "traffic_vs_algorithmic": None if traffic is None else traffic / b_or,
-                     "traffic_source": traffic_src,
-                     "launch_us": t_or * 1e6, "bytes_per_launch": b_or,
-                     "hb_pair_us": t_hb * 1e6, "hb_gbs": b_hb / t_hb / 1e9,
-                     "hb_pair_us_hw_math": t_hb_hw * 1e6,
-                     "device_copy_gbs": copy_gbs, "frac_of_copy": gbs_or / copy_gbs},
+        "roofline": roofline(inst, quad, t_or, b_or, t_quad, b_quad, t_hb, b_hb, t_hb_hw, traffic,
+                             traffic_src, copy_gbs),
         "cpu_baseline": cpu,
         "analysis": analysis,
     }

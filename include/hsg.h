@@ -140,6 +140,12 @@ hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t 
  * else two passes. Uses the current sweep counter and does not advance it. */
 hsg_status hsg_pair_sweep(hsg_lattice *h, int32_t kind, int32_t rep, hsg_stream_t stream);
 
+/* n_pairs >= 1 over-relaxation pairs (Eq. (3); parity 0, then 1, each time) of
+ * every replica, as inside hsg_sweep: two by two in one launch where the kernel
+ * variant allows it, the odd one as a pair. Deterministic, so it needs no
+ * counter; energies are not computed. */
+hsg_status hsg_or_pairs(hsg_lattice *h, int32_t n_pairs, hsg_stream_t stream);
+
 /* One standalone tempering pass over every ladder using the energies of the
  * last sweep (or of the last hsg_measure_energy); advances the standalone-call
  * counter. */
@@ -217,7 +223,9 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
  * 2 = the z-march kernel, one launch per half-sweep (L % 4 == 0; other sizes
  * keep the gather kernel); 3 = the z-march kernel with both half-sweeps of a
  * pair in one launch where the whole plane fits a work-group (L <= 32), else
- * as 2; 0 = automatic (currently 3). */
+ * as 2; 4 = as 3, and the over-relaxation pairs of a sweep two by two in one
+ * launch (four half-sweeps per read and write of the spins) where eleven
+ * staged planes fit the work-group's LDS; 0 = automatic (currently 4). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
 /* Arithmetic of the heat-bath draw (Eq. (2)). 0 (default): correctly rounded

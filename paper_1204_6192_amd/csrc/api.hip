@@ -251,7 +251,10 @@ struct hsg_lattice {
     uint64_t t = 0, pt_calls = 0;
     char *state = nullptr, *coup = nullptr, *field = nullptr, *scratch = nullptr;
     int32_t slots_per_item = 0;
-    int32_t kernel_variant = 0;  // 0 automatic (= 3), 1 gather, 2 z-march, 3 z-march with fused pairs
+    // 0 automatic (= 4), 1 gather, 2 z-march, 3 z-march with fused pairs, 4 fused pairs and
+    // over-relaxation pairs fused two by two
+    int32_t kernel_variant = 0;
+    size_t max_lds = 64 * 1024;  // LDS bytes per work-group the device allows
     bool hw_math = false;        // heat bath with the hardware transcendentals (kernel kind 2)
     int64_t batch = -1;   // replicas per sweep batch: -1 off, 0 automatic (about 192 MiB of spins)
     bool stats = false;   // accumulate run statistics after every sweep
@@ -331,7 +334,23 @@ bool use_pair(const hsg_lattice *h, const Group &g)
     return g.stream_ok && g.s_TY == g.L;
 }
 
-hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep, bool pair,
+// LDS floats per replica of a fused z-march over whole planes: 6 planes for a
+// pair, 11 for two over-relaxation pairs, each 3 components of L x L/2.
+size_t fused_lds_bytes(const Group &g, int fuse)
+{
+    const size_t planes = fuse == 2 ? 11 : fuse == 1 ? 6 : 2;
+    return planes * (size_t)g.s_RB * 3 * (size_t)g.s_rows * (size_t)(g.L / 2) * sizeof(float);
+}
+
+// Two over-relaxation pairs in one z-march, where the pair is fused and the
+// eleven staged planes fit the work-group's LDS.
+bool use_quad(const hsg_lattice *h, const Group &g)
+{
+    if (h->kernel_variant != 0 && h->kernel_variant != 4) return false;
+    return use_pair(h, g) && fused_lds_bytes(g, 2) <= h->max_lds;
+}
+
+hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, uint32_t rep, int fuse,
                             int64_t r0 = 0, int64_t r1 = -1)
 {
     if (r1 < 0) r1 = g.n_rep;
@@ -353,7 +372,7 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     a.RB = g.s_RB;
     a.rows = g.s_rows;
     a.n_ytiles = g.s_ytiles;
-    a.n_zslabs = pair ? 1 : g.s_zslabs;
+    a.n_zslabs = fuse ? 1 : g.s_zslabs;
     a.zlen = g.L / a.n_zslabs;
     const int64_t nb = (r1 - r0 + g.s_RB - 1) / g.s_RB * g.s_ytiles * a.n_zslabs;
     a.n_blocks = nb > 0x7FFFFFFFll ? -1 : (int32_t)nb;
@@ -368,17 +387,15 @@ hsg::StreamArgs stream_args(const hsg_lattice *h, const Group &g, int parity, ui
     return a;
 }
 
-// One half-sweep (pair = false, of parity `parity`) or one fused pair of
-// half-sweeps (pair = true) for the groups selected by `pick`: the z-march
+// Launches one half-sweep of parity `parity` (fuse = 0), one fused pair
+// (fuse = 1) or two fused over-relaxation pairs (fuse = 2) for the groups
+// `pick` selects, over replicas [r0, r1) of each (r1 < 0: all). The z-march
 // groups go into as few launches as possible (up to kMaxStreamGroups per
-// launch); the others use the gather kernel one group at a time. The energy of
-// every selected group is reduced afterwards when `energy` is set.
+// launch); the others use the gather kernel one group at a time. With energy,
+// the partial sums are reduced into E unless reduce is false (the caller
+// reduces once every replica range is done).
 template <class Pick>
-// Launches one half-sweep (pair = false) or one fused pair (pair = true) for
-// the groups `pick` selects, over replicas [r0, r1) of each (r1 < 0: all), and
-// with energy, reduces the partial sums into E unless reduce is false (the
-// caller reduces once every replica range is done).
-hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy, bool pair, Pick pick,
+hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy, int fuse, Pick pick,
                       hipStream_t s, int64_t r0 = 0, int64_t r1 = -1, bool reduce = true)
 {
     if (kind == 0 && h->hw_math) kind = 2;
@@ -390,7 +407,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
         if (m.n_groups == 0) return HSG_OK;
         m.block_start[m.n_groups] = (int32_t)blocks;
         m.n_blocks = (int32_t)blocks;
-        const hipError_t e = hsg::launch_half_sweep_stream(m, h->storage, kind, energy, pair, threads, lds, s);
+        const hipError_t e = hsg::launch_half_sweep_stream(m, h->storage, kind, energy, fuse, threads, lds, s);
         m = hsg::MultiStreamArgs{};
         threads = 0;
         lds = 0;
@@ -400,12 +417,12 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
     };
     for (const Group &g : h->lay.g) {
         if (!pick(g)) continue;
-        if (pair || use_stream(h, g)) {
+        if (fuse || use_stream(h, g)) {
             if (m.n_groups == hsg::kMaxStreamGroups) {
                 hsg_status st = flush();
                 if (st != HSG_OK) return st;
             }
-            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep, pair, r0, r1);
+            const hsg::StreamArgs a = stream_args(h, g, parity, (uint32_t)rep, fuse, r0, r1);
             const int64_t nb = (int64_t)a.n_blocks;
             if (nb < 0 || blocks + nb > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "grid too large");
             m.block_start[m.n_groups] = (int32_t)blocks;
@@ -413,7 +430,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
             blocks += nb;
             const unsigned t = (unsigned)((a.RB * a.TY * a.P + 63) / 64 * 64);
             threads = t > threads ? t : threads;
-            const size_t l = (size_t)(pair ? 18 : 6) * a.RB * a.rows * a.Lh * sizeof(float);
+            const size_t l = fused_lds_bytes(g, fuse);
             lds = l > lds ? l : lds;
         } else {
             if (r0 != 0 || (r1 >= 0 && r1 != g.n_rep)) return fail(HSG_E_STATE, "replica ranges need the z-march");
@@ -428,7 +445,7 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
     if (energy && reduce) {
         for (const Group &g : h->lay.g) {
             if (!pick(g)) continue;
-            const int n_pb = pair ? 1 : use_stream(h, g) ? g.s_ytiles * g.s_zslabs : g.n_pb_sweep;
+            const int n_pb = fuse ? 1 : use_stream(h, g) ? g.s_ytiles * g.s_zslabs : g.n_pb_sweep;
             const hipError_t e = hsg::launch_reduce_partials(reinterpret_cast<double *>(h->scratch + g.o_scr), n_pb,
                                                              g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
             if (e != hipSuccess) return hip_fail(e, "energy reduction launch");
@@ -439,33 +456,89 @@ hsg_status run_groups(hsg_lattice *h, int kind, int parity, int rep, bool energy
 
 hsg_status run_half_sweep(hsg_lattice *h, int kind, int parity, int rep, bool energy, hipStream_t s)
 {
-    return run_groups(h, kind, parity, rep, energy, false, [](const Group &) { return true; }, s);
+    return run_groups(h, kind, parity, rep, energy, 0, [](const Group &) { return true; }, s);
 }
 
-// A pair of half-sweeps (parity 0, then parity 1) of every group: fused where
-// the group holds whole planes, as two single passes otherwise. `energy`: the
-// parity-1 pass computes the energies.
-hsg_status run_pair(hsg_lattice *h, int kind, int rep, bool energy, hipStream_t s, const Group *only = nullptr,
-                    int64_t r0 = 0, int64_t r1 = -1, bool reduce = true)
+// A pair of half-sweeps (parity 0, then parity 1) of the groups `pick`
+// selects: fused where the group holds whole planes, as two single passes
+// otherwise. `energy`: the parity-1 pass computes the energies.
+template <class Pick>
+hsg_status run_pair_of(hsg_lattice *h, int kind, int rep, bool energy, hipStream_t s, Pick pick, int64_t r0,
+                       int64_t r1, bool reduce)
 {
     bool any_pair = false, any_single = false;
     for (const Group &g : h->lay.g) {
-        if (only != nullptr && &g != only) continue;
+        if (!pick(g)) continue;
         any_pair = any_pair || use_pair(h, g);
         any_single = any_single || !use_pair(h, g);
     }
     if (any_pair) {
-        auto fused = [h, only](const Group &g) { return (only == nullptr || &g == only) && use_pair(h, g); };
-        hsg_status st = run_groups(h, kind, 0, rep, energy, true, fused, s, r0, r1, reduce);
+        auto fused = [h, &pick](const Group &g) { return pick(g) && use_pair(h, g); };
+        hsg_status st = run_groups(h, kind, 0, rep, energy, 1, fused, s, r0, r1, reduce);
         if (st != HSG_OK) return st;
     }
     if (any_single) {
-        auto single = [h, only](const Group &g) { return (only == nullptr || &g == only) && !use_pair(h, g); };
-        hsg_status st = run_groups(h, kind, 0, rep, false, false, single, s, r0, r1, reduce);
-        if (st == HSG_OK) st = run_groups(h, kind, 1, rep, energy, false, single, s, r0, r1, reduce);
+        auto single = [h, &pick](const Group &g) { return pick(g) && !use_pair(h, g); };
+        hsg_status st = run_groups(h, kind, 0, rep, false, 0, single, s, r0, r1, reduce);
+        if (st == HSG_OK) st = run_groups(h, kind, 1, rep, energy, 0, single, s, r0, r1, reduce);
         if (st != HSG_OK) return st;
     }
     return HSG_OK;
+}
+
+// One pair for every group (only == nullptr) or for group *only.
+hsg_status run_pair(hsg_lattice *h, int kind, int rep, bool energy, hipStream_t s, const Group *only = nullptr,
+                    int64_t r0 = 0, int64_t r1 = -1, bool reduce = true)
+{
+    auto pick = [only](const Group &g) { return only == nullptr || &g == only; };
+    return run_pair_of(h, kind, rep, energy, s, pick, r0, r1, reduce);
+}
+
+// Two over-relaxation pairs: one z-march where use_quad allows it, two pairs
+// elsewhere. `energy`: the last pass computes the energies.
+hsg_status run_or_quad(hsg_lattice *h, bool energy, hipStream_t s, const Group *only = nullptr, int64_t r0 = 0,
+                       int64_t r1 = -1, bool reduce = true)
+{
+    bool any_quad = false, any_other = false;
+    for (const Group &g : h->lay.g) {
+        if (only != nullptr && &g != only) continue;
+        any_quad = any_quad || use_quad(h, g);
+        any_other = any_other || !use_quad(h, g);
+    }
+    if (any_quad) {
+        auto quad = [h, only](const Group &g) { return (only == nullptr || &g == only) && use_quad(h, g); };
+        hsg_status st = run_groups(h, 1, 0, 0, energy, 2, quad, s, r0, r1, reduce);
+        if (st != HSG_OK) return st;
+    }
+    if (any_other) {
+        auto other = [h, only](const Group &g) { return (only == nullptr || &g == only) && !use_quad(h, g); };
+        hsg_status st = run_pair_of(h, 1, 0, false, s, other, r0, r1, reduce);
+        if (st == HSG_OK) st = run_pair_of(h, 1, 0, energy, s, other, r0, r1, reduce);
+        if (st != HSG_OK) return st;
+    }
+    return HSG_OK;
+}
+
+// n_or over-relaxation pairs, two by two where possible; the last pass
+// computes the energies when `energy` is set.
+hsg_status run_or_rounds(hsg_lattice *h, int n_or, bool energy, hipStream_t s, const Group *only = nullptr,
+                         int64_t r0 = 0, int64_t r1 = -1, bool reduce = true)
+{
+    bool any_quad = false;
+    for (const Group &g : h->lay.g)
+        if (only == nullptr || &g == only) any_quad = any_quad || use_quad(h, g);
+    int r = 0;
+    hsg_status st = HSG_OK;
+    while (r < n_or && st == HSG_OK) {
+        if (any_quad && r + 1 < n_or) {
+            st = run_or_quad(h, energy && r + 2 == n_or, s, only, r0, r1, reduce);
+            r += 2;
+        } else {
+            st = run_pair(h, 1, 0, energy && r + 1 == n_or, s, only, r0, r1, reduce);
+            r += 1;
+        }
+    }
+    return st;
 }
 
 // Replicas per batch of the sweep for group g (0: no batching). A batch's pairs
@@ -643,10 +716,8 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
             hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s);
             if (st != HSG_OK) return st;
         }
-        for (int r = 0; r < h->n_or; ++r) {
-            hsg_status st = run_pair(h, 1, 0, r == h->n_or - 1, s);
-            if (st != HSG_OK) return st;
-        }
+        hsg_status st = run_or_rounds(h, h->n_or, true, s);
+        if (st != HSG_OK) return st;
     } else {
         // Replicas never interact within the pairs of a sweep: all pairs of one
         // batch of replicas run back to back (the batch stays in the last-level
@@ -661,10 +732,8 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
                     hsg_status st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s, &g, r0, r1, b == 0);
                     if (st != HSG_OK) return st;
                 }
-                for (int r = 0; r < h->n_or; ++r) {
-                    hsg_status st = run_pair(h, 1, 0, r == h->n_or - 1, s, &g, r0, r1, b == 0);
-                    if (st != HSG_OK) return st;
-                }
+                hsg_status st = run_or_rounds(h, h->n_or, true, s, &g, r0, r1, b == 0);
+                if (st != HSG_OK) return st;
             }
             if (b > 0) {  // one reduction over every batch's partial sums
                 const int n_pb = use_pair(h, g) ? 1 : g.s_ytiles * g.s_zslabs;
@@ -775,6 +844,12 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
     h->coup = static_cast<char *>(d_couplings);
     h->field = static_cast<char *>(d_field);
     h->scratch = static_cast<char *>(d_scratch);
+    {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            h->max_lds = (size_t)v;
+    }
     hipStream_t s = S(stream);
     {
         const hipError_t e = hipMemsetAsync(h->state, 0, kAlign, s);
@@ -890,6 +965,13 @@ hsg_status hsg_pair_sweep(hsg_lattice *h, int32_t kind, int32_t rep, hsg_stream_
     if (kind != 0 && kind != 1) return fail(HSG_E_INVALID, "kind = %d, need 0 (HB) or 1 (OR)", kind);
     if (rep < 0 || rep > 15) return fail(HSG_E_SIZE, "rep = %d, need 0..15", rep);
     return run_pair(h, kind, rep, false, S(stream));
+}
+
+hsg_status hsg_or_pairs(hsg_lattice *h, int32_t n_pairs, hsg_stream_t stream)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (n_pairs < 1 || n_pairs > 1000) return fail(HSG_E_INVALID, "n_pairs = %d, need 1..1000", n_pairs);
+    return run_or_rounds(h, n_pairs, false, S(stream));
 }
 
 hsg_status hsg_pt_exchange(hsg_lattice *h, hsg_stream_t stream)
@@ -1119,7 +1201,7 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item)
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
-    if (variant < 0 || variant > 3) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..3", variant);
+    if (variant < 0 || variant > 4) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..4", variant);
     h->kernel_variant = variant;
     drop_graphs(h);
     return HSG_OK;
@@ -1165,7 +1247,15 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
         else
             cands.push_back({v, 0});
     };
-    if (any_pair) add(3, any_gather);
+    if (any_pair) {
+        const int32_t v0 = h->kernel_variant;
+        h->kernel_variant = 4;
+        bool any_quad = false;
+        for (const Group &g : h->lay.g) any_quad = any_quad || use_quad(h, g);
+        h->kernel_variant = v0;
+        if (any_quad && h->n_or >= 2) add(4, any_gather);
+        add(3, any_gather);
+    }
     if (any_stream) add(2, any_gather);
     add(1, true);
     if (h->t + need * cands.size() > 0x100000000ull)

@@ -112,25 +112,30 @@ __device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
 
 // ---------------------------------------------------------------- Eq. (2)
 // New spin drawn from exp(beta h.s): c = cos(angle to h) by inverting the CDF
-// of exp(kappa c) on [-1, 1], kappa = beta |h|, with algebraically equal forms
-// of c = 1 + ln(x) / kappa, x = u + (1 - u) e^{-2 kappa}, chosen for float32
-// accuracy: for small kappa log1p(-(1 - u)(1 - e^{-2 kappa})) with expm1 (no
-// loss near c = 2u - 1); for larger kappa the same log1p while x >= 1/2 (new
-// spins close to the field, where 1 - c must keep its relative precision) and
-// ln of the sum x of two positive terms below 1/2 (no cancellation; e^{-2 kappa}
-// only underflows); 1 + c from its own log1p form when c < 0. Azimuth 2 pi u2 about h in the
-// frame of Frisvad (JGT 2012), which is continuous except at n = -z (a frame
-// with a jump along a whole great circle would turn float32 rounding of h into
-// O(1) jumps of the new spin); 1 + n_z is formed without cancellation for
+// of exp(kappa c) on [-1, 1], kappa = beta |h|: c = 1 + ln(x) / kappa with
+// x = u + (1 - u) e^{-2 kappa}. In float32 both ends of [-1, 1] need care, and
+// the form must not branch per site (a wave runs every branch any of its sites
+// takes). One exponential E = e^{-2 kappa} and one logarithm per site:
+//   A = e^{-2 kappa} - 1 from its Taylor series for 2 kappa < 0.35, else E - 1;
+//   c >= 0 (x >= e^{-kappa}): kappa (1 - c) = -ln(1 + Y), Y = (1 - u) A, with
+//     X = u + (1 - u) E (a sum of two positive terms) standing for 1 + Y;
+//   c < 0: kappa (1 + c) = ln(1 + Y), Y = u B, B = e^{2 kappa} - 1 = -A / E,
+//     X = 1 + Y;
+//   ln(1 + Y) = ln X + ((1 - X) + Y) / X where 1 - X is exact (X in [1/2, 2]):
+//     the first-order correction for the rounding of X.
+// So 1 - c keeps its relative precision near c = 1 and 1 + c near c = -1, and
+// so does the transverse length sqrt((1 - c)(1 + c)). Azimuth 2 pi u2 about h
+// in the frame of Frisvad (JGT 2012), which is continuous except at n = -z (a
+// frame with a jump along a whole great circle would turn float32 rounding of h
+// into O(1) jumps of the new spin); 1 + n_z is formed without cancellation for
 // n_z < 0. Zero field: uniform, z frame.
 //
-// HW = false uses the correctly rounded square root and division and the
-// library sincospi. HW = true (an opt-in variant) takes the field's length and
+// HW = false uses the correctly rounded square root and division (except in
+// the rounding correction of ln X above) and the library sincospi. HW = true (an opt-in variant) takes the field's length and
 // direction from the hardware reciprocal square root, the divisions from the
 // hardware reciprocal (1 ulp) and the azimuth from the hardware sin/cos of
 // revolutions (absolute error about 1.2e-7, one float32 spacing at 1). Both
-// keep the library log, exp, log1p and expm1: 1 - c must keep its relative
-// precision when the new spin is nearly parallel to the field.
+// keep the library exp and log.
 template <bool HW>
 __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t w1)
 {
@@ -146,47 +151,56 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         rs = 1.0f / hn;
     }
     const float kappa = beta * hn;
-    // omc = 1 - c and opc = 1 + c are each formed directly (omc = -ln(x) / kappa;
-    // opc = ln(u e^{2 kappa} + 1 - u) / kappa when c < 0), so neither loses its
-    // relative precision at its end of [-1, 1], nor does the transverse length
-    // sqrt(omc opc).
     v3 n;
-    float omc, opc;
+    float omc, opc;  // 1 - c and 1 + c
+    bool upper;      // c >= 0: c is taken from 1 - c, else from 1 + c
     if (hh == 0.0f || !(kappa > 0.0f)) {
         n = v3{0.0f, 0.0f, 1.0f};
         omc = 2.0f * (1.0f - u1);  // c = 2 u1 - 1, exact
         opc = 2.0f * u1;
+        upper = u1 >= 0.5f;
     } else {
         n = scale3(h, rs);
         const float omu = 1.0f - u1;  // exact on the 2^-24 grid
-        float lg;
-        if (kappa < 0.5f) {
-            lg = log1pf(omu * expm1f(-2.0f * kappa));
-        } else {
-            const float e2k = expf(-2.0f * kappa);
-            const float x = fmaf(omu, e2k, u1);  // u + (1 - u) e^{-2 kappa}, both terms positive
-            lg = x >= 0.5f ? log1pf(-omu * (1.0f - e2k)) : logf(x);
-        }
-        omc = fminf(2.0f, fmaxf(0.0f, HW ? -lg * hw_rcp(kappa) : -lg / kappa));
-        if (omc > 1.0f) {  // c < 0: only for kappa < 17 (u >= 2^-24), so e^{2 kappa} is finite
-            const float l2 = log1pf(u1 * expm1f(2.0f * kappa));
-            opc = fminf(2.0f, fmaxf(0.0f, HW ? l2 * hw_rcp(kappa) : l2 / kappa));
-        } else {
-            opc = 2.0f - omc;
-        }
+        const float z = -2.0f * kappa;
+        const float E = expf(z);  // 0 past underflow
+        float p = 2.7557319e-6f;  // 1/9!, then Horner down to 1/2!
+        p = fmaf(z, p, 2.4801588e-5f);
+        p = fmaf(z, p, 1.9841270e-4f);
+        p = fmaf(z, p, 1.3888889e-3f);
+        p = fmaf(z, p, 8.3333333e-3f);
+        p = fmaf(z, p, 4.1666667e-2f);
+        p = fmaf(z, p, 1.6666667e-1f);
+        p = fmaf(z, p, 0.5f);
+        const float A = z > -0.35f ? z * fmaf(z, p, 1.0f) : E - 1.0f;  // e^{-2 kappa} - 1
+        const float xo = fmaf(omu, E, u1);                               // x
+        upper = xo * xo >= E;  // x >= e^{-kappa}, i.e. c >= 0
+        // c < 0 needs kappa < 17 (u >= 2^-24), where E is a normal number
+        const float yb = u1 * (HW ? -A * hw_rcp(E) : -A / E);
+        const float X = upper ? xo : 1.0f + yb;
+        const float Y = upper ? omu * A : yb;
+        const float d = (1.0f - X) + Y;
+        // (a relative correction of order 1e-7: the hardware reciprocal's 1 ulp is far below float32 spacing)
+        const float corr = (X >= 0.5f && X <= 2.0f) ? d * hw_rcp(X) : 0.0f;
+        const float t = HW ? (logf(X) + corr) * hw_rcp(kappa) : (logf(X) + corr) / kappa;
+        omc = fminf(2.0f, fmaxf(0.0f, upper ? -t : 2.0f - t));
+        opc = fminf(2.0f, fmaxf(0.0f, upper ? 2.0f + t : t));
     }
-    const float c = omc <= 1.0f ? 1.0f - omc : opc - 1.0f;
+    const float c = upper ? 1.0f - omc : opc - 1.0f;
     v3 e1, e2;
     const float rxy = fmaf(n.x, n.x, n.y * n.y);
     if (n.z < 0.0f && rxy == 0.0f) {
         e1 = v3{-1.0f, 0.0f, 0.0f};
         e2 = v3{0.0f, 1.0f, 0.0f};
     } else {
-        float a;  // 1 / (1 + n_z)
+        // a = 1 / (1 + n_z), as (1 - n_z) / (n_x^2 + n_y^2) for n_z < 0: one division
+        const bool up = n.z >= 0.0f;
+        const float num = up ? 1.0f : 1.0f - n.z, den = up ? 1.0f + n.z : rxy;
+        float a;
         if constexpr (HW)
-            a = (n.z >= 0.0f) ? hw_rcp(1.0f + n.z) : (1.0f - n.z) * hw_rcp(rxy);
+            a = num * hw_rcp(den);
         else
-            a = (n.z >= 0.0f) ? 1.0f / (1.0f + n.z) : (1.0f - n.z) / rxy;
+            a = num / den;
         const float b = -n.x * n.y * a;
         e1 = v3{fmaf(-n.x * n.x, a, 1.0f), b, -n.x};
         e2 = v3{b, fmaf(-n.y * n.y, a, 1.0f), -n.y};

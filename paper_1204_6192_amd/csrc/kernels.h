@@ -89,9 +89,10 @@ struct MultiStreamArgs {
     int32_t block_start[kMaxStreamGroups + 1];
     StreamArgs g[kMaxStreamGroups];
 };
-// pair = false: one half-sweep of parity a.parity; pair = true: both parities
-// of a pair (every group must hold whole planes, TY = L).
-hipError_t launch_half_sweep_stream(const MultiStreamArgs &m, int storage, int kind, bool energy, bool pair,
+// fuse = 0: one half-sweep of parity a.parity; 1: both parities of a pair;
+// 2: two over-relaxation pairs (kind 1). Fused launches need whole planes
+// (TY = L) in every group.
+hipError_t launch_half_sweep_stream(const MultiStreamArgs &m, int storage, int kind, bool energy, int fuse,
                                     unsigned threads, size_t lds_bytes, hipStream_t s);
 
 // *flag = 1 if any of the n values is not exactly +1 or -1, else 0.

@@ -17,6 +17,8 @@
 // generic kernel (same neighbour order, same functions), so both produce the
 // same bits.
 #pragma once
+#include <type_traits>
+
 #include "device.h"
 #include "kernels.h"
 
@@ -478,6 +480,241 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
     }
 }
 
+// Two over-relaxation pairs (four half-sweeps: parity 0, 1, 0, 1) in one z-march
+// over whole planes (TY = L). Stage s = 0 .. 3 updates parity s & 1; at step z
+// it works on plane w = z - s (mod L), for the steps 2s .. 2s + L - 1, so it
+// visits the planes s, s + 1, ..., L - 1, 0, ..., s - 1. Its inputs come from
+// stage s - 1 (stage 0: the old parity-1 planes): plane w + 1 made earlier in
+// the same step, plane w made one step before (staged in LDS for the in-plane
+// neighbours) and plane w - 1 made two steps before; over-relaxation also needs
+// the site's own value from stage s - 2 (stages 0 and 1: the old spins). The
+// last two planes of a stage need the first two planes of the stages before
+// it, made at the start of the march: the first is kept in LDS, the second at
+// the thread's own positions in registers. Only stages 2 and 3 store, so every
+// stored spin is read and written once per four half-sweeps; every stage
+// rounds its output through the storage codec as a stored and reloaded
+// half-sweep would, and the result equals four single half-sweeps bit for bit.
+__device__ __forceinline__ v3 pick(bool c, v3 a, v3 b)
+{
+    return v3{c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+
+template <int STORE, bool FIELD, bool ENERGY, bool UNI, bool JB>
+__device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, float *lds, double *red)
+{
+    constexpr int D = 4;  // half-sweeps per march
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    const int tid = threadIdx.x;
+    const int per_rep = a.TY * a.P;
+    const int rb = tid / per_rep;
+    const int rem = tid - rb * per_rep;
+    const int ty = rem / a.P, m = rem - ty * a.P;
+    const int64_t r_first = a.r_base + (int64_t)lb * a.RB;  // the group's first replica (always present)
+    const int64_t r_lane = r_first + rb;
+    const bool active = rb < a.RB && r_lane < a.n_rep;
+    const int L = a.L, Lh = a.Lh;
+    const uint32_t Nh = (uint32_t)a.Nh;
+    const int y = ty;
+    const int lrm = ty == 0 ? L - 1 : ty - 1;
+    const int lrp = ty == L - 1 ? 0 : ty + 1;
+    const int cstride = L * Lh;
+    const int xh0 = 2 * m;
+    const int rbc = active ? rb : 0;
+    const int pl = 3 * cstride;  // floats per staged plane
+    // per replica: IN[2] (old parity 1), RING[s][2] and SAVED[s] for s < D - 1
+    const int base_l = rbc * (3 * D - 1) * pl;
+    const int lrow_w = ty * Lh + xh0;
+    auto l_in = [&](int k) { return base_l + k * pl; };
+    auto l_ring = [&](int s, int k) { return base_l + (2 + 2 * s + k) * pl; };
+    auto l_saved = [&](int s) { return base_l + (2 * D + s) * pl; };
+
+    // Idle lanes read the group's first replica (valid memory) and discard it:
+    // every global load is issued on every path, so the hardware's in-order
+    // count of outstanding memory operations lets each wait below name exactly
+    // the loads it needs.
+    int64_t r = active ? r_lane : r_first;
+    if (UNI) r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r & 0xFFFFFFFF));
+    const int64_t d = r / a.slots_per_sample;
+    T *sp0 = (T *)a.spins + r * 2 * C::kPlanes * (int64_t)Nh;
+    T *sp1 = sp0 + (int64_t)C::kPlanes * Nh;
+    const bool jbits = JB && a.Jbits != nullptr;
+    const bool field = FIELD && a.Hp != nullptr;
+    const float *J0 = a.J6 + (d * 2 + 0) * 6 * (int64_t)Nh;
+    const float *J1 = a.J6 + (d * 2 + 1) * 6 * (int64_t)Nh;
+    const uint8_t *Jb0 = jbits ? a.Jbits + (d * 2 + 0) * (int64_t)Nh : nullptr;
+    const uint8_t *Jb1 = jbits ? a.Jbits + (d * 2 + 1) * (int64_t)Nh : nullptr;
+    const float *H0 = field ? a.Hp + (d * 2 + 0) * 3 * (int64_t)Nh : nullptr;
+    const float *H1 = field ? a.Hp + (d * 2 + 1) * 3 * (int64_t)Nh : nullptr;
+
+    // The loaded spins are addressed by the step modulo 4 (the march is
+    // unrolled by four, so the indices are constants and a load lands where it
+    // is used): old parity-1 spins at my positions, slot (z' mod 4) for planes
+    // z' = z - 1 .. z + 2 of the march; old parity-0 spins, slot (z' mod 2) for
+    // z' = z, z + 1. Stage outputs at my positions roll forward: slot 0 this
+    // step, 1 and 2 one and two steps before. Then the second plane of each
+    // stage but the last.
+    v3 ia[4], ib[4], oa[2], ob[2];
+    v3 qa[D - 1][3], qb[D - 1][3];
+    v3 fa[D - 1], fb[D - 1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) ia[k] = ib[k] = v3{0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) qa[s][k] = qb[s][k] = v3{0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < D - 1; ++s) fa[s] = fb[s] = v3{0.f, 0.f, 0.f};
+    oa[1] = ob[1] = v3{0.f, 0.f, 0.f};
+    C::load_pair(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), ia[3], ib[3]);
+    C::load_pair(sp1, Nh, (uint32_t)(y * Lh + xh0), ia[0], ib[0]);
+    C::load_pair(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), ia[1], ib[1]);
+    C::load_pair(sp0, Nh, (uint32_t)(y * Lh + xh0), oa[0], ob[0]);
+    double e = 0.0;
+    const int n_steps = L + 2 * (D - 1);
+    auto wrap = [L](int v) {
+        while (v >= L) v -= L;
+        return v;
+    };
+
+    auto step = [&](auto kc, const int z) __attribute__((always_inline)) {
+        constexpr int K = decltype(kc)::value;  // z mod 4
+        float2 jc[D][6];
+        v3 hs0[D], hs1[D];
+        if (active && z < L) lds_put_pair(lds, l_in(K & 1) + lrow_w, cstride, ia[K], ib[K]);
+#pragma unroll
+        for (int s = 0; s < D; ++s) {  // every stage's couplings, also for the steps it idles
+            const uint32_t jw = (uint32_t)((wrap(z + L - s) * L + y) * Lh + xh0);
+            if (s & 1) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+            else load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+        }
+        // The spin loads for the next step go out last, so that the waits for
+        // this step's couplings leave them in flight. Past the end of the march
+        // their values are never used: they repeat the last loads (cache hits).
+        __builtin_amdgcn_sched_barrier(0);
+        const int zi = z + 1 < L ? wrap(z + 2) : 0, zo = z + 1 < L ? z + 1 : L - 1;
+        C::load_pair(sp1, Nh, (uint32_t)((zi * L + y) * Lh + xh0), ia[(K + 2) & 3], ib[(K + 2) & 3]);
+        C::load_pair(sp0, Nh, (uint32_t)((zo * L + y) * Lh + xh0), oa[(K + 1) & 1], ob[(K + 1) & 1]);
+        __syncthreads();
+        // one stage; written as a function of a constant so that every register
+        // index is known before the compiler places the arrays
+        auto stage = [&](auto sc) __attribute__((always_inline)) {
+            constexpr int s = decltype(sc)::value;
+            const int i = z - 2 * s;
+            if (i < 0 || i >= L) return;
+            const int w = wrap(z + L - s);
+            const uint32_t jw = (uint32_t)((w * L + y) * Lh + xh0);
+            const int o = (y + w + (s & 1)) & 1;
+            int lo;
+            v3 c0, c1, zp0, zp1, zm0, zm1, od0, od1;
+            if constexpr (s == 0) {
+                lo = l_in(K & 1);
+                c0 = ia[K]; c1 = ib[K];
+                zp0 = ia[(K + 1) & 3]; zp1 = ib[(K + 1) & 3];
+                zm0 = ia[(K + 3) & 3]; zm1 = ib[(K + 3) & 3];
+                od0 = oa[K & 1]; od1 = ob[K & 1];
+            } else {
+                // The first plane of stage s - 1 (and of s - 2) at my positions is
+                // read from LDS every time and picked by value: a branch between a
+                // register and an LDS read would make the compiler address the
+                // registers through memory.
+                v3 g0, g1, h0, h1;
+                lds_get_pair(lds, l_saved(s - 1) + lrow_w, cstride, g0, g1);
+                if constexpr (s >= 2) lds_get_pair(lds, l_saved(s - 2) + lrow_w, cstride, h0, h1);
+                else h0 = h1 = v3{0.f, 0.f, 0.f};
+                const bool c_ring = i <= L - 2;  // plane w of stage s - 1, made one step before, else its first
+                lo = c_ring ? l_ring(s - 1, (K + 1) & 1) : l_saved(s - 1);
+                c0 = pick(c_ring, qa[s - 1][1], g0);
+                c1 = pick(c_ring, qb[s - 1][1], g1);
+                // plane w + 1 of stage s - 1: made earlier in this step, else its first or second plane
+                zp0 = pick(i <= L - 3, qa[s - 1][0], pick(i == L - 2, g0, fa[s - 1]));
+                zp1 = pick(i <= L - 3, qb[s - 1][0], pick(i == L - 2, g1, fb[s - 1]));
+                zm0 = qa[s - 1][2]; zm1 = qb[s - 1][2];
+                if constexpr (s == 1) {  // the old parity-1 spin of plane w = z - 1
+                    od0 = ia[(K + 3) & 3]; od1 = ib[(K + 3) & 3];
+                } else {
+                    od0 = pick(i <= L - 3, qa[s - 2][2], pick(i == L - 2, h0, fa[s - 2]));
+                    od1 = pick(i <= L - 3, qb[s - 2][2], pick(i == L - 2, h1, fb[s - 2]));
+                }
+            }
+            v3 r0, r1;
+            if constexpr (s == D - 1) {
+                e += update_pair<STORE, 1, ENERGY>(lds, lo, cstride, Lh, ty, lrm, lrp, xh0, o, c0, c1, zp0, zp1, zm0,
+                                                   zm1, jc[s], hs0[s], hs1[s], od0, od1, u32x4{0u, 0u, 0u, 0u}, 0.0f,
+                                                   r0, r1);
+                if (ENERGY && field) {  // field on the parity-0 sites at the same half-indices: stage D - 2
+                    const float2 fx = *reinterpret_cast<const float2 *>(H0 + jw);
+                    const float2 fy = *reinterpret_cast<const float2 *>(H0 + Nh + jw);
+                    const float2 fz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + jw);
+                    e -= (double)fx.x * c0.x + (double)fy.x * c0.y + (double)fz.x * c0.z;
+                    e -= (double)fx.y * c1.x + (double)fy.y * c1.y + (double)fz.y * c1.z;
+                }
+            } else {
+                (void)update_pair<STORE, 1, false>(lds, lo, cstride, Lh, ty, lrm, lrp, xh0, o, c0, c1, zp0, zp1, zm0,
+                                                   zm1, jc[s], hs0[s], hs1[s], od0, od1, u32x4{0u, 0u, 0u, 0u}, 0.0f,
+                                                   r0, r1);
+            }
+            if (s >= D - 2) C::store_pair((s & 1) ? sp1 : sp0, Nh, jw, r0, r1);
+            if constexpr (s < D - 1) {
+                r0 = C::stored_value(r0);
+                r1 = C::stored_value(r1);
+                lds_put_pair(lds, l_ring(s, K & 1) + lrow_w, cstride, r0, r1);
+                if (i == 0) lds_put_pair(lds, l_saved(s) + lrow_w, cstride, r0, r1);
+                if (i == 1) { fa[s] = r0; fb[s] = r1; }
+                qa[s][0] = r0; qb[s][0] = r1;
+            }
+        };
+        if (active) {
+            stage(std::integral_constant<int, 0>{});
+            stage(std::integral_constant<int, 1>{});
+            stage(std::integral_constant<int, 2>{});
+            stage(std::integral_constant<int, 3>{});
+        }
+        static_assert(D == 4, "the stages are listed by hand");
+#pragma unroll
+        for (int s = 0; s < D - 1; ++s) {
+            qa[s][2] = qa[s][1]; qb[s][2] = qb[s][1];
+            qa[s][1] = qa[s][0]; qb[s][1] = qb[s][0];
+        }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    // steps past n_steps idle (every stage done), so the count rounds up to 4
+    for (int z = 0; z < n_steps; z += 4) {
+        step(I0{}, z);
+        step(I1{}, z + 1);
+        step(I2{}, z + 2);
+        step(I3{}, z + 3);
+    }
+
+    if (ENERGY) {
+        red[tid] = e;
+        __syncthreads();
+        if (tid < a.RB) {
+            const int64_t r2 = a.r_base + (int64_t)lb * a.RB + tid;
+            if (r2 < a.n_rep) {
+                double sum = 0.0;
+                for (int k = 0; k < per_rep; ++k) sum += red[tid * per_rep + k];
+                a.e_partials[r2 * a.n_ytiles] = sum;
+            }
+        }
+    }
+}
+
+template <int STORE, bool ENERGY, bool FIELD, bool UNI, bool JB>
+__global__ __launch_bounds__(kBlock) void k_or_quad_stream(MultiStreamArgs m)
+{
+    extern __shared__ float lds[];  // [RB][IN0 IN1 R00 R01 R10 R11 R20 R21 S0 S1 S2][3][L][L/2] floats
+    __shared__ double red[kBlock];
+    const int b = xcd_remap((int)blockIdx.x, m.n_blocks);
+    int k = 0;
+    while (k + 1 < m.n_groups && b >= m.block_start[k + 1]) ++k;
+    quad_body<STORE, FIELD, ENERGY, UNI, JB>(m.g[k], b - m.block_start[k], lds, red);
+}
+
 template <int STORE, int KIND, bool ENERGY, bool FIELD, bool UNI, bool JB>
 __global__ __launch_bounds__(kBlock) void k_pair_stream(MultiStreamArgs m)
 {
@@ -501,13 +738,21 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep_stream(MultiStreamArgs m)
     stream_body<STORE, KIND, FIELD, ENERGY, UNI, JB>(m.g[k], b - m.block_start[k], lds, red);
 }
 
+// fuse: 0 one half-sweep, 1 a pair, 2 two over-relaxation pairs.
 template <int STORE, int KIND, bool ENERGY>
-static hipError_t launch_stream_e(const MultiStreamArgs &m, bool pair, bool field, bool uni, bool jb, dim3 grid,
+static hipError_t launch_stream_e(const MultiStreamArgs &m, int fuse, bool field, bool uni, bool jb, dim3 grid,
                                   dim3 block, size_t lds_bytes, hipStream_t s)
 {
+    if (fuse == 2 && KIND != 1) return hipErrorInvalidValue;
 #define HSG_L(F, U, J)                                                                                        \
     do {                                                                                                      \
-        if (pair) hipLaunchKernelGGL((k_pair_stream<STORE, KIND, ENERGY, F, U, J>), grid, block, lds_bytes, s, m); \
+        if constexpr (KIND == 1) {                                                                            \
+            if (fuse == 2) {                                                                                  \
+                hipLaunchKernelGGL((k_or_quad_stream<STORE, ENERGY, F, U, J>), grid, block, lds_bytes, s, m); \
+                break;                                                                                        \
+            }                                                                                                 \
+        }                                                                                                     \
+        if (fuse == 1) hipLaunchKernelGGL((k_pair_stream<STORE, KIND, ENERGY, F, U, J>), grid, block, lds_bytes, s, m); \
         else hipLaunchKernelGGL((k_half_sweep_stream<STORE, KIND, ENERGY, F, U, J>), grid, block, lds_bytes, s, m); \
     } while (0)
     if (field) {
@@ -522,7 +767,7 @@ static hipError_t launch_stream_e(const MultiStreamArgs &m, bool pair, bool fiel
 }
 
 template <int STORE>
-hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, bool pair, unsigned threads,
+hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, int fuse, unsigned threads,
                            size_t lds_bytes, hipStream_t s)
 {
     bool field = false, uni = true, jb = false;
@@ -533,15 +778,15 @@ hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, bool
     }
     const dim3 grid((unsigned)m.n_blocks), block(threads);
     if (kind == 0) {
-        if (energy) return launch_stream_e<STORE, 0, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
-        return launch_stream_e<STORE, 0, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+        if (energy) return launch_stream_e<STORE, 0, true>(m, fuse, field, uni, jb, grid, block, lds_bytes, s);
+        return launch_stream_e<STORE, 0, false>(m, fuse, field, uni, jb, grid, block, lds_bytes, s);
     }
     if (kind == 2) {
-        if (energy) return launch_stream_e<STORE, 2, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
-        return launch_stream_e<STORE, 2, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+        if (energy) return launch_stream_e<STORE, 2, true>(m, fuse, field, uni, jb, grid, block, lds_bytes, s);
+        return launch_stream_e<STORE, 2, false>(m, fuse, field, uni, jb, grid, block, lds_bytes, s);
     }
-    if (energy) return launch_stream_e<STORE, 1, true>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
-    return launch_stream_e<STORE, 1, false>(m, pair, field, uni, jb, grid, block, lds_bytes, s);
+    if (energy) return launch_stream_e<STORE, 1, true>(m, fuse, field, uni, jb, grid, block, lds_bytes, s);
+    return launch_stream_e<STORE, 1, false>(m, fuse, field, uni, jb, grid, block, lds_bytes, s);
 }
 
 }  // namespace hsg

@@ -3,5 +3,5 @@
 #include "sweep_stream.h"
 
 namespace hsg {
-template hipError_t launch_stream_s<0>(const MultiStreamArgs &, int, bool, bool, unsigned, size_t, hipStream_t);
+template hipError_t launch_stream_s<0>(const MultiStreamArgs &, int, bool, int, unsigned, size_t, hipStream_t);
 }  // namespace hsg

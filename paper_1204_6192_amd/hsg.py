@@ -77,6 +77,7 @@ _SIG = {
     "hsg_sweep": [_vp, _i32, _vp],
     "hsg_half_sweep": [_vp, _i32, _i32, _i32, _vp],
     "hsg_pair_sweep": [_vp, _i32, _i32, _vp],
+    "hsg_or_pairs": [_vp, _i32, _vp],
     "hsg_pt_exchange": [_vp, _vp],
     "hsg_measure_energy": [_vp, _vp, _vp],
     "hsg_get_energies": [_vp, _vp, _vp],
@@ -214,6 +215,10 @@ class Lattice:
 
     def pair_sweep(self, kind: int, rep: int = 0) -> None:
         check(lib.hsg_pair_sweep(self.h, int(kind), int(rep), _stream(self.stream)))
+
+    def or_pairs(self, n_pairs: int) -> None:
+        """n_pairs over-relaxation pairs as inside a sweep (two by two where fused)."""
+        check(lib.hsg_or_pairs(self.h, int(n_pairs), _stream(self.stream)))
 
     def pt_exchange(self) -> None:
         check(lib.hsg_pt_exchange(self.h, _stream(self.stream)))

@@ -758,9 +758,10 @@ def test_gpu_long_run_statistics_vs_oracle(hsg, oracle_lib):
 
 @pytest.mark.parametrize("storage,math", [("f32", 0), ("f16", 0), ("qangle", 0), ("f32", 1)])
 def test_kernel_variants_bit_identical(hsg, storage, math):
-    """The gather kernel, the z-march kernel (L divisible by 4) and the z-march with
-    both half-sweeps of a pair fused (whole planes, L <= 32) compute the same
-    per-site arithmetic: spins and temperature maps agree bit for bit. L = 36
+    """The gather kernel, the z-march kernel (L divisible by 4), the z-march with
+    both half-sweeps of a pair fused (whole planes, L <= 32) and the one that also
+    runs the over-relaxation pairs two by two compute the same per-site
+    arithmetic: spins and temperature maps agree bit for bit. L = 36
     cannot fuse and runs as two single passes next to the fused groups. Covers a
     whole plane in LDS with 16, 7 and 4 replicas per work-group (L = 8, 12, 16; at
     L = 16 every wave holds one replica), one replica per group (L = 24, 144
@@ -776,7 +777,7 @@ def test_kernel_variants_bit_identical(hsg, storage, math):
         uid += D
     seed = inputs.PHILOX_KEY_BASE + 60
     res = []
-    for variant in (1, 2, 3):
+    for variant in (1, 2, 3, 4):
         lat = _lat(hsg, groups, seed, storage=storage)
         lat.set_kernel(variant)
         lat.set_math(math)
@@ -788,6 +789,39 @@ def test_kernel_variants_bit_identical(hsg, storage, math):
         assert torch.equal(res[0][1], other[1])
         assert torch.allclose(res[0][2], other[2], rtol=1e-12, atol=1e-9)
         assert torch.equal(res[0][3], other[3])  # same spins, same recomputation
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "qangle"])
+def test_or_pairs_two_by_two_bit_identical(hsg, storage):
+    """Over-relaxation pairs fused two by two (one z-march of four half-sweeps,
+    whole planes in LDS) against the same pairs as single half-sweeps: 1, 2, 3
+    and 5 pairs (the odd one runs as a fused pair), spins bit for bit. Lattice
+    sizes 8, 12, 16, 24 and 32 in one launch cover 16 (partly filled), 7, 4 and
+    1 replicas per work-group, waves that span two replicas (L = 12) or run
+    part-empty (L = 24, 144 threads), and the first and last planes of every
+    stage (the periodic closure in z); a field (L = 12) and +-1 couplings read
+    as sign bits (L = 16)."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 64))
+    groups, uid = [], 0
+    for L, D, T, field, cpl in ((8, 2, 3, None, "gaussian"), (12, 2, 2, ("gaussian", 0.3), "gaussian"),
+                                (16, 2, 2, None, "bimodal"), (24, 1, 2, None, "gaussian"),
+                                (32, 2, 2, None, "gaussian")):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, T),
+                                        couplings=cpl, field=field, sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 64
+    for n in (1, 2, 3, 5):
+        ref = _lat(hsg, groups, seed, storage=storage)
+        ref.set_kernel(2)
+        for _ in range(n):
+            ref.half_sweep(1, 0)
+            ref.half_sweep(1, 1)
+        lat = _lat(hsg, groups, seed, storage=storage)
+        lat.set_kernel(4)
+        lat.or_pairs(n)
+        a, b = ref.get_spins().cpu(), lat.get_spins().cpu()
+        print(f"{storage} pairs={n}: max |diff| {float((a - b).abs().max()):.3g}", flush=True)
+        assert torch.equal(a, b)
 
 
 def test_autotune_keeps_the_chain(hsg):
