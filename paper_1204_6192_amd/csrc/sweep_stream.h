@@ -578,11 +578,14 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
         return v;
     };
 
-    auto step = [&](auto kc, const int z) __attribute__((always_inline)) {
+    // F: a step of the steady state (8 <= z, z + 3 < L), where every stage is
+    // active and takes all its inputs from registers and the LDS ring.
+    auto step = [&](auto kc, auto fc, const int z) __attribute__((always_inline)) {
         constexpr int K = decltype(kc)::value;  // z mod 4
+        constexpr bool F = decltype(fc)::value;
         float2 jc[D][6];
         v3 hs0[D], hs1[D];
-        if (active && z < L) lds_put_pair(lds, l_in(K & 1) + lrow_w, cstride, ia[K], ib[K]);
+        if (active && (F || z < L)) lds_put_pair(lds, l_in(K & 1) + lrow_w, cstride, ia[K], ib[K]);
 #pragma unroll
         for (int s = 0; s < D; ++s) {  // every stage's couplings, also for the steps it idles
             const uint32_t jw = (uint32_t)((wrap(z + L - s) * L + y) * Lh + xh0);
@@ -602,7 +605,8 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
         auto stage = [&](auto sc) __attribute__((always_inline)) {
             constexpr int s = decltype(sc)::value;
             const int i = z - 2 * s;
-            if (i < 0 || i >= L) return;
+            if constexpr (!F)
+                if (i < 0 || i >= L) return;
             const int w = wrap(z + L - s);
             const uint32_t jw = (uint32_t)((w * L + y) * Lh + xh0);
             const int o = (y + w + (s & 1)) & 1;
@@ -614,6 +618,16 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
                 zp0 = ia[(K + 1) & 3]; zp1 = ib[(K + 1) & 3];
                 zm0 = ia[(K + 3) & 3]; zm1 = ib[(K + 3) & 3];
                 od0 = oa[K & 1]; od1 = ob[K & 1];
+            } else if constexpr (F) {
+                lo = l_ring(s - 1, (K + 1) & 1);
+                c0 = qa[s - 1][1]; c1 = qb[s - 1][1];
+                zp0 = qa[s - 1][0]; zp1 = qb[s - 1][0];
+                zm0 = qa[s - 1][2]; zm1 = qb[s - 1][2];
+                if constexpr (s == 1) {
+                    od0 = ia[(K + 3) & 3]; od1 = ib[(K + 3) & 3];
+                } else {
+                    od0 = qa[s - 2][2]; od1 = qb[s - 2][2];
+                }
             } else {
                 // The first plane of stage s - 1 (and of s - 2) at my positions is
                 // read from LDS every time and picked by value: a branch between a
@@ -660,8 +674,10 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
                 r0 = C::stored_value(r0);
                 r1 = C::stored_value(r1);
                 lds_put_pair(lds, l_ring(s, K & 1) + lrow_w, cstride, r0, r1);
-                if (i == 0) lds_put_pair(lds, l_saved(s) + lrow_w, cstride, r0, r1);
-                if (i == 1) { fa[s] = r0; fb[s] = r1; }
+                if constexpr (!F) {
+                    if (i == 0) lds_put_pair(lds, l_saved(s) + lrow_w, cstride, r0, r1);
+                    if (i == 1) { fa[s] = r0; fb[s] = r1; }
+                }
                 qa[s][0] = r0; qb[s][0] = r1;
             }
         };
@@ -682,12 +698,27 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
-    // steps past n_steps idle (every stage done), so the count rounds up to 4
-    for (int z = 0; z < n_steps; z += 4) {
-        step(I0{}, z);
-        step(I1{}, z + 1);
-        step(I2{}, z + 2);
-        step(I3{}, z + 3);
+    using G = std::false_type;
+    using S = std::true_type;
+    // Steps past n_steps idle (every stage done), so the count rounds up to 4.
+    int z = 0;
+    for (; z < 8 && z < n_steps; z += 4) {
+        step(I0{}, G{}, z);
+        step(I1{}, G{}, z + 1);
+        step(I2{}, G{}, z + 2);
+        step(I3{}, G{}, z + 3);
+    }
+    for (; z + 4 <= L; z += 4) {
+        step(I0{}, S{}, z);
+        step(I1{}, S{}, z + 1);
+        step(I2{}, S{}, z + 2);
+        step(I3{}, S{}, z + 3);
+    }
+    for (; z < n_steps; z += 4) {
+        step(I0{}, G{}, z);
+        step(I1{}, G{}, z + 1);
+        step(I2{}, G{}, z + 2);
+        step(I3{}, G{}, z + 3);
     }
 
     if (ENERGY) {
