@@ -262,6 +262,22 @@ struct Codec<0> {  // float32: stored renormalised, read as is
         a = v3{x.x, y.x, z.x};
         b = v3{x.y, y.y, z.y};
     }
+    // The same pair split into the memory access and the decoding, so that a
+    // load can be issued a step before its value is used.
+    struct R {
+        float2 x, y, z;
+    };
+    __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t cs, uint32_t j0, R &r)
+    {
+        r.x = *reinterpret_cast<const float2 *>(p + j0);
+        r.y = *reinterpret_cast<const float2 *>(p + cs + j0);
+        r.z = *reinterpret_cast<const float2 *>(p + 2 * cs + j0);
+    }
+    __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
+    {
+        a = v3{r.x.x, r.y.x, r.z.x};
+        b = v3{r.x.y, r.y.y, r.z.y};
+    }
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
         *reinterpret_cast<float2 *>(p + j0) = make_float2(a.x, b.x);
@@ -296,6 +312,20 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
         const __half2 z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
         a = normalise_rsq(v3{__low2float(x), __low2float(y), __low2float(z)});
         b = normalise_rsq(v3{__high2float(x), __high2float(y), __high2float(z)});
+    }
+    struct R {
+        __half2 x, y, z;
+    };
+    __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t cs, uint32_t j0, R &r)
+    {
+        r.x = *reinterpret_cast<const __half2 *>(p + j0);
+        r.y = *reinterpret_cast<const __half2 *>(p + cs + j0);
+        r.z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
+    }
+    __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
+    {
+        a = normalise_rsq(v3{__low2float(r.x), __low2float(r.y), __low2float(r.z)});
+        b = normalise_rsq(v3{__high2float(r.x), __high2float(r.y), __high2float(r.z)});
     }
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
@@ -340,6 +370,21 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
         a = normalise_rsq(v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)});
         b = normalise_rsq(v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u),
                              __uint_as_float(z & 0xFFFF0000u)});
+    }
+    struct R {
+        uint32_t x, y, z;
+    };
+    __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t cs, uint32_t j0, R &r)
+    {
+        r.x = *reinterpret_cast<const uint32_t *>(p + j0);
+        r.y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
+        r.z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
+    }
+    __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
+    {
+        a = normalise_rsq(v3{__uint_as_float(r.x << 16), __uint_as_float(r.y << 16), __uint_as_float(r.z << 16)});
+        b = normalise_rsq(v3{__uint_as_float(r.x & 0xFFFF0000u), __uint_as_float(r.y & 0xFFFF0000u),
+                             __uint_as_float(r.z & 0xFFFF0000u)});
     }
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
@@ -398,6 +443,18 @@ struct Codec<3> {
         const uint2 w = *reinterpret_cast<const uint2 *>(p + j0);
         a = oct_decode(w.x);
         b = oct_decode(w.y);
+    }
+    struct R {
+        uint2 w;
+    };
+    __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t, uint32_t j0, R &r)
+    {
+        r.w = *reinterpret_cast<const uint2 *>(p + j0);
+    }
+    __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
+    {
+        a = oct_decode(r.w.x);
+        b = oct_decode(r.w.y);
     }
     __device__ static __forceinline__ void store_pair(T *p, uint32_t, uint32_t j0, v3 a, v3 b)
     {

@@ -59,9 +59,14 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     const int rbc = active ? rb : 0;
     const int lbuf[2] = {rbc * 3 * cstride, (a.RB + rbc) * 3 * cstride};
 
-    int64_t r = r_lane;
-    if (UNI) r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r_lane >> 32)) << 32) |
-                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r_lane & 0xFFFFFFFF));
+    // Idle lanes read the group's first replica (valid memory) and discard it, so
+    // that every global load is issued on every path: the hardware counts
+    // outstanding memory operations in issue order, and a wait then names only
+    // the loads it needs.
+    const int64_t r_first = a.r_base + (int64_t)rblk * a.RB;
+    int64_t r = active ? r_lane : r_first;
+    if (UNI) r = ((int64_t)__builtin_amdgcn_readfirstlane((int)(r >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)(r & 0xFFFFFFFF));
     const int64_t d = r / a.slots_per_sample;
     const int sis = (int)(r - d * a.slots_per_sample);
     T *base = (T *)a.spins + r * 2 * C::kPlanes * (int64_t)Nh;
@@ -82,58 +87,79 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
         c2 = (uint32_t)ts | ((uint32_t)o << 8) | (a.rep << 12) | ((uint32_t)p << 16);
         uid = a.uid_base + (uint32_t)d;
     }
+    // The halo rows y0 - 1 and y0 + TY of the other parity are staged by the
+    // first and last rows' threads; the others load their own row in their place
+    // (a cache hit), so the load is issued by every lane.
+    const bool halo = !full && (ty == 0 || ty == a.TY - 1);
+    const int hy = !halo ? y : (ty == 0) ? (y == 0 ? L - 1 : y - 1) : (y + 1 == L ? 0 : y + 1);
+    const int hw_row = (ty == 0) ? 0 : a.TY + 1;
+    auto wrapz = [L](int v) { return v >= L ? v - L : v; };
 
-    // rolling planes of the other parity at my two positions
+    // Other parity at my two positions: planes z - 1, z, z + 1 decoded and
+    // rolling; plane z + 2, the halo row of plane z + 1 and (over-relaxation)
+    // my own old spins of plane z + 1 are loaded one step ahead, raw.
     v3 prv0{}, prv1{}, cur0{}, cur1{}, nxt0{}, nxt1{};
-    if (active) {
+    typename C::R nraw, graw, oraw;
+    {
         C::load_pair(oth, Nh, (uint32_t)((((z0 == 0 ? L : z0) - 1) * L + y) * Lh + xh0), prv0, prv1);
         C::load_pair(oth, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), cur0, cur1);
+        C::load_raw_pair(oth, Nh, (uint32_t)((wrapz(z0 + 1) * L + y) * Lh + xh0), nraw);
+        C::load_raw_pair(oth, Nh, (uint32_t)((z0 * L + hy) * Lh + xh0), graw);
+        C::load_raw_pair(own, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), oraw);
     }
     double e = 0.0;
 
     for (int z = z0; z < z1; ++z) {
         const int lo = lbuf[z & 1];
-        const int zn = (z + 1 == L) ? 0 : z + 1;
         const uint32_t j0 = (uint32_t)((z * L + y) * Lh + xh0);  // my first site, half-index
-        float2 jc[6];
-        v3 hs0{0.f, 0.f, 0.f}, hs1{0.f, 0.f, 0.f}, old0{}, old1{};
-        u32x4 rr{0u, 0u, 0u, 0u};
-        if (active) {
-            // every global access of this step is issued before the barrier
-            C::load_pair(oth, Nh, (uint32_t)((zn * L + y) * Lh + xh0), nxt0, nxt1);
-            if (jbits) {  // +-1 couplings from sign bits (exactly the float values)
-                const uint32_t bits = *reinterpret_cast<const uint16_t *>(Jbb + j0);
-#pragma unroll
-                for (int n = 0; n < 6; ++n)
-                    jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
-            } else {
-#pragma unroll
-                for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
-            }
-            if (field) {
-                const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
-                const float2 hy = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
-                const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
-                hs0 = v3{hx.x, hy.x, hz.x};
-                hs1 = v3{hx.y, hy.y, hz.y};
-            }
-            if (KIND == 1) C::load_pair(own, Nh, j0, old0, old1);
-            // stage plane z (my two positions) in LDS
+        // values that arrived during the last step
+        C::decode_pair(nraw, nxt0, nxt1);
+        v3 old0{}, old1{};
+        if (KIND == 1) C::decode_pair(oraw, old0, old1);
+        v3 g0, g1;
+        C::decode_pair(graw, g0, g1);
+        if (active) {  // stage plane z (my two positions, and the halo rows) in LDS
             const int w = lo + lrow * Lh + xh0;
             *reinterpret_cast<float2 *>(&lds[w]) = make_float2(cur0.x, cur1.x);
             *reinterpret_cast<float2 *>(&lds[w + cstride]) = make_float2(cur0.y, cur1.y);
             *reinterpret_cast<float2 *>(&lds[w + 2 * cstride]) = make_float2(cur0.z, cur1.z);
-            if (!full && (ty == 0 || ty == a.TY - 1)) {  // halo rows y0 - 1 and y0 + TY
-                const int hy = (ty == 0) ? (y == 0 ? L - 1 : y - 1) : (y + 1 == L ? 0 : y + 1);
-                const int hw = lo + ((ty == 0) ? 0 : a.TY + 1) * Lh + xh0;
-                v3 g0, g1;
-                C::load_pair(oth, Nh, (uint32_t)((z * L + hy) * Lh + xh0), g0, g1);
+            if (halo) {
+                const int hw = lo + hw_row * Lh + xh0;
                 *reinterpret_cast<float2 *>(&lds[hw]) = make_float2(g0.x, g1.x);
                 *reinterpret_cast<float2 *>(&lds[hw + cstride]) = make_float2(g0.y, g1.y);
                 *reinterpret_cast<float2 *>(&lds[hw + 2 * cstride]) = make_float2(g0.z, g1.z);
             }
-            if (KIND != 1) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
         }
+        float2 jc[6];
+        v3 hs0{0.f, 0.f, 0.f}, hs1{0.f, 0.f, 0.f};
+        if (jbits) {  // +-1 couplings from sign bits (exactly the float values)
+            const uint32_t bits = *reinterpret_cast<const uint16_t *>(Jbb + j0);
+#pragma unroll
+            for (int n = 0; n < 6; ++n)
+                jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
+        } else {
+#pragma unroll
+            for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
+        }
+        if (field) {
+            const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
+            const float2 hy2 = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
+            const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
+            hs0 = v3{hx.x, hy2.x, hz.x};
+            hs1 = v3{hx.y, hy2.y, hz.y};
+        }
+        // Loads for the next step go out last, so that waiting for this step's
+        // couplings leaves them in flight. At the end of the slab they repeat
+        // planes already read (their values are never used).
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            const int zn = z + 1 < z1 ? z + 1 : z;
+            C::load_raw_pair(oth, Nh, (uint32_t)((wrapz(z + 2 <= z1 ? z + 2 : z1) * L + y) * Lh + xh0), nraw);
+            C::load_raw_pair(oth, Nh, (uint32_t)((zn * L + hy) * Lh + xh0), graw);
+            C::load_raw_pair(own, Nh, (uint32_t)((zn * L + y) * Lh + xh0), oraw);
+        }
+        u32x4 rr{0u, 0u, 0u, 0u};
+        if (KIND != 1 && active) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
         __syncthreads();
         if (active) {
             const int o = (y + z + p) & 1;  // x = 2 x/2 + o on this row
