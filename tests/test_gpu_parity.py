@@ -796,15 +796,17 @@ def test_or_pairs_two_by_two_bit_identical(hsg, storage):
     """Over-relaxation pairs fused two by two (one z-march of four half-sweeps,
     whole planes in LDS) against the same pairs as single half-sweeps: 1, 2, 3
     and 5 pairs (the odd one runs as a fused pair), spins bit for bit. Lattice
-    sizes 8, 12, 16, 24 and 32 in one launch cover 16 (partly filled), 7, 4 and
-    1 replicas per work-group, waves that span two replicas (L = 12) or run
-    part-empty (L = 24, 144 threads), and the first and last planes of every
-    stage (the periodic closure in z); a field (L = 12) and +-1 couplings read
-    as sign bits (L = 16)."""
+    sizes 4, 8, 12, 16, 20, 24 and 32 in one launch cover 64 and 16 (partly
+    filled), 7, 4, 2 and 1 replicas per work-group, waves that span two
+    replicas (L = 12, 20) or run part-empty (L = 24, 144 threads), the first
+    and last planes of every stage (the periodic closure in z; at L = 4 they
+    are the whole march), and the steady-state steps (L >= 12); a field
+    (L = 12) and +-1 couplings read as sign bits (L = 16)."""
     rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 64))
     groups, uid = [], 0
-    for L, D, T, field, cpl in ((8, 2, 3, None, "gaussian"), (12, 2, 2, ("gaussian", 0.3), "gaussian"),
-                                (16, 2, 2, None, "bimodal"), (24, 1, 2, None, "gaussian"),
+    for L, D, T, field, cpl in ((4, 3, 3, None, "gaussian"), (8, 2, 3, None, "gaussian"),
+                                (12, 2, 2, ("gaussian", 0.3), "gaussian"), (16, 2, 2, None, "bimodal"),
+                                (20, 1, 3, None, "gaussian"), (24, 1, 2, None, "gaussian"),
                                 (32, 2, 2, None, "gaussian")):
         groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, T),
                                         couplings=cpl, field=field, sample_uid_base=uid))
