@@ -136,14 +136,16 @@ hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t 
                           hsg_stream_t stream);
 
 /* Both half-sweeps of a pair (parity 0, then parity 1) of every replica, as
- * inside hsg_sweep: one fused launch where the kernel variant allows it,
- * else two passes. Uses the current sweep counter and does not advance it. */
+ * inside a sweep of the full-lattice chain (whatever hsg_set_chain selected):
+ * one fused launch where the kernel variant allows it, else two passes. Uses
+ * the current sweep counter and does not advance it. */
 hsg_status hsg_pair_sweep(hsg_lattice *h, int32_t kind, int32_t rep, hsg_stream_t stream);
 
-/* n_pairs >= 1 over-relaxation pairs (Eq. (3); parity 0, then 1, each time) of
- * every replica, as inside hsg_sweep: two by two in one launch where the kernel
- * variant allows it, the odd one as a pair. Deterministic, so it needs no
- * counter; energies are not computed. */
+/* n_pairs in 1..1000 over-relaxation pairs (Eq. (3); parity 0, then 1, each
+ * time) of every replica, as inside a sweep of the full-lattice chain: two by
+ * two in one launch where the kernel variant allows it, the odd one as a pair.
+ * Deterministic, so it needs no counter; energies are not computed. Returns
+ * HSG_E_INVALID for a NULL handle or n_pairs outside 1..1000. */
 hsg_status hsg_or_pairs(hsg_lattice *h, int32_t n_pairs, hsg_stream_t stream);
 
 /* One standalone tempering pass over every ladder using the energies of the
