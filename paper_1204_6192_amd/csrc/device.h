@@ -6,6 +6,7 @@
 // reductions; the library is compiled with -ffp-contract=off so that every
 // fused multiply-add below is one written on purpose.
 #pragma once
+#include <type_traits>
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -233,6 +234,21 @@ __device__ __forceinline__ v3 over_relax(v3 s, v3 h)
 }
 
 // ---------------------------------------------------------------- storage
+// Element i of an array. B32: as the base plus a 32-bit byte offset, which the
+// hardware adds to a wave-uniform base by itself (no 64-bit address arithmetic
+// per lane); the caller guarantees i * sizeof(T) < 2^32. Else ordinary
+// pointer arithmetic.
+template <bool B32, class T>
+__device__ __forceinline__ T *elem(T *p, uint32_t i)
+{
+    if constexpr (B32) {
+        using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+        return reinterpret_cast<T *>(reinterpret_cast<B *>(p) + i * (uint32_t)sizeof(T));
+    } else {
+        return p + i;
+    }
+}
+
 // Spins of one replica, one parity: three component planes of Nh values.
 template <int STORE>
 struct Codec;
@@ -254,11 +270,12 @@ struct Codec<0> {  // float32: stored renormalised, read as is
     __device__ static __forceinline__ v3 stored_value(v3 s) { return s; }
     // Two neighbouring sites j0, j0 + 1 (j0 even, 8-byte aligned): one 8-byte
     // access per component plane; 32-bit offsets (3 Nh < 2^32 for L <= 1024).
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
-        const float2 x = *reinterpret_cast<const float2 *>(p + j0);
-        const float2 y = *reinterpret_cast<const float2 *>(p + cs + j0);
-        const float2 z = *reinterpret_cast<const float2 *>(p + 2 * cs + j0);
+        const float2 x = *reinterpret_cast<const float2 *>(elem<B32>(p, j0));
+        const float2 y = *reinterpret_cast<const float2 *>(elem<B32>(p, cs + j0));
+        const float2 z = *reinterpret_cast<const float2 *>(elem<B32>(p, 2 * cs + j0));
         a = v3{x.x, y.x, z.x};
         b = v3{x.y, y.y, z.y};
     }
@@ -267,22 +284,24 @@ struct Codec<0> {  // float32: stored renormalised, read as is
     struct R {
         float2 x, y, z;
     };
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t cs, uint32_t j0, R &r)
     {
-        r.x = *reinterpret_cast<const float2 *>(p + j0);
-        r.y = *reinterpret_cast<const float2 *>(p + cs + j0);
-        r.z = *reinterpret_cast<const float2 *>(p + 2 * cs + j0);
+        r.x = *reinterpret_cast<const float2 *>(elem<B32>(p, j0));
+        r.y = *reinterpret_cast<const float2 *>(elem<B32>(p, cs + j0));
+        r.z = *reinterpret_cast<const float2 *>(elem<B32>(p, 2 * cs + j0));
     }
     __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
     {
         a = v3{r.x.x, r.y.x, r.z.x};
         b = v3{r.x.y, r.y.y, r.z.y};
     }
+    template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<float2 *>(p + j0) = make_float2(a.x, b.x);
-        *reinterpret_cast<float2 *>(p + cs + j0) = make_float2(a.y, b.y);
-        *reinterpret_cast<float2 *>(p + 2 * cs + j0) = make_float2(a.z, b.z);
+        *reinterpret_cast<float2 *>(elem<B32>(p, j0)) = make_float2(a.x, b.x);
+        *reinterpret_cast<float2 *>(elem<B32>(p, cs + j0)) = make_float2(a.y, b.y);
+        *reinterpret_cast<float2 *>(elem<B32>(p, 2 * cs + j0)) = make_float2(a.z, b.z);
     }
 };
 
@@ -305,33 +324,38 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
         return normalise_rsq(v3{__half2float(__float2half_rn(s.x)), __half2float(__float2half_rn(s.y)),
                                 __half2float(__float2half_rn(s.z))});
     }
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
-        const __half2 x = *reinterpret_cast<const __half2 *>(p + j0);
-        const __half2 y = *reinterpret_cast<const __half2 *>(p + cs + j0);
-        const __half2 z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
+        const __half2 x = *reinterpret_cast<const __half2 *>(elem<B32>(p, j0));
+        const __half2 y = *reinterpret_cast<const __half2 *>(elem<B32>(p, cs + j0));
+        const __half2 z = *reinterpret_cast<const __half2 *>(elem<B32>(p, 2 * cs + j0));
         a = normalise_rsq(v3{__low2float(x), __low2float(y), __low2float(z)});
         b = normalise_rsq(v3{__high2float(x), __high2float(y), __high2float(z)});
     }
     struct R {
         __half2 x, y, z;
     };
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t cs, uint32_t j0, R &r)
     {
-        r.x = *reinterpret_cast<const __half2 *>(p + j0);
-        r.y = *reinterpret_cast<const __half2 *>(p + cs + j0);
-        r.z = *reinterpret_cast<const __half2 *>(p + 2 * cs + j0);
+        r.x = *reinterpret_cast<const __half2 *>(elem<B32>(p, j0));
+        r.y = *reinterpret_cast<const __half2 *>(elem<B32>(p, cs + j0));
+        r.z = *reinterpret_cast<const __half2 *>(elem<B32>(p, 2 * cs + j0));
     }
     __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
     {
         a = normalise_rsq(v3{__low2float(r.x), __low2float(r.y), __low2float(r.z)});
         b = normalise_rsq(v3{__high2float(r.x), __high2float(r.y), __high2float(r.z)});
     }
+    template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<__half2 *>(p + j0) = __halves2half2(__float2half_rn(a.x), __float2half_rn(b.x));
-        *reinterpret_cast<__half2 *>(p + cs + j0) = __halves2half2(__float2half_rn(a.y), __float2half_rn(b.y));
-        *reinterpret_cast<__half2 *>(p + 2 * cs + j0) = __halves2half2(__float2half_rn(a.z), __float2half_rn(b.z));
+        *reinterpret_cast<__half2 *>(elem<B32>(p, j0)) = __halves2half2(__float2half_rn(a.x), __float2half_rn(b.x));
+        *reinterpret_cast<__half2 *>(elem<B32>(p, cs + j0)) =
+            __halves2half2(__float2half_rn(a.y), __float2half_rn(b.y));
+        *reinterpret_cast<__half2 *>(elem<B32>(p, 2 * cs + j0)) =
+            __halves2half2(__float2half_rn(a.z), __float2half_rn(b.z));
     }
 };
 
@@ -362,11 +386,12 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
         return normalise_rsq(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
                                 bf16_to_f32(f32_to_bf16_rne(s.z))});
     }
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_pair(const T *p, uint32_t cs, uint32_t j0, v3 &a, v3 &b)
     {
-        const uint32_t x = *reinterpret_cast<const uint32_t *>(p + j0);
-        const uint32_t y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
-        const uint32_t z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
+        const uint32_t x = *reinterpret_cast<const uint32_t *>(elem<B32>(p, j0));
+        const uint32_t y = *reinterpret_cast<const uint32_t *>(elem<B32>(p, cs + j0));
+        const uint32_t z = *reinterpret_cast<const uint32_t *>(elem<B32>(p, 2 * cs + j0));
         a = normalise_rsq(v3{__uint_as_float(x << 16), __uint_as_float(y << 16), __uint_as_float(z << 16)});
         b = normalise_rsq(v3{__uint_as_float(x & 0xFFFF0000u), __uint_as_float(y & 0xFFFF0000u),
                              __uint_as_float(z & 0xFFFF0000u)});
@@ -374,11 +399,12 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
     struct R {
         uint32_t x, y, z;
     };
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t cs, uint32_t j0, R &r)
     {
-        r.x = *reinterpret_cast<const uint32_t *>(p + j0);
-        r.y = *reinterpret_cast<const uint32_t *>(p + cs + j0);
-        r.z = *reinterpret_cast<const uint32_t *>(p + 2 * cs + j0);
+        r.x = *reinterpret_cast<const uint32_t *>(elem<B32>(p, j0));
+        r.y = *reinterpret_cast<const uint32_t *>(elem<B32>(p, cs + j0));
+        r.z = *reinterpret_cast<const uint32_t *>(elem<B32>(p, 2 * cs + j0));
     }
     __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
     {
@@ -386,11 +412,15 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
         b = normalise_rsq(v3{__uint_as_float(r.x & 0xFFFF0000u), __uint_as_float(r.y & 0xFFFF0000u),
                              __uint_as_float(r.z & 0xFFFF0000u)});
     }
+    template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<uint32_t *>(p + j0) = (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(b.x) << 16);
-        *reinterpret_cast<uint32_t *>(p + cs + j0) = (uint32_t)f32_to_bf16_rne(a.y) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
-        *reinterpret_cast<uint32_t *>(p + 2 * cs + j0) = (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(b.z) << 16);
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, j0)) =
+            (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(b.x) << 16);
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, cs + j0)) =
+            (uint32_t)f32_to_bf16_rne(a.y) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, 2 * cs + j0)) =
+            (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(b.z) << 16);
     }
 };
 
@@ -438,27 +468,30 @@ struct Codec<3> {
     __device__ static __forceinline__ v3 load(const T *p, int64_t, int64_t j) { return oct_decode(p[j]); }
     __device__ static __forceinline__ void store(T *p, int64_t, int64_t j, v3 s) { p[j] = oct_encode(s); }
     __device__ static __forceinline__ v3 stored_value(v3 s) { return oct_decode(oct_encode(s)); }
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_pair(const T *p, uint32_t, uint32_t j0, v3 &a, v3 &b)
     {
-        const uint2 w = *reinterpret_cast<const uint2 *>(p + j0);
+        const uint2 w = *reinterpret_cast<const uint2 *>(elem<B32>(p, j0));
         a = oct_decode(w.x);
         b = oct_decode(w.y);
     }
     struct R {
         uint2 w;
     };
+    template <bool B32 = false>
     __device__ static __forceinline__ void load_raw_pair(const T *p, uint32_t, uint32_t j0, R &r)
     {
-        r.w = *reinterpret_cast<const uint2 *>(p + j0);
+        r.w = *reinterpret_cast<const uint2 *>(elem<B32>(p, j0));
     }
     __device__ static __forceinline__ void decode_pair(const R &r, v3 &a, v3 &b)
     {
         a = oct_decode(r.w.x);
         b = oct_decode(r.w.y);
     }
+    template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<uint2 *>(p + j0) = make_uint2(oct_encode(a), oct_encode(b));
+        *reinterpret_cast<uint2 *>(elem<B32>(p, j0)) = make_uint2(oct_encode(a), oct_encode(b));
     }
 };
 
@@ -481,26 +514,54 @@ __device__ __forceinline__ void lds_get_pair(const float *lds, int w, int cstrid
     b = v3{x.y, y.y, z.y};
 }
 
+// The same for lattices addressed with 32-bit byte offsets, from one uniform
+// base per coupling plane (Jp[n] = the plane of bond n): each load is that base
+// plus the lane's byte offset, with no per-load address arithmetic.
 template <bool JB, bool FIELD>
-__device__ __forceinline__ void load_couplings(const float *Jb, const uint8_t *Jbb, const float *Hb, bool jbits,
-                                               bool field, uint32_t Nh, uint32_t j0, float2 (&jc)[6], v3 &hs0,
-                                               v3 &hs1)
+__device__ __forceinline__ void load_couplings_planes(const float *const (&Jp)[6], const uint8_t *Jbb,
+                                                      const float *Hb, bool jbits, bool field, uint32_t Nh,
+                                                      uint32_t j0, float2 (&jc)[6], v3 &hs0, v3 &hs1)
 {
     if (JB && jbits) {
-        const uint32_t bits = *reinterpret_cast<const uint16_t *>(Jbb + j0);
+        const uint32_t bits = *reinterpret_cast<const uint16_t *>(elem<true>(Jbb, j0));
 #pragma unroll
         for (int n = 0; n < 6; ++n)
             jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
     } else {
 #pragma unroll
-        for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
+        for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(elem<true>(Jp[n], j0));
     }
     hs0 = v3{0.f, 0.f, 0.f};
     hs1 = v3{0.f, 0.f, 0.f};
     if (FIELD && field) {
-        const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
-        const float2 hy = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
-        const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
+        const float2 hx = *reinterpret_cast<const float2 *>(elem<true>(Hb, j0));
+        const float2 hy = *reinterpret_cast<const float2 *>(elem<true>(Hb, Nh + j0));
+        const float2 hz = *reinterpret_cast<const float2 *>(elem<true>(Hb, 2 * Nh + j0));
+        hs0 = v3{hx.x, hy.x, hz.x};
+        hs1 = v3{hx.y, hy.y, hz.y};
+    }
+}
+
+template <bool JB, bool FIELD, bool B32 = false>
+__device__ __forceinline__ void load_couplings(const float *Jb, const uint8_t *Jbb, const float *Hb, bool jbits,
+                                               bool field, uint32_t Nh, uint32_t j0, float2 (&jc)[6], v3 &hs0,
+                                               v3 &hs1)
+{
+    if (JB && jbits) {
+        const uint32_t bits = *reinterpret_cast<const uint16_t *>(elem<B32>(Jbb, j0));
+#pragma unroll
+        for (int n = 0; n < 6; ++n)
+            jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
+    } else {
+#pragma unroll
+        for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(elem<B32>(Jb, n * Nh + j0));
+    }
+    hs0 = v3{0.f, 0.f, 0.f};
+    hs1 = v3{0.f, 0.f, 0.f};
+    if (FIELD && field) {
+        const float2 hx = *reinterpret_cast<const float2 *>(elem<B32>(Hb, j0));
+        const float2 hy = *reinterpret_cast<const float2 *>(elem<B32>(Hb, Nh + j0));
+        const float2 hz = *reinterpret_cast<const float2 *>(elem<B32>(Hb, 2 * Nh + j0));
         hs0 = v3{hx.x, hy.x, hz.x};
         hs1 = v3{hx.y, hy.y, hz.y};
     }

@@ -320,7 +320,9 @@ __device__ __forceinline__ double update_pair(const float *lds, int lo, int cstr
 // z - 2, z - 1, z. The periodic seam is closed after the march: the parity-1
 // sites of planes L - 1 and 0 need new parity-0 planes 0 and 1, kept in LDS
 // from the first two steps. The result equals the two single half-sweeps bit
-// for bit; every stored spin is read and written once per pair.
+// for bit; every stored spin is read and written once per pair. Whole planes
+// in one work-group mean L <= 32, so every byte offset into a replica's spins,
+// couplings and field fits 32 bits (the fused kernels address that way).
 template <int STORE, int KIND, bool FIELD, bool ENERGY, bool UNI, bool JB>
 __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, float *lds, double *red)
 {
@@ -362,6 +364,12 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
     const uint8_t *Jb1 = jbits ? a.Jbits + (d * 2 + 1) * (int64_t)Nh : nullptr;
     const float *H0 = field ? a.Hp + (d * 2 + 0) * 3 * (int64_t)Nh : nullptr;
     const float *H1 = field ? a.Hp + (d * 2 + 1) * 3 * (int64_t)Nh : nullptr;
+    const float *Jp0[6], *Jp1[6];  // one uniform base per coupling plane
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        Jp0[n] = J0 + n * Nh;
+        Jp1[n] = J1 + n * Nh;
+    }
     float beta = 0.0f;
     uint32_t c2A = 0, c2B = 0, uid = 0;
     const uint32_t tsweep = *a.tptr;
@@ -384,10 +392,10 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
 #pragma unroll
     for (int n = 0; n < 6; ++n) jcB[n] = make_float2(0.f, 0.f);
     if (active) {
-        C::load_pair(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), o_prv0, o_prv1);
-        C::load_pair(sp1, Nh, (uint32_t)(y * Lh + xh0), o_cur0, o_cur1);
-        C::load_pair(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), o_nxt0, o_nxt1);
-        if (KIND == 1) C::load_pair(sp0, Nh, (uint32_t)(y * Lh + xh0), oldA0, oldA1);
+        C::template load_pair<true>(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), o_prv0, o_prv1);
+        C::template load_pair<true>(sp1, Nh, (uint32_t)(y * Lh + xh0), o_cur0, o_cur1);
+        C::template load_pair<true>(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), o_nxt0, o_nxt1);
+        if (KIND == 1) C::template load_pair<true>(sp0, Nh, (uint32_t)(y * Lh + xh0), oldA0, oldA1);
     }
     double e = 0.0;
 
@@ -400,11 +408,11 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
             if (z + 1 < L) {  // for step z + 1: old parity 1 of plane z + 2, old parity 0 of plane z + 1
                 const int z2 = (z + 2 >= L) ? z + 2 - L : z + 2;
                 const uint32_t jA1 = jA + (uint32_t)(L * Lh);
-                C::load_pair(sp1, Nh, (uint32_t)((z2 * L + y) * Lh + xh0), o_nn0, o_nn1);
-                if (KIND == 1) C::load_pair(sp0, Nh, jA1, oldN0, oldN1);
+                C::template load_pair<true>(sp1, Nh, (uint32_t)((z2 * L + y) * Lh + xh0), o_nn0, o_nn1);
+                if (KIND == 1) C::template load_pair<true>(sp0, Nh, jA1, oldN0, oldN1);
             }
-            load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
-            if (doB) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
+            load_couplings_planes<JB, FIELD>(Jp0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
+            if (doB) load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
             lds_put_pair(lds, lA[z & 1] + lrow_w, cstride, o_cur0, o_cur1);
             if (KIND != 1) {
                 rrA = philox4x32_10(u32x4{jA >> 1, tsweep, c2A, uid}, a.key0, a.key1);
@@ -417,7 +425,7 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
             update_pair<STORE, KIND, false>(lds, lA[z & 1], cstride, Lh, ty, lrm, lrp, xh0, (y + z) & 1, o_cur0,
                                             o_cur1, o_nxt0, o_nxt1, o_prv0, o_prv1, jcA, hA0, hA1, oldA0, oldA1, rrA,
                                             beta, sA0, sA1);
-            C::store_pair(sp0, Nh, jA, sA0, sA1);
+            C::template store_pair<true>(sp0, Nh, jA, sA0, sA1);
             // later stages read the stored (rounded) values, as the single passes do
             sA0 = C::stored_value(sA0);
             sA1 = C::stored_value(sA1);
@@ -428,11 +436,11 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
                 e += update_pair<STORE, KIND, ENERGY>(lds, lB[(z - 1) & 1], cstride, Lh, ty, lrm, lrp, xh0,
                                                       (y + z) & 1, a_m10, a_m11, sA0, sA1, a_m20, a_m21, jcB, hB0,
                                                       hB1, o_prv0, o_prv1, rrB, beta, sB0, sB1);
-                C::store_pair(sp1, Nh, jB, sB0, sB1);
+                C::template store_pair<true>(sp1, Nh, jB, sB0, sB1);
                 if (ENERGY && field) {  // field on the parity-0 sites at the same half-indices
-                    const float2 fx = *reinterpret_cast<const float2 *>(H0 + jB);
-                    const float2 fy = *reinterpret_cast<const float2 *>(H0 + Nh + jB);
-                    const float2 fz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + jB);
+                    const float2 fx = *reinterpret_cast<const float2 *>(elem<true>(H0, jB));
+                    const float2 fy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + jB));
+                    const float2 fz = *reinterpret_cast<const float2 *>(elem<true>(H0, 2 * Nh + jB));
                     e -= (double)fx.x * a_m10.x + (double)fy.x * a_m10.y + (double)fz.x * a_m10.z;
                     e -= (double)fx.y * a_m11.x + (double)fy.y * a_m11.y + (double)fz.y * a_m11.z;
                 }
@@ -454,8 +462,8 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         v3 hL0, hL1, hZ0, hZ1;
         u32x4 rrL{0u, 0u, 0u, 0u}, rr0{0u, 0u, 0u, 0u};
         if (active) {
-            load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
-            load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
+            load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
+            load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
             if (KIND != 1) {
                 rrL = philox4x32_10(u32x4{jL >> 1, tsweep, c2B, uid}, a.key0, a.key1);
                 rr0 = philox4x32_10(u32x4{j0 >> 1, tsweep, c2B, uid}, a.key0, a.key1);
@@ -475,17 +483,17 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
             e += update_pair<STORE, KIND, ENERGY>(lds, lS[0], cstride, Lh, ty, lrm, lrp, xh0, (y + 1) & 1, n00,
                                                   n01, n10, n11, a_m10, a_m11, jc0, hZ0, hZ1, o_cur0, o_cur1, rr0,
                                                   beta, sZ0, sZ1);
-            C::store_pair(sp1, Nh, jL, sL0, sL1);
-            C::store_pair(sp1, Nh, j0, sZ0, sZ1);
+            C::template store_pair<true>(sp1, Nh, jL, sL0, sL1);
+            C::template store_pair<true>(sp1, Nh, j0, sZ0, sZ1);
             if (ENERGY && field) {
-                const float2 fx = *reinterpret_cast<const float2 *>(H0 + jL);
-                const float2 fy = *reinterpret_cast<const float2 *>(H0 + Nh + jL);
-                const float2 fz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + jL);
+                const float2 fx = *reinterpret_cast<const float2 *>(elem<true>(H0, jL));
+                const float2 fy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + jL));
+                const float2 fz = *reinterpret_cast<const float2 *>(elem<true>(H0, 2 * Nh + jL));
                 e -= (double)fx.x * a_m10.x + (double)fy.x * a_m10.y + (double)fz.x * a_m10.z;
                 e -= (double)fx.y * a_m11.x + (double)fy.y * a_m11.y + (double)fz.y * a_m11.z;
-                const float2 gx = *reinterpret_cast<const float2 *>(H0 + j0);
-                const float2 gy = *reinterpret_cast<const float2 *>(H0 + Nh + j0);
-                const float2 gz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + j0);
+                const float2 gx = *reinterpret_cast<const float2 *>(elem<true>(H0, j0));
+                const float2 gy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + j0));
+                const float2 gz = *reinterpret_cast<const float2 *>(elem<true>(H0, 2 * Nh + j0));
                 e -= (double)gx.x * n00.x + (double)gy.x * n00.y + (double)gz.x * n00.z;
                 e -= (double)gx.y * n01.x + (double)gy.y * n01.y + (double)gz.y * n01.z;
             }
@@ -573,6 +581,14 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
     const uint8_t *Jb1 = jbits ? a.Jbits + (d * 2 + 1) * (int64_t)Nh : nullptr;
     const float *H0 = field ? a.Hp + (d * 2 + 0) * 3 * (int64_t)Nh : nullptr;
     const float *H1 = field ? a.Hp + (d * 2 + 1) * 3 * (int64_t)Nh : nullptr;
+    // one base per coupling plane: uniform, so each load is that base plus the
+    // lane's byte offset, with no per-load address arithmetic
+    const float *Jp[2][6];
+#pragma unroll
+    for (int n = 0; n < 6; ++n) {
+        Jp[0][n] = J0 + n * Nh;
+        Jp[1][n] = J1 + n * Nh;
+    }
 
     // The loaded spins are addressed by the step modulo 4 (the march is
     // unrolled by four, so the indices are constants and a load lands where it
@@ -593,10 +609,10 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
 #pragma unroll
     for (int s = 0; s < D - 1; ++s) fa[s] = fb[s] = v3{0.f, 0.f, 0.f};
     oa[1] = ob[1] = v3{0.f, 0.f, 0.f};
-    C::load_pair(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), ia[3], ib[3]);
-    C::load_pair(sp1, Nh, (uint32_t)(y * Lh + xh0), ia[0], ib[0]);
-    C::load_pair(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), ia[1], ib[1]);
-    C::load_pair(sp0, Nh, (uint32_t)(y * Lh + xh0), oa[0], ob[0]);
+    C::template load_pair<true>(sp1, Nh, (uint32_t)(((L - 1) * L + y) * Lh + xh0), ia[3], ib[3]);
+    C::template load_pair<true>(sp1, Nh, (uint32_t)(y * Lh + xh0), ia[0], ib[0]);
+    C::template load_pair<true>(sp1, Nh, (uint32_t)((L + y) * Lh + xh0), ia[1], ib[1]);
+    C::template load_pair<true>(sp0, Nh, (uint32_t)(y * Lh + xh0), oa[0], ob[0]);
     double e = 0.0;
     const int n_steps = L + 2 * (D - 1);
     auto wrap = [L](int v) {
@@ -615,16 +631,16 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
 #pragma unroll
         for (int s = 0; s < D; ++s) {  // every stage's couplings, also for the steps it idles
             const uint32_t jw = (uint32_t)((wrap(z + L - s) * L + y) * Lh + xh0);
-            if (s & 1) load_couplings<JB, FIELD>(J1, Jb1, H1, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
-            else load_couplings<JB, FIELD>(J0, Jb0, H0, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+            if (s & 1) load_couplings_planes<JB, FIELD>(Jp[1], Jb1, H1, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+            else load_couplings_planes<JB, FIELD>(Jp[0], Jb0, H0, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
         }
         // The spin loads for the next step go out last, so that the waits for
         // this step's couplings leave them in flight. Past the end of the march
         // their values are never used: they repeat the last loads (cache hits).
         __builtin_amdgcn_sched_barrier(0);
         const int zi = z + 1 < L ? wrap(z + 2) : 0, zo = z + 1 < L ? z + 1 : L - 1;
-        C::load_pair(sp1, Nh, (uint32_t)((zi * L + y) * Lh + xh0), ia[(K + 2) & 3], ib[(K + 2) & 3]);
-        C::load_pair(sp0, Nh, (uint32_t)((zo * L + y) * Lh + xh0), oa[(K + 1) & 1], ob[(K + 1) & 1]);
+        C::template load_pair<true>(sp1, Nh, (uint32_t)((zi * L + y) * Lh + xh0), ia[(K + 2) & 3], ib[(K + 2) & 3]);
+        C::template load_pair<true>(sp0, Nh, (uint32_t)((zo * L + y) * Lh + xh0), oa[(K + 1) & 1], ob[(K + 1) & 1]);
         __syncthreads();
         // one stage; written as a function of a constant so that every register
         // index is known before the compiler places the arrays
@@ -684,9 +700,9 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
                                                    zm1, jc[s], hs0[s], hs1[s], od0, od1, u32x4{0u, 0u, 0u, 0u}, 0.0f,
                                                    r0, r1);
                 if (ENERGY && field) {  // field on the parity-0 sites at the same half-indices: stage D - 2
-                    const float2 fx = *reinterpret_cast<const float2 *>(H0 + jw);
-                    const float2 fy = *reinterpret_cast<const float2 *>(H0 + Nh + jw);
-                    const float2 fz = *reinterpret_cast<const float2 *>(H0 + 2 * Nh + jw);
+                    const float2 fx = *reinterpret_cast<const float2 *>(elem<true>(H0, jw));
+                    const float2 fy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + jw));
+                    const float2 fz = *reinterpret_cast<const float2 *>(elem<true>(H0, 2 * Nh + jw));
                     e -= (double)fx.x * c0.x + (double)fy.x * c0.y + (double)fz.x * c0.z;
                     e -= (double)fx.y * c1.x + (double)fy.y * c1.y + (double)fz.y * c1.z;
                 }
@@ -695,7 +711,7 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
                                                    zm1, jc[s], hs0[s], hs1[s], od0, od1, u32x4{0u, 0u, 0u, 0u}, 0.0f,
                                                    r0, r1);
             }
-            if (s >= D - 2) C::store_pair((s & 1) ? sp1 : sp0, Nh, jw, r0, r1);
+            if (s >= D - 2) C::template store_pair<true>((s & 1) ? sp1 : sp0, Nh, jw, r0, r1);
             if constexpr (s < D - 1) {
                 r0 = C::stored_value(r0);
                 r1 = C::stored_value(r1);
