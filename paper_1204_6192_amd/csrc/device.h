@@ -222,13 +222,19 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
 }
 
 // ---------------------------------------------------------------- Eq. (3)
-// Reflection of s about the local field; a zero field leaves s unchanged. The
-// spin must be a unit vector to float32 precision (the reflection keeps |s|).
+// Reflection of s about the local field; a zero field (|h|^2 below 1e-30)
+// leaves s unchanged. The spin must be a unit vector to float32 precision (the
+// reflection keeps |s|).
 __device__ __forceinline__ v3 over_relax(v3 s, v3 h)
 {
     const float hh = dot3(h, h);
-    if (hh == 0.0f) return s;
-    const float f = 2.0f * dot3(s, h) / hh;
+    // A field with |h|^2 below 1e-30 counts as zero (its direction is noise).
+    if (!(hh >= 1e-30f)) return s;
+    // 2 (s.h) / (h.h) from the hardware reciprocal refined by one Newton step:
+    // within about an ulp (the result is renormalised below in any case).
+    float rh = __builtin_amdgcn_rcpf(hh);
+    rh = fmaf(rh, fmaf(-hh, rh, 1.0f), rh);
+    const float f = 2.0f * dot3(s, h) * rh;
     v3 r{fmaf(f, h.x, -s.x), fmaf(f, h.y, -s.y), fmaf(f, h.z, -s.z)};
     return renorm_unit(r);
 }
