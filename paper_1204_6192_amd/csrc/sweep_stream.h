@@ -411,8 +411,14 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
                 C::template load_pair<true>(sp1, Nh, (uint32_t)((z2 * L + y) * Lh + xh0), o_nn0, o_nn1);
                 if (KIND == 1) C::template load_pair<true>(sp0, Nh, jA1, oldN0, oldN1);
             }
-            load_couplings_planes<JB, FIELD>(Jp0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
-            if (doB) load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
+            {
+                if constexpr (UNI) load_couplings_planes<JB, FIELD>(Jp0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
+                else load_couplings<JB, FIELD, true>(J0, Jb0, H0, jbits, field, Nh, jA, jcA, hA0, hA1);
+            }
+            if (doB) {
+                if constexpr (UNI) load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
+                else load_couplings<JB, FIELD, true>(J1, Jb1, H1, jbits, field, Nh, jB, jcB, hB0, hB1);
+            }
             lds_put_pair(lds, lA[z & 1] + lrow_w, cstride, o_cur0, o_cur1);
             if (KIND != 1) {
                 rrA = philox4x32_10(u32x4{jA >> 1, tsweep, c2A, uid}, a.key0, a.key1);
@@ -462,8 +468,14 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         v3 hL0, hL1, hZ0, hZ1;
         u32x4 rrL{0u, 0u, 0u, 0u}, rr0{0u, 0u, 0u, 0u};
         if (active) {
-            load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
-            load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
+            {
+                if constexpr (UNI) load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
+                else load_couplings<JB, FIELD, true>(J1, Jb1, H1, jbits, field, Nh, jL, jcL, hL0, hL1);
+            }
+            {
+                if constexpr (UNI) load_couplings_planes<JB, FIELD>(Jp1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
+                else load_couplings<JB, FIELD, true>(J1, Jb1, H1, jbits, field, Nh, j0, jc0, hZ0, hZ1);
+            }
             if (KIND != 1) {
                 rrL = philox4x32_10(u32x4{jL >> 1, tsweep, c2B, uid}, a.key0, a.key1);
                 rr0 = philox4x32_10(u32x4{j0 >> 1, tsweep, c2B, uid}, a.key0, a.key1);
@@ -631,8 +643,15 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
 #pragma unroll
         for (int s = 0; s < D; ++s) {  // every stage's couplings, also for the steps it idles
             const uint32_t jw = (uint32_t)((wrap(z + L - s) * L + y) * Lh + xh0);
-            if (s & 1) load_couplings_planes<JB, FIELD>(Jp[1], Jb1, H1, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
-            else load_couplings_planes<JB, FIELD>(Jp[0], Jb0, H0, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+            // per-plane bases pay off where they are uniform (scalar registers);
+            // per lane they would cost 24 vector registers
+            if constexpr (UNI) {
+                if (s & 1) load_couplings_planes<JB, FIELD>(Jp[1], Jb1, H1, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+                else load_couplings_planes<JB, FIELD>(Jp[0], Jb0, H0, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+            } else {
+                if (s & 1) load_couplings<JB, FIELD, true>(J1, Jb1, H1, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+                else load_couplings<JB, FIELD, true>(J0, Jb0, H0, jbits, field, Nh, jw, jc[s], hs0[s], hs1[s]);
+            }
         }
         // The spin loads for the next step go out last, so that the waits for
         // this step's couplings leave them in flight. Past the end of the march
