@@ -1,0 +1,58 @@
+"""The benchmark's accounting of algorithmic bytes and flops, against the
+formulas the roofline figures use (written out here per workload)."""
+import os
+import sys
+from types import SimpleNamespace
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _group(L, D, O, T, coupling_kind=0, field=False):
+    return SimpleNamespace(L=L, N=L ** 3, n_samples=D, n_slots=D * O * T, coupling_kind=coupling_kind,
+                           H=object() if field else None)
+
+
+def test_batched_workload_bytes():
+    """L = 32, 64 samples x 2 copies x 32 temperatures, float32: a fused pair
+    reads and writes every spin once (24 B per site) and reads the 24 B of
+    couplings per site once per sample; two fused over-relaxation pairs move the
+    spins once and the couplings twice."""
+    g = _group(32, 64, 2, 32)
+    N, R, D = 32 ** 3, 4096, 64
+    assert bench.fused(g)
+    assert bench.algorithmic_bytes([g], "f32", 1) == R * N * 24 + D * N * 24  # 3.272 GB
+    assert bench.algorithmic_bytes([g], "f32", 0) == R * N * 18 + D * N * 24  # heat bath: parity 0 not read
+    assert bench.or_bytes_two_pairs([g], "f32") == R * N * 24 + 2 * D * N * 24  # 3.322 GB
+    assert abs(bench.or_bytes_two_pairs([g], "f32") / 3.322e9 - 1) < 1e-3
+
+
+def test_unfused_and_compressed_bytes():
+    """Lattices that do not fuse pay 3 b_s per over-relaxation update and 2 b_s
+    per heat-bath update; float16 halves b_s; +-1 couplings cost one byte per
+    site and a field 12 B per site, per sample."""
+    g = _group(64, 16, 2, 24, field=True)
+    N, R, D = 64 ** 3, 768, 16
+    assert not bench.fused(g)
+    assert bench.algorithmic_bytes([g], "f16", 1) == R * N * 18 + D * N * (24 + 12)
+    assert bench.algorithmic_bytes([g], "f16", 0) == R * N * 12 + D * N * (24 + 12)
+    gb = _group(128, 1, 2, 32, coupling_kind=1)
+    assert bench.algorithmic_bytes([gb], "qangle", 1) == 64 * 128 ** 3 * 12 + 128 ** 3 * 1
+
+
+def test_flop_count_and_ridge():
+    """90 FP32 flops per over-relaxation update (an FMA counting two): the local
+    field 18 FMA, h.h and s.h (a product and two FMA each), 2 (s.h) times the
+    reciprocal, the reflection 3 FMA and the compensated renormalisation (36).
+    Both over-relaxation kernels of the batched workload lie below the ridge of
+    the published peaks."""
+    assert bench.OR_FLOPS_PER_UPDATE == 36 + 5 + 5 + 2 + 6 + 36 == 90
+    ridge = bench.PEAK_FP32_TFLOPS * 1e12 / (bench.PEAK_HBM_GBS * 1e9)
+    assert ridge == pytest.approx(19.66, rel=1e-3)
+    g = _group(32, 64, 2, 32)
+    upd = g.n_slots * g.N
+    assert 2 * upd * 90 / bench.or_bytes_two_pairs([g], "f32") < ridge
+    assert upd * 90 / bench.algorithmic_bytes([g], "f32", 1) < ridge
