@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--overlap-every", type=int, default=None,
                     help="measure the overlap after every k-th sweep inside the timed region "
                          "(default: 1 for the large workload, else never)")
+    ap.add_argument("--two-streams", type=int, default=None, choices=[0, 1],
+                    help="sweep the two halves of the samples on two streams, one half's heat bath "
+                         "beside the other's over-relaxation (default: 1 for the uneven workload, else 0)")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=40)
@@ -271,6 +274,10 @@ def main():
         f"storage {inst.storage}; inputs in {time.perf_counter() - t_gen:.1f} s")
     lat = hsg.Lattice(inst.groups, storage=inst.storage, n_hb=inst.n_hb, n_or=inst.n_or,
                       pt_every=inst.pt_every, seed=inst.seed)
+    two_streams = args.two_streams
+    if two_streams is None:
+        two_streams = 1 if args.config == "uneven" else 0
+    lat.set_overlap(two_streams)
     n_hit = 1
     if args.tiles:
         ty, tz, n_hit = (int(v) for v in args.tiles.split(","))
@@ -354,7 +361,7 @@ def main():
                     + (f" + overlap every {overlap_every}" if overlap_every else ""),
            "field_amp": None if inst.groups[0].H is None else float(
                args.field_amp if args.field_amp is not None else 0.1),
-           "spins": lat.n_spins, "replicas": lat.n_replicas}
+           "two_streams": bool(two_streams), "spins": lat.n_spins, "replicas": lat.n_replicas}
     out = {
         "metric": METRIC, "value": ns_update, "unit": "ns/update", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,

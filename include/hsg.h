@@ -230,6 +230,20 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
  * staged planes fit the work-group's LDS; 0 = automatic (currently 4). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
+/* Tuning (results do not depend on it): 1 = where every lattice size runs
+ * the z-march, has at least two samples and no replica batches, and the
+ * full-lattice chain is selected, hsg_sweep runs the two halves of every
+ * group's samples on two streams (the caller's and one of the library's,
+ * joined before it returns), each half with its own device sweep counter
+ * (the second copied from the first at the start of every call); one half's
+ * heat-bath pairs then run beside the other half's over-relaxation pairs.
+ * Samples never interact (tempering is per sample), so every replica gets the
+ * same updates with the same random numbers. 0 (default) = one stream (and
+ * hipGraph replay). It pays where the two kinds of pass are limited by
+ * different resources (lattice sizes of unequal cost); hsg_autotune tries it.
+ * Returns HSG_E_INVALID for a NULL handle or a value other than 0 and 1. */
+hsg_status hsg_set_overlap(hsg_lattice *h, int32_t enable);
+
 /* Arithmetic of the heat-bath draw (Eq. (2)). 0 (default): correctly rounded
  * square root and division, library sincospi, log, exp, log1p and expm1.
  * 1: the field's length, direction and the divisions from the hardware
@@ -262,8 +276,10 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
 /* Autotuner of the launch configuration (the batching row of the method: tile
  * shape and fusion per lattice size). Times n_sweeps (1..1000) whole sweeps of
  * each distinct kernel variant of hsg_set_kernel (and, where lattices use the
- * gather kernel, 2, 4, 8 or 16 slots per work item) with HIP events after one
- * warm-up sweep each, and keeps the fastest. Every variant computes the same
+ * gather kernel, 2, 4, 8 or 16 slots per work item; where hsg_set_overlap
+ * applies, each z-march variant also with overlapped sweeps) with HIP events
+ * after one warm-up sweep each, and keeps the fastest (the overlap choice is
+ * kept too and is not reported). Every variant computes the same
  * bits, so the trial sweeps are ordinary sweeps of the chain: with
  * d_backup == NULL the chain advances by them (n_sweeps + 1 per candidate);
  * with d_backup (device, state_bytes of hsg_query_sizes, 256-byte aligned,

@@ -264,6 +264,13 @@ struct hsg_lattice {
     bool have_energies = false;
     // hipGraph replay of whole sweeps (tempering every sweep or never)
     bool use_graphs = true;
+    // Overlapped sweeps (hsg_set_overlap): two halves of every group's samples on
+    // two streams, each with its own device sweep counter (cohort 0: the
+    // counter at the start of the state buffer, cohort 1: the next word).
+    bool overlap = false;
+    int32_t cohort = 0;  // the counter the launches being enqueued read
+    hipStream_t stream2 = nullptr;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};  // fork, half 0 HB, half 1 HB, join
     hipStream_t capture_stream = nullptr;
     hipGraph_t graph[2] = {nullptr, nullptr};         // 1 sweep, kGraphSweeps sweeps
     hipGraphExec_t graph_exec[2] = {nullptr, nullptr};
@@ -275,7 +282,7 @@ constexpr int kGraphSweeps = 8;
 
 hipStream_t S(hsg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
-uint32_t *dev_counter(const hsg_lattice *h) { return reinterpret_cast<uint32_t *>(h->state); }
+uint32_t *dev_counter(const hsg_lattice *h) { return reinterpret_cast<uint32_t *>(h->state) + h->cohort; }
 
 void drop_graphs(hsg_lattice *h)
 {
@@ -915,6 +922,139 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
     return HSG_OK;
 }
 
+// ---------------------------------------------------------------- overlapped sweeps
+// Samples never interact, so the two halves of every group's samples can run
+// their sweeps on two streams, each half with its own device sweep counter.
+// The second half's heat-bath pairs of a sweep wait for the first half's, and
+// the first half's next heat-bath pairs for the second half's, so that each
+// half's heat bath (bound by instruction issue) runs beside the other half's
+// over-relaxation (bound by latency). Every replica gets the same updates with
+// the same counters as in one stream, so the results are the same bits.
+bool overlap_ok(const hsg_lattice *h)
+{
+    if (!h->overlap || h->chain != 0) return false;
+    for (const Group &g : h->lay.g) {
+        if (!use_stream(h, g) || g.D < 2 || batch_of(h, g) > 0) return false;
+    }
+    return true;
+}
+
+// Replica and sample range [r0, r1), [d0, d1) of half c of group g.
+void half_range(const Group &g, int c, int64_t &d0, int64_t &d1, int64_t &r0, int64_t &r1)
+{
+    const int64_t half = g.D / 2, spp = (int64_t)g.O * g.T;
+    d0 = c == 0 ? 0 : half;
+    d1 = c == 0 ? half : g.D;
+    r0 = d0 * spp;
+    r1 = d1 * spp;
+}
+
+// One sweep of half c (heat-bath pairs, then the rest), on stream s; `hb_done`
+// is recorded after the heat-bath pairs.
+hsg_status enqueue_half_sweep(hsg_lattice *h, int c, bool pt, hipStream_t s, hipEvent_t hb_done)
+{
+    h->cohort = c;
+    const int last_kind = h->n_or > 0 ? 1 : 0;
+    hsg_status st = HSG_OK;
+    for (const Group &g : h->lay.g) {
+        int64_t d0, d1, r0, r1;
+        half_range(g, c, d0, d1, r0, r1);
+        for (int r = 0; r < h->n_hb && st == HSG_OK; ++r)
+            st = run_pair(h, 0, r, last_kind == 0 && r == h->n_hb - 1, s, &g, r0, r1, false);
+    }
+    hipError_t e = st == HSG_OK ? hipEventRecord(hb_done, s) : hipSuccess;
+    if (e != hipSuccess) st = hip_fail(e, "event record");
+    for (const Group &g : h->lay.g) {
+        if (st != HSG_OK) break;
+        int64_t d0, d1, r0, r1;
+        half_range(g, c, d0, d1, r0, r1);
+        st = run_or_rounds(h, h->n_or, true, s, &g, r0, r1, false);
+        if (st != HSG_OK) break;
+        const int n_pb = use_pair(h, g) ? 1 : g.s_ytiles * g.s_zslabs;
+        e = hsg::launch_reduce_partials(reinterpret_cast<double *>(h->scratch + g.o_scr) + r0 * n_pb, n_pb,
+                                        r1 - r0, reinterpret_cast<double *>(h->state + g.o_E) + r0, s);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "energy reduction launch");
+            break;
+        }
+        const int64_t OT = (int64_t)g.O * g.T;
+        if (pt) {
+            hsg::PtArgs a{};
+            a.slot_at_temp = reinterpret_cast<int32_t *>(h->state + g.o_sat) + d0 * OT;
+            a.temp_of_slot = reinterpret_cast<int32_t *>(h->state + g.o_tos) + d0 * OT;
+            a.E = reinterpret_cast<const double *>(h->state + g.o_E) + d0 * OT;
+            a.beta64 = reinterpret_cast<const double *>(h->coup + g.o_b64);
+            a.accepts = reinterpret_cast<unsigned long long *>(h->state + g.o_acc) + d0 * g.O * (g.T - 1);
+            a.D = (int32_t)(d1 - d0);
+            a.O = g.O;
+            a.T = g.T;
+            a.tptr = dev_counter(h);
+            a.ctr1 = 0;
+            a.purpose = 1;
+            a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+            a.key1 = (uint32_t)(h->seed >> 32);
+            a.uid_base = g.uid_base + (uint32_t)d0;
+            e = hsg::launch_pt(a, s);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "tempering launch");
+                break;
+            }
+        }
+        if (h->stats) {
+            hsg::StatsArgs a = stats_args(h, g);
+            a.slot_at_temp += d0 * OT;
+            a.E += d0 * OT;
+            a.sum += d0 * OT * 2;
+            a.flag += d0 * OT;
+            a.trips += d0 * OT;
+            a.D = (int32_t)(d1 - d0);
+            e = hsg::launch_stats(a, false, s);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "statistics launch");
+                break;
+            }
+        }
+    }
+    if (st == HSG_OK) {
+        e = hsg::launch_advance(dev_counter(h), s);
+        if (e != hipSuccess) st = hip_fail(e, "counter launch");
+    }
+    h->cohort = 0;
+    return st;
+}
+
+hsg_status overlapped_sweeps(hsg_lattice *h, int32_t n_sweeps, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    if (h->stream2 == nullptr) e = hipStreamCreateWithFlags(&h->stream2, hipStreamNonBlocking);
+    for (auto &x : h->ev)
+        if (e == hipSuccess && x == nullptr) e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(e, "overlap stream or events");
+    hipStream_t s2 = h->stream2;
+    // Sweeps on one stream advance only the first counter: the second half starts from it.
+    uint32_t *const ctr = reinterpret_cast<uint32_t *>(h->state);
+    e = hsg::launch_copy_u32(ctr, ctr + 1, s);
+    if (e == hipSuccess) e = hipEventRecord(h->ev[0], s);  // fork: the second stream starts after the caller's work
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, h->ev[0], 0);
+    if (e != hipSuccess) return hip_fail(e, "overlap fork");
+    hsg_status st = HSG_OK;
+    for (int k = 0; k < n_sweeps && st == HSG_OK; ++k) {
+        const bool pt = h->pt_every > 0 && ((h->t + 1) % (uint64_t)h->pt_every) == 0;
+        if (k > 0) e = hipStreamWaitEvent(s, h->ev[2], 0);  // half 0's heat bath after half 1's
+        if (e != hipSuccess) return hip_fail(e, "overlap wait");
+        st = enqueue_half_sweep(h, 0, pt, s, h->ev[1]);
+        if (st != HSG_OK) break;
+        e = hipStreamWaitEvent(s2, h->ev[1], 0);  // half 1's heat bath after half 0's
+        if (e != hipSuccess) return hip_fail(e, "overlap wait");
+        st = enqueue_half_sweep(h, 1, pt, s2, h->ev[2]);
+        if (st == HSG_OK) h->t += 1;
+    }
+    e = hipEventRecord(h->ev[3], s2);  // join: the caller's stream continues after both halves
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev[3], 0);
+    if (e != hipSuccess && st == HSG_OK) st = hip_fail(e, "overlap join");
+    return st;
+}
+
 hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
@@ -924,7 +1064,11 @@ hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream)
     hipStream_t s = S(stream);
     const bool graphs = h->use_graphs && h->pt_every <= 1;
     int done = 0;
-    if (graphs) {
+    if (n_sweeps > 0 && overlap_ok(h)) {
+        hsg_status st = overlapped_sweeps(h, n_sweeps, s);
+        if (st != HSG_OK) return st;
+        done = n_sweeps;
+    } else if (graphs) {
         while (n_sweeps - done >= kGraphSweeps) {
             hsg_status st = launch_graph(h, 1, s);
             if (st != HSG_OK) return st;
@@ -1181,7 +1325,9 @@ hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_cal
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
     if (sweep_counter > 0xFFFFFFFFull || pt_calls > 0xFFFFFFFFull)
         return fail(HSG_E_SIZE, "counters are limited to 32 bits");
-    const hipError_t e = hsg::launch_set_u32(dev_counter(h), (uint32_t)sweep_counter, S(stream));
+    hipError_t e = hsg::launch_set_u32(reinterpret_cast<uint32_t *>(h->state), (uint32_t)sweep_counter, S(stream));
+    if (e == hipSuccess)
+        e = hsg::launch_set_u32(reinterpret_cast<uint32_t *>(h->state) + 1, (uint32_t)sweep_counter, S(stream));
     if (e != hipSuccess) return hip_fail(e, "set_state");
     h->t = sweep_counter;
     h->pt_calls = pt_calls;
@@ -1207,6 +1353,14 @@ hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
     return HSG_OK;
 }
 
+hsg_status hsg_set_overlap(hsg_lattice *h, int32_t enable)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (enable != 0 && enable != 1) return fail(HSG_E_INVALID, "overlap = %d, need 0 or 1", enable);
+    h->overlap = enable == 1;
+    return HSG_OK;
+}
+
 hsg_status hsg_set_math(hsg_lattice *h, int32_t mode)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
@@ -1226,6 +1380,7 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
     const uint64_t need = (uint64_t)n_sweeps + 1;  // trial sweeps per candidate
     struct Cand {
         int32_t variant, slots;
+        bool overlap;
     };
     bool any_stream = false, any_pair = false, any_gather = false;
     int max_spp = 1;
@@ -1243,9 +1398,10 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
     std::vector<Cand> cands;
     auto add = [&](int32_t v, bool gather_used) {
         if (gather_used)
-            for (int32_t c : slot_opts) cands.push_back({v, c});
+            for (int32_t c : slot_opts) cands.push_back({v, c, false});
         else
-            cands.push_back({v, 0});
+            cands.push_back({v, 0, false});
+        if (any_stream) cands.push_back({v, gather_used ? slot_opts.back() : 0, true});
     };
     if (any_pair) {
         const int32_t v0 = h->kernel_variant;
@@ -1265,6 +1421,7 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
     const uint64_t t0 = h->t, pt0 = h->pt_calls;
     const bool have_e0 = h->have_energies;
     const int32_t var0 = h->kernel_variant, slots0 = h->slots_per_item;
+    const bool ov0 = h->overlap;
     hipError_t e = hipSuccess;
     if (d_backup != nullptr)
         e = hipMemcpyAsync(d_backup, h->state, h->lay.sz.state_bytes, hipMemcpyDeviceToDevice, s);
@@ -1274,11 +1431,13 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
         if (e == hipSuccess) e = hipEventCreate(&x);
     hsg_status st = e == hipSuccess ? HSG_OK : hip_fail(e, "autotune: event");
     float best = 0.0f;
-    Cand pick{var0, slots0};
+    Cand pick{var0, slots0, ov0};
     bool have_pick = false;
     for (size_t k = 0; k < cands.size() && st == HSG_OK; ++k) {
         h->kernel_variant = cands[k].variant;
         h->slots_per_item = cands[k].slots;
+        h->overlap = cands[k].overlap;
+        if (h->overlap && !overlap_ok(h)) continue;  // this choice would run as the one without overlap
         drop_graphs(h);
         st = hsg_sweep(h, 1, stream);  // warm-up (and graph capture)
         if (st != HSG_OK) break;
@@ -1303,6 +1462,7 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
         if (x) (void)hipEventDestroy(x);
     h->kernel_variant = st == HSG_OK ? pick.variant : var0;
     h->slots_per_item = st == HSG_OK ? pick.slots : slots0;
+    h->overlap = st == HSG_OK ? pick.overlap : ov0;
     drop_graphs(h);
     if (d_backup != nullptr) {
         e = hipMemcpyAsync(h->state, d_backup, h->lay.sz.state_bytes, hipMemcpyDeviceToDevice, s);
@@ -1435,6 +1595,9 @@ void hsg_destroy(hsg_lattice *h)
     if (h == nullptr) return;
     drop_graphs(h);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    if (h->stream2) (void)hipStreamDestroy(h->stream2);
+    for (auto &x : h->ev)
+        if (x) (void)hipEventDestroy(x);
     delete h;
 }
 

@@ -198,6 +198,7 @@ hipError_t launch_invert_maps(const int32_t *slot_at_temp, int32_t *temp_of_slot
 // Advance the device sweep counter by one (end of a sweep).
 hipError_t launch_advance(uint32_t *tptr, hipStream_t s);
 hipError_t launch_set_u32(uint32_t *ptr, uint32_t value, hipStream_t s);
+hipError_t launch_copy_u32(const uint32_t *src, uint32_t *dst, hipStream_t s);
 hipError_t launch_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n,
                          hipStream_t s);
 hipError_t launch_hw_math(const float *x, float *out, int64_t n, hipStream_t s);

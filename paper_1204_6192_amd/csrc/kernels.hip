@@ -903,6 +903,17 @@ hipError_t launch_set_u32(uint32_t *ptr, uint32_t value, hipStream_t s)
     return hipGetLastError();
 }
 
+__global__ void k_copy_u32(const uint32_t *src, uint32_t *dst)
+{
+    if (threadIdx.x == 0) *dst = *src;
+}
+
+hipError_t launch_copy_u32(const uint32_t *src, uint32_t *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- debug
 __global__ __launch_bounds__(256) void k_philox(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int64_t n)
 {

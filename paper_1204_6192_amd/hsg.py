@@ -91,6 +91,7 @@ _SIG = {
     "hsg_set_state": [_vp, _u64, _u64, _vp],
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
+    "hsg_set_overlap": [_vp, _i32],
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
     "hsg_measure_pair_overlaps": [_vp, _vp, _vp],
     "hsg_measure_kmodes": [_vp, _vp, _vp],
@@ -302,6 +303,10 @@ class Lattice:
 
     def set_kernel(self, variant: int) -> None:
         check(lib.hsg_set_kernel(self.h, int(variant)))
+
+    def set_overlap(self, enable: bool) -> None:
+        """Sweeps of the two halves of the samples on two streams (1) or one (0, default)."""
+        check(lib.hsg_set_overlap(self.h, int(bool(enable))))
 
     def autotune(self, n_sweeps: int = 4, restore: bool = True):
         """Time each kernel variant over n_sweeps real sweeps and keep the fastest.

@@ -826,6 +826,48 @@ def test_or_pairs_two_by_two_bit_identical(hsg, storage):
         assert torch.equal(a, b)
 
 
+@pytest.mark.parametrize("n_hb,n_or,pt_every", [(1, 4, 1), (2, 3, 2), (1, 0, 1)])
+def test_overlapped_sweeps_bit_identical(hsg, n_hb, n_or, pt_every):
+    """Sweeps of the two halves of the samples on two streams (each half with its
+    own device counter, one half's heat bath beside the other half's
+    over-relaxation) against one stream: spins, temperature maps, energies,
+    tempering acceptances, run statistics and the counter agree bit for bit.
+    Odd and even sample counts (L = 8 with three samples splits 1 + 2), the
+    fused pair and two-pair kernels, a single-pass lattice (L = 36), heat-bath
+    rounds, an odd over-relaxation count, tempering every other sweep and no
+    over-relaxation at all (the energy from the heat bath); one-stream sweeps
+    between overlapped ones."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 65))
+    groups, uid = [], 0
+    for L, D, T in ((8, 3, 4), (16, 2, 3), (36, 2, 2)):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.3, T),
+                                        sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 65
+    res = []
+    for overlap in (0, 1):
+        lat = _lat(hsg, groups, seed, n_hb=n_hb, n_or=n_or, pt_every=pt_every)
+        lat.set_overlap(overlap)
+        lat.set_stats(True)
+        lat.sweep(3)
+        lat.set_overlap(0)  # one stream in between: only the first counter advances
+        lat.sweep(2)
+        lat.set_overlap(overlap)
+        lat.sweep(1)
+        sums, trips, n = lat.get_stats()
+        res.append((lat.get_spins().cpu(), lat.get_temp_map().cpu(), lat.get_energies().cpu(),
+                    lat.get_pt_accepts().cpu(), sums.cpu(), trips.cpu(), n, lat.get_state()))
+        lat.pt_exchange()  # the standalone pass reads the first counter after the join
+        res[-1] += (lat.get_temp_map().cpu(),)
+        lat.close()
+    a, b = res
+    for x, y in zip(a, b):
+        if isinstance(x, torch.Tensor):
+            assert torch.equal(x, y)
+        else:
+            assert x == y
+
+
 def test_autotune_keeps_the_chain(hsg):
     """The autotuner's trial sweeps are ordinary sweeps. With a backup buffer the
     state (spins, maps, energies, counters) comes back unchanged and the chain
