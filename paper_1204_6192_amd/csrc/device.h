@@ -74,6 +74,38 @@ __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(
 __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 
+// a / b within one ulp: the hardware reciprocal refined by one Newton step,
+// then one correction of the quotient from its exact residual a - b q (an fma);
+// Markstein's scheme (IA-64 and Elementary Functions, 2000). About 6
+// instructions against about 10 for the correctly rounded division. b must be
+// a normal number.
+__device__ __forceinline__ float div_nr(float a, float b)
+{
+    float r = __builtin_amdgcn_rcpf(b);
+    r = fmaf(fmaf(-b, r, 1.0f), r, r);
+    const float q = a * r;
+    return fmaf(fmaf(-b, q, a), r, q);
+}
+
+// sqrt(x) and 1 / sqrt(x) for x > 0, each within one ulp: the hardware
+// reciprocal square root y, then one coupled Newton step on g = x y and
+// h = y / 2 and one residual correction of g (Markstein, as above). Inputs
+// below 2^-64 are scaled by 2^64 first, since the hardware instruction
+// flushes subnormal inputs.
+__device__ __forceinline__ float sqrt_rsqrt_nr(float x, float &rs)
+{
+    const bool tiny = x < 0x1p-64f;
+    const float xs = tiny ? x * 0x1p64f : x;
+    const float y = __builtin_amdgcn_rsqf(xs);
+    float g = xs * y, h = 0.5f * y;
+    const float r = fmaf(-g, h, 0.5f);
+    g = fmaf(g, r, g);
+    h = fmaf(h, r, h);
+    g = fmaf(fmaf(-g, g, xs), h, g);
+    rs = tiny ? (2.0f * h) * 0x1p32f : 2.0f * h;
+    return tiny ? g * 0x1p-32f : g;
+}
+
 // Error-free sum a + b = s + e (Knuth's TwoSum).
 __device__ __forceinline__ float two_sum(float a, float b, float &e)
 {
@@ -131,12 +163,14 @@ __device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
 // into O(1) jumps of the new spin); 1 + n_z is formed without cancellation for
 // n_z < 0. Zero field: uniform, z frame.
 //
-// HW = false uses the correctly rounded square root and division (except in
-// the rounding correction of ln X above) and the library sincospi. HW = true (an opt-in variant) takes the field's length and
-// direction from the hardware reciprocal square root, the divisions from the
-// hardware reciprocal (1 ulp) and the azimuth from the hardware sin/cos of
-// revolutions (absolute error about 1.2e-7, one float32 spacing at 1). Both
-// keep the library exp and log.
+// HW = false (the default) takes square roots and divisions within one ulp
+// from the hardware reciprocal (square root) refined by Newton steps
+// (sqrt_rsqrt_nr, div_nr) and the azimuth from the library sincospi. HW = true
+// (an opt-in variant) takes the field's length and direction from the bare
+// hardware reciprocal square root, the divisions from the bare hardware
+// reciprocal (1 ulp each, but the products they feed round again) and the
+// azimuth from the hardware sin/cos of revolutions (absolute error about
+// 1.2e-7, one float32 spacing at 1). Both keep the library exp and log.
 template <bool HW>
 __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t w1)
 {
@@ -148,8 +182,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         rs = hw_rsq(hh);  // infinite for a zero field, then unused
         hn = hh * rs;
     } else {
-        hn = sqrtf(hh);
-        rs = 1.0f / hn;
+        hn = hh > 0.0f ? sqrt_rsqrt_nr(hh, rs) : 0.0f;
     }
     const float kappa = beta * hn;
     v3 n;
@@ -177,13 +210,13 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         const float xo = fmaf(omu, E, u1);                               // x
         upper = xo * xo >= E;  // x >= e^{-kappa}, i.e. c >= 0
         // c < 0 needs kappa < 17 (u >= 2^-24), where E is a normal number
-        const float yb = u1 * (HW ? -A * hw_rcp(E) : -A / E);
+        const float yb = u1 * (HW ? -A * hw_rcp(E) : div_nr(-A, E));
         const float X = upper ? xo : 1.0f + yb;
         const float Y = upper ? omu * A : yb;
         const float d = (1.0f - X) + Y;
         // (a relative correction of order 1e-7: the hardware reciprocal's 1 ulp is far below float32 spacing)
         const float corr = (X >= 0.5f && X <= 2.0f) ? d * hw_rcp(X) : 0.0f;
-        const float t = HW ? (logf(X) + corr) * hw_rcp(kappa) : (logf(X) + corr) / kappa;
+        const float t = HW ? (logf(X) + corr) * hw_rcp(kappa) : div_nr(logf(X) + corr, kappa);
         omc = fminf(2.0f, fmaxf(0.0f, upper ? -t : 2.0f - t));
         opc = fminf(2.0f, fmaxf(0.0f, upper ? 2.0f + t : t));
     }
@@ -201,7 +234,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         if constexpr (HW)
             a = num * hw_rcp(den);
         else
-            a = num / den;
+            a = div_nr(num, den);
         const float b = -n.x * n.y * a;
         e1 = v3{fmaf(-n.x * n.x, a, 1.0f), b, -n.x};
         e2 = v3{b, fmaf(-n.y * n.y, a, 1.0f), -n.y};
@@ -212,7 +245,9 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         sp = hw_sin_rev(u2);
         cp = hw_cos_rev(u2);
     } else {
-        st = sqrtf(omc * opc);
+        const float p = omc * opc;
+        float unused;
+        st = p > 0.0f ? sqrt_rsqrt_nr(p, unused) : 0.0f;
         sincospif(2.0f * u2, &sp, &cp);
     }
     const float ta = st * cp, tb = st * sp;
