@@ -933,12 +933,16 @@ __global__ __launch_bounds__(256) void k_hw_math(const float *x, float *out, int
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float v = x[g];
-    out[6 * g + 0] = hw_sin_rev(v);
-    out[6 * g + 1] = hw_cos_rev(v);
-    out[6 * g + 2] = hw_log(v);
-    out[6 * g + 3] = hw_exp(-v);
-    out[6 * g + 4] = hw_rcp(v);
-    out[6 * g + 5] = hw_rsq(v);
+    float* o = out + 10 * g;
+    o[0] = hw_sin_rev(v);
+    o[1] = hw_cos_rev(v);
+    o[2] = hw_log(v);
+    o[3] = hw_exp(-v);
+    o[4] = hw_rcp(v);
+    o[5] = hw_rsq(v);
+    sincos_2pi(v, o[6], o[7]);
+    o[8] = v > 0.0f ? sqrt_rsqrt_nr(v, o[9]) : 0.0f;
+    if (!(v > 0.0f)) o[9] = 0.0f;
 }
 
 hipError_t launch_hw_math(const float *x, float *out, int64_t n, hipStream_t s)

@@ -996,3 +996,34 @@ def test_hardware_transcendentals_accuracy(hsg):
     assert err_log < 2e-6
     assert err_exp < 1e-5
     assert err_rcp < 3e-7 and err_rsq < 3e-7
+
+
+def test_heat_bath_refined_math_accuracy(hsg):
+    """The default heat bath's own routines against float64: the polynomial
+    sin(2 pi u), cos(2 pi u) on the 2^-24 grid of the uniforms (every quarter
+    and eighth turn and their neighbours, and random points) within 7e-8
+    absolute, with sin^2 + cos^2 within 2e-7 of 1; the refined square root
+    within one ulp and its reciprocal within 1.5 ulp, over normal and
+    subnormal inputs (the subnormal ones take the scaled path)."""
+    rng = np.random.default_rng(81)
+    edges = (np.arange(0, 9)[:, None] * 2 ** 21 + np.arange(-3, 4)[None, :]).ravel()
+    k = np.unique(np.clip(np.concatenate([edges, rng.integers(1, 2 ** 24 + 1, 1 << 21)]), 1, 2 ** 24))
+    u = (k * 2.0 ** -24).astype(np.float32)
+    r = hsg.debug_hw_math(u).astype(np.float64)
+    u64 = u.astype(np.float64)
+    err_s = np.abs(r[:, 6] - np.sin(2 * np.pi * u64)).max()
+    err_c = np.abs(r[:, 7] - np.cos(2 * np.pi * u64)).max()
+    norm = np.abs(r[:, 6] ** 2 + r[:, 7] ** 2 - 1.0).max()
+    x = np.concatenate([np.exp(rng.uniform(np.log(1e-12), np.log(1e4), 1 << 20)),
+                        np.exp(rng.uniform(np.log(1e-44), np.log(1e-19), 1 << 16))]).astype(np.float32)
+    x = x[x > 0]
+    q = hsg.debug_hw_math(x).astype(np.float64)
+    ref = np.sqrt(x.astype(np.float64))
+    ulp_sqrt = (np.abs(q[:, 8] - ref) / np.spacing(ref.astype(np.float32))).max()
+    ulp_rsq = (np.abs(q[:, 9] - 1.0 / ref) / np.spacing((1.0 / ref).astype(np.float32))).max()
+    exact = np.mean(q[:, 8] == np.sqrt(x))
+    print(f"polynomial sin {err_s:.2e} cos {err_c:.2e} |(s,c)|^2 - 1 {norm:.2e}; sqrt {ulp_sqrt:.2f} ulp "
+          f"({exact:.6f} correctly rounded), 1/sqrt {ulp_rsq:.2f} ulp", flush=True)
+    assert err_s <= 7e-8 and err_c <= 7e-8
+    assert norm <= 2e-7
+    assert ulp_sqrt <= 1.0 and ulp_rsq <= 1.5
