@@ -247,10 +247,11 @@ hsg_status hsg_set_overlap(hsg_lattice *h, int32_t enable);
 /* Arithmetic of the heat-bath draw (Eq. (2)). 0 (default): square roots and
  * divisions from the hardware reciprocal (square root) refined by Newton steps
  * (within one ulp, almost always correctly rounded), the azimuth's sine and
- * cosine from polynomials (absolute error at most 7e-8), library log and exp.
+ * cosine from polynomials (absolute error at most 7e-8); in both modes e^z and
+ * ln X from the hardware 2^x and log2 with extended-precision scaling.
  * 1: the field's length, direction and the divisions from the bare hardware
  * reciprocal square root and reciprocal (1 ulp), the azimuth from the hardware
- * sin/cos (absolute error about 1.2e-7); log and exp unchanged. Mode 1
+ * sin/cos (absolute error about 1.2e-7). Mode 1
  * changes the trajectory at the float32 rounding level and is the faster
  * choice; over-relaxation is the same in both. HSG_E_INVALID for a NULL
  * handle or a mode other than 0 and 1. */
@@ -339,11 +340,12 @@ hsg_status hsg_debug_philox(const uint32_t *d_ctr, const uint32_t *d_key, uint32
                             int64_t n, hsg_stream_t stream);
 
 /* Test hook: the hardware transcendentals and the refined routines the
- * kernels use, for x = d_x[i]: d_out[10 i ..] = hardware sin(2 pi x),
+ * kernels use, for x = d_x[i]: d_out[12 i ..] = hardware sin(2 pi x),
  * cos(2 pi x), ln x, e^-x, 1/x, 1/sqrt(x); then the default heat bath's
- * polynomial sin(2 pi x), cos(2 pi x) (x on the 2^-24 grid) and its refined
- * sqrt(x), 1/sqrt(x) (0, 0 for x <= 0) (device arrays, n >= 0), so that their
- * accuracy can be checked against float64. HSG_E_INVALID for n < 0 or a NULL
+ * polynomial sin(2 pi x), cos(2 pi x) (x on the 2^-24 grid), its refined
+ * sqrt(x), 1/sqrt(x) (0, 0 for x <= 0), and the heat bath's e^-x (0 for
+ * x < 0) and ln x (0 below the smallest normal number) (device arrays,
+ * n >= 0), so that their accuracy can be checked against float64. HSG_E_INVALID for n < 0 or a NULL
  * array with n > 0. */
 hsg_status hsg_debug_hw_math(const float *d_x, float *d_out, int64_t n, hsg_stream_t stream);
 

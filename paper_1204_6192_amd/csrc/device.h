@@ -92,12 +92,13 @@ __device__ __forceinline__ float div_nr(float a, float b)
 
 // sqrt(x) and 1 / sqrt(x) for x > 0, each within one ulp: the hardware
 // reciprocal square root y, then one coupled Newton step on g = x y and
-// h = y / 2 and one residual correction of g (Markstein, as above). Inputs
-// below 2^-64 are scaled by 2^64 first, since the hardware instruction
-// flushes subnormal inputs.
+// h = y / 2 and one residual correction of g (Markstein, as above). With
+// SCALE, inputs below 2^-64 are scaled by 2^64 first, since the hardware
+// instruction flushes subnormal inputs; without it x must be at least 2^-64.
+template <bool SCALE = true>
 __device__ __forceinline__ float sqrt_rsqrt_nr(float x, float &rs)
 {
-    const bool tiny = x < 0x1p-64f;
+    const bool tiny = SCALE && x < 0x1p-64f;
     const float xs = tiny ? x * 0x1p64f : x;
     const float y = __builtin_amdgcn_rsqf(xs);
     float g = xs * y, h = 0.5f * y;
@@ -133,6 +134,30 @@ __device__ __forceinline__ void sincos_2pi(float u, float &s, float &c)
     const float so = (n & 1) ? cr : sr, co = (n & 1) ? sr : cr;
     s = __uint_as_float(__float_as_uint(so) ^ ((uint32_t)(n & 2) << 30));
     c = __uint_as_float(__float_as_uint(co) ^ ((uint32_t)((n + 1) & 2) << 30));
+}
+
+// e^z for finite z <= 0: z log2(e) as the unevaluated sum of p = fl(z H) and
+// its residual (the exact fma error plus z L; log2(e) = H + L to 2^-50),
+// split into an integer n and f = (p - n) + residual with |f| <= 1/2 + 2^-20,
+// 2^f from the hardware (1 ulp on [1/sqrt 2, sqrt 2]) and the exact scaling by
+// 2^n, which rounds correctly into the subnormal range and to zero.
+__device__ __forceinline__ float exp_nonpos(float z)
+{
+    constexpr float H = 0x1.715476p+0f, L = 0x1.4ae0c0p-26f;
+    const float p = z * H;
+    const float pe = fmaf(z, L, fmaf(z, H, -p));
+    const float n = fmaxf(__builtin_rintf(p), -256.0f);
+    return ldexpf(__builtin_amdgcn_exp2f((p - n) + pe), (int)n);
+}
+
+// ln x for finite normal x > 0: the hardware log2 (about 1 ulp), times ln 2
+// as the unevaluated sum H + L (to 2^-53) with the product's exact residual.
+__device__ __forceinline__ float log_normal(float x)
+{
+    constexpr float H = 0x1.62e430p-1f, L = -0x1.05c610p-29f;
+    const float l = __builtin_amdgcn_logf(x);
+    const float p = l * H;
+    return p + fmaf(l, L, fmaf(l, H, -p));
 }
 
 // Error-free sum a + b = s + e (Knuth's TwoSum).
@@ -199,7 +224,8 @@ __device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
 // hardware reciprocal square root, the divisions from the bare hardware
 // reciprocal (1 ulp each, but the products they feed round again) and the
 // azimuth from the hardware sin/cos of revolutions (absolute error about
-// 1.2e-7, one float32 spacing at 1). Both keep the library exp and log.
+// 1.2e-7, one float32 spacing at 1). Both take e^z and ln X from the hardware
+// 2^x and log2 with extended-precision scaling (exp_nonpos, log_normal).
 template <bool HW>
 __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t w1)
 {
@@ -226,7 +252,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         n = scale3(h, rs);
         const float omu = 1.0f - u1;  // exact on the 2^-24 grid
         const float z = -2.0f * kappa;
-        const float E = expf(z);  // 0 past underflow
+        const float E = exp_nonpos(z);  // 0 past underflow
         float p = 2.7557319e-6f;  // 1/9!, then Horner down to 1/2!
         p = fmaf(z, p, 2.4801588e-5f);
         p = fmaf(z, p, 1.9841270e-4f);
@@ -245,7 +271,9 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         const float d = (1.0f - X) + Y;
         // (a relative correction of order 1e-7: the hardware reciprocal's 1 ulp is far below float32 spacing)
         const float corr = (X >= 0.5f && X <= 2.0f) ? d * hw_rcp(X) : 0.0f;
-        const float t = HW ? (logf(X) + corr) * hw_rcp(kappa) : div_nr(logf(X) + corr, kappa);
+        // X >= u1 >= 2^-24 (upper) or X >= 1: a normal number
+        const float lx = log_normal(X);
+        const float t = HW ? (lx + corr) * hw_rcp(kappa) : div_nr(lx + corr, kappa);
         omc = fminf(2.0f, fmaxf(0.0f, upper ? -t : 2.0f - t));
         opc = fminf(2.0f, fmaxf(0.0f, upper ? 2.0f + t : t));
     }
@@ -276,7 +304,9 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
     } else {
         const float p = omc * opc;
         float unused;
-        st = p > 0.0f ? sqrt_rsqrt_nr(p, unused) : 0.0f;
+        // a positive p is at least about 2^-24 / kappa: 1 - c and 1 + c are
+        // either 0 or at least (1 - e^{-2 kappa}) 2^-24 / kappa; far above 2^-64
+        st = p > 0.0f ? sqrt_rsqrt_nr<false>(p, unused) : 0.0f;
         sincos_2pi(u2, sp, cp);
     }
     const float ta = st * cp, tb = st * sp;

@@ -933,7 +933,7 @@ __global__ __launch_bounds__(256) void k_hw_math(const float *x, float *out, int
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= n) return;
     const float v = x[g];
-    float* o = out + 10 * g;
+    float *o = out + 12 * g;
     o[0] = hw_sin_rev(v);
     o[1] = hw_cos_rev(v);
     o[2] = hw_log(v);
@@ -943,6 +943,8 @@ __global__ __launch_bounds__(256) void k_hw_math(const float *x, float *out, int
     sincos_2pi(v, o[6], o[7]);
     o[8] = v > 0.0f ? sqrt_rsqrt_nr(v, o[9]) : 0.0f;
     if (!(v > 0.0f)) o[9] = 0.0f;
+    o[10] = v >= 0.0f ? exp_nonpos(-v) : 0.0f;
+    o[11] = v >= 0x1p-126f ? log_normal(v) : 0.0f;
 }
 
 hipError_t launch_hw_math(const float *x, float *out, int64_t n, hipStream_t s)

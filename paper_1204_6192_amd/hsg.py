@@ -383,11 +383,12 @@ def debug_philox(ctr, key):
 def debug_hw_math(x):
     """Hardware sin(2 pi x), cos(2 pi x), ln x, e^-x, 1/x, 1/sqrt(x), then the
     polynomial sin(2 pi x), cos(2 pi x) and the refined sqrt(x), 1/sqrt(x) of the
-    default heat bath, on the device: an (n, 10) array."""
+    default heat bath, and the heat bath's e^-x and ln x, on the device: an
+    (n, 12) array."""
     import torch
     x = np.ascontiguousarray(x, dtype=np.float32)
     dx = torch.from_numpy(x).cuda()
-    out = torch.empty((x.size, 10), dtype=torch.float32, device="cuda")
+    out = torch.empty((x.size, 12), dtype=torch.float32, device="cuda")
     check(lib.hsg_debug_hw_math(_ptr(dx), _ptr(out), x.size, _stream(None)))
     torch.cuda.synchronize()
     return out.cpu().numpy()

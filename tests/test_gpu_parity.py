@@ -999,12 +999,14 @@ def test_hardware_transcendentals_accuracy(hsg):
 
 
 def test_heat_bath_refined_math_accuracy(hsg):
-    """The default heat bath's own routines against float64: the polynomial
+    """The heat bath's own routines against float64: the polynomial
     sin(2 pi u), cos(2 pi u) on the 2^-24 grid of the uniforms (every quarter
     and eighth turn and their neighbours, and random points) within 7e-8
     absolute, with sin^2 + cos^2 within 2e-7 of 1; the refined square root
     within one ulp and its reciprocal within 1.5 ulp, over normal and
-    subnormal inputs (the subnormal ones take the scaled path)."""
+    subnormal inputs (the subnormal ones take the scaled path); e^-x and ln x
+    within 2.5e-7 relative over the ranges the draw uses (e^-x also where it
+    underflows into subnormal numbers, to the last bit)."""
     rng = np.random.default_rng(81)
     edges = (np.arange(0, 9)[:, None] * 2 ** 21 + np.arange(-3, 4)[None, :]).ravel()
     k = np.unique(np.clip(np.concatenate([edges, rng.integers(1, 2 ** 24 + 1, 1 << 21)]), 1, 2 ** 24))
@@ -1027,3 +1029,23 @@ def test_heat_bath_refined_math_accuracy(hsg):
     assert err_s <= 7e-8 and err_c <= 7e-8
     assert norm <= 2e-7
     assert ulp_sqrt <= 1.0 and ulp_rsq <= 1.5
+    # e^-x on the heat bath's exponent range (dense below 0.35, where the
+    # Taylor form takes over, and out to the subnormal results past 87)
+    x = np.concatenate([rng.uniform(0, 0.35, 1 << 18), rng.uniform(0, 110, 1 << 20),
+                        np.arange(0, 4096) * 2.0 ** -20]).astype(np.float32)
+    e = hsg.debug_hw_math(x)[:, 10].astype(np.float64)
+    ref = np.exp(-x.astype(np.float64))
+    normal = ref >= 2.0 ** -126
+    rel_exp = (np.abs(e - ref) / ref)[normal].max()
+    abs_sub = np.abs(e - ref)[~normal].max()
+    # ln x over the heat bath's argument range [2^-24, 2^50] and next to 1
+    k = np.arange(1, 1 << 14)
+    v = np.concatenate([np.exp(rng.uniform(np.log(2.0 ** -24), np.log(2.0 ** 50), 1 << 20)),
+                        1.0 - k * 2.0 ** -24, 1.0 + k * 2.0 ** -23]).astype(np.float32)
+    lv = hsg.debug_hw_math(v)[:, 11].astype(np.float64)
+    lref = np.log(v.astype(np.float64))
+    nz = lref != 0
+    rel_log = (np.abs(lv - lref)[nz] / np.abs(lref[nz])).max()
+    print(f"e^-x rel {rel_exp:.2e} (subnormal abs {abs_sub:.2e}); ln x rel {rel_log:.2e}", flush=True)
+    assert rel_exp <= 2.5e-7 and abs_sub <= 2.0 ** -149
+    assert rel_log <= 2.5e-7 and np.all(lv[~nz] == 0.0)
