@@ -761,7 +761,10 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
     using I3 = std::integral_constant<int, 3>;
     using G = std::false_type;
     using S = std::true_type;
-    // Steps past n_steps idle (every stage done), so the count rounds up to 4.
+    // n_steps = L + 6 >= 10, so the first two groups of four are whole. The
+    // last group stops at n_steps (the test is uniform over the work-group, so
+    // every thread meets the same barriers); the spin loads that the last step
+    // issued for the next one are dropped.
     int z = 0;
     for (; z < 8 && z < n_steps; z += 4) {
         step(I0{}, G{}, z);
@@ -777,8 +780,11 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
     }
     for (; z < n_steps; z += 4) {
         step(I0{}, G{}, z);
+        if (z + 1 >= n_steps) break;
         step(I1{}, G{}, z + 1);
+        if (z + 2 >= n_steps) break;
         step(I2{}, G{}, z + 2);
+        if (z + 3 >= n_steps) break;
         step(I3{}, G{}, z + 3);
     }
 
