@@ -151,15 +151,16 @@ def copy_bandwidth(torch, mib=1024, reps=10):
     return 2 * n / t / 1e9
 
 
-def measured_traffic(build_id, workload):
+def measured_traffic(build_id, workload, storage, kernel):
     """HBM bytes per launch of the dominant kernel from the hardware counters, as
     recorded in a profile summary under profiles/ by a line
 
-        traffic: build_id=<id> workload=<name> bytes_per_launch=<B> ...
+        traffic: build_id=<id> workload=<name> storage=<codec> kernel=<name> bytes_per_launch=<B> ...
 
-    (FETCH_SIZE and WRITE_SIZE of the same build and workload, each scaled by
-    what it reads for a plain copy of known size). None when no summary was
-    taken with this build, since counters of other code say nothing about it."""
+    (FETCH_SIZE and WRITE_SIZE of the same build, workload, spin storage and
+    kernel, each scaled by what it reads for a plain copy of known size). None
+    when no summary was taken with this build and launch, since counters of
+    other code say nothing about it."""
     import glob
     for fn in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(fn) as f:
@@ -167,7 +168,8 @@ def measured_traffic(build_id, workload):
                 if not line.startswith("traffic:"):
                     continue
                 kv = dict(tok.split("=", 1) for tok in line[len("traffic:"):].split() if "=" in tok)
-                if kv.get("build_id") == build_id and kv.get("workload") == workload:
+                if (kv.get("build_id") == build_id and kv.get("workload") == workload
+                        and kv.get("storage") == storage and kv.get("kernel") == kernel):
                     return float(kv["bytes_per_launch"]), os.path.relpath(fn, ROOT)
     return None, None
 
@@ -240,7 +242,12 @@ def main():
                          "(default: 1 for the large workload, else never)")
     ap.add_argument("--two-streams", type=int, default=None, choices=[0, 1],
                     help="sweep the two halves of the samples on two streams, one half's heat bath "
-                         "beside the other's over-relaxation (default: 1 for the uneven workload, else 0)")
+                         "beside the other's over-relaxation (default: the autotuner's choice; with "
+                         "--autotune 0, 1 for the uneven workload, else 0)")
+    ap.add_argument("--autotune", type=int, default=8,
+                    help="before the timed run, time every launch choice over this many sweeps "
+                         "(hsg_autotune, the state restored afterwards) and keep the fastest; "
+                         "0 = the library's default choice")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=40)
@@ -274,15 +281,22 @@ def main():
         f"storage {inst.storage}; inputs in {time.perf_counter() - t_gen:.1f} s")
     lat = hsg.Lattice(inst.groups, storage=inst.storage, n_hb=inst.n_hb, n_or=inst.n_or,
                       pt_every=inst.pt_every, seed=inst.seed)
-    two_streams = args.two_streams
-    if two_streams is None:
-        two_streams = 1 if args.config == "uneven" else 0
-    lat.set_overlap(two_streams)
     n_hit = 1
     if args.tiles:
         ty, tz, n_hit = (int(v) for v in args.tiles.split(","))
         lat.set_chain(1, ty, tz, n_hit)
         log(f"tile-local chain: tiles of L x {ty or 'L'} x {tz or 'L'}, {n_hit} repetition(s) per visit")
+    if args.autotune > 0 and not args.tiles:
+        t_tune = time.perf_counter()
+        lat.autotune(n_sweeps=args.autotune, restore=True)
+        log(f"autotune over {args.autotune} sweeps per choice: {time.perf_counter() - t_tune:.1f} s")
+    if args.two_streams is not None:
+        lat.set_overlap(args.two_streams)
+    elif args.autotune <= 0 and args.config == "uneven":
+        lat.set_overlap(1)
+    variant, slots, two_streams = lat.get_tuning()
+    log(f"launch choice: kernel variant {variant} (0 = automatic, the two-pair z-march), slots per item "
+        f"{slots}, two streams {two_streams}")
     torch.cuda.synchronize()
 
     if args.calibrate_copy_mib > 0:
@@ -317,7 +331,7 @@ def main():
 
     # the kernels of a sweep: heat-bath pair, over-relaxation pair, and two
     # over-relaxation pairs in one z-march where every lattice fuses them
-    quad = inst.n_or >= 2 and all(fused(g) for g in inst.groups)
+    quad = inst.n_or >= 2 and all(fused(g) for g in inst.groups) and variant in (0, 4)
     t_or = time_kernel(lat, 1, args.kernel_launches, torch)
     t_hb = time_kernel(lat, 0, max(4, args.kernel_launches // 4), torch)
     t_quad = time_kernel(lat, 3, max(4, args.kernel_launches // 2), torch) if quad else None
@@ -341,7 +355,8 @@ def main():
 
     analysis = time_analysis(lat, inst, torch)
     log("analysis: " + ", ".join(f"{k} {v:.1f}" for k, v in analysis.items()))
-    traffic, traffic_src = measured_traffic(hsg.build_id(), args.config)
+    dominant = "k_or_quad_stream" if quad else "k_pair_stream"
+    traffic, traffic_src = measured_traffic(hsg.build_id(), args.config, inst.storage, dominant)
     copy_gbs = copy_bandwidth(torch)
     log(f"device copy: {copy_gbs:.0f} GB/s read+write; OR pair at {gbs_or / copy_gbs:.1%} of it")
     cpu = None
@@ -361,7 +376,9 @@ def main():
                     + (f" + overlap every {overlap_every}" if overlap_every else ""),
            "field_amp": None if inst.groups[0].H is None else float(
                args.field_amp if args.field_amp is not None else 0.1),
-           "two_streams": bool(two_streams), "spins": lat.n_spins, "replicas": lat.n_replicas}
+           "two_streams": bool(two_streams), "kernel_variant": variant, "slots_per_item": slots,
+           "autotune_sweeps": args.autotune if not args.tiles else 0,
+           "spins": lat.n_spins, "replicas": lat.n_replicas}
     out = {
         "metric": METRIC, "value": ns_update, "unit": "ns/update", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,

@@ -244,6 +244,12 @@ hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
  * Returns HSG_E_INVALID for a NULL handle or a value other than 0 and 1. */
 hsg_status hsg_set_overlap(hsg_lattice *h, int32_t enable);
 
+/* The launch choices in force (as set by hsg_set_kernel, hsg_set_tuning,
+ * hsg_set_overlap or chosen by hsg_autotune): kernel variant (0 = automatic),
+ * slots per work item (0 = automatic) and overlapped sweeps (0 or 1), each
+ * written to its non-NULL host output. HSG_E_INVALID for a NULL handle. */
+hsg_status hsg_get_tuning(const hsg_lattice *h, int32_t *variant, int32_t *slots_per_item, int32_t *overlap);
+
 /* Arithmetic of the heat-bath draw (Eq. (2)). 0 (default): square roots and
  * divisions from the hardware reciprocal (square root) refined by Newton steps
  * (within one ulp, almost always correctly rounded), the azimuth's sine and
@@ -282,10 +288,13 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
  * each distinct kernel variant of hsg_set_kernel (and, where lattices use the
  * gather kernel, 2, 4, 8 or 16 slots per work item; where hsg_set_overlap
  * applies, each z-march variant also with overlapped sweeps) with HIP events
- * after one warm-up sweep each, and keeps the fastest (the overlap choice is
- * kept too and is not reported). Every variant computes the same
+ * after ten warm-up sweeps each (the sweep graphs are captured and launched
+ * once), in two rounds over all candidates, and keeps
+ * the fastest by best time, where a candidate must be at least 1 % faster
+ * than an earlier one in the order above to replace it (the overlap choice is
+ * kept too; hsg_get_tuning reports it). Every variant computes the same
  * bits, so the trial sweeps are ordinary sweeps of the chain: with
- * d_backup == NULL the chain advances by them (n_sweeps + 1 per candidate);
+ * d_backup == NULL the chain advances by them (2 (n_sweeps + 10) per candidate);
  * with d_backup (device, state_bytes of hsg_query_sizes, 256-byte aligned,
  * caller-owned) the state is saved first and restored afterwards, so the chain
  * is left exactly as it was. Synchronises the stream. On success the chosen

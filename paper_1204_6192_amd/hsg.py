@@ -92,6 +92,7 @@ _SIG = {
     "hsg_set_tuning": [_vp, _i32],
     "hsg_set_kernel": [_vp, _i32],
     "hsg_set_overlap": [_vp, _i32],
+    "hsg_get_tuning": [_vp, _vp, _vp, _vp],
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
     "hsg_measure_pair_overlaps": [_vp, _vp, _vp],
     "hsg_measure_kmodes": [_vp, _vp, _vp],
@@ -307,6 +308,12 @@ class Lattice:
     def set_overlap(self, enable: bool) -> None:
         """Sweeps of the two halves of the samples on two streams (1) or one (0, default)."""
         check(lib.hsg_set_overlap(self.h, int(bool(enable))))
+
+    def get_tuning(self):
+        """(kernel variant, slots per work item, overlapped sweeps) in force."""
+        v, c, o = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib.hsg_get_tuning(self.h, C.byref(v), C.byref(c), C.byref(o)))
+        return v.value, c.value, o.value
 
     def autotune(self, n_sweeps: int = 4, restore: bool = True):
         """Time each kernel variant over n_sweeps real sweeps and keep the fastest.

@@ -115,7 +115,7 @@ def test_init_rejects_null_buffers_without_device():
 def test_null_handle_calls_fail_cleanly():
     for name, extra in (("hsg_sweep", (1, None)), ("hsg_pt_exchange", (None,)),
                         ("hsg_measure_energy", (None, None)), ("hsg_set_tuning", (0,)),
-                        ("hsg_set_math", (0,)), ("hsg_pair_sweep", (1, 0, None)), ("hsg_or_pairs", (2, None)), ("hsg_set_overlap", (1,)),
+                        ("hsg_set_math", (0,)), ("hsg_pair_sweep", (1, 0, None)), ("hsg_or_pairs", (2, None)), ("hsg_set_overlap", (1,)), ("hsg_get_tuning", (None, None, None)),
                         ("hsg_autotune", (4, None, None, None, None))):
         assert getattr(hsg.lib, name)(None, *extra) == hsg.E_INVALID
     hsg.lib.hsg_destroy(None)

@@ -887,7 +887,7 @@ def test_autotune_keeps_the_chain(hsg):
     ref.sweep(2)
     a.sweep(2)
     v, c = a.autotune(n_sweeps=2, restore=True)
-    assert v in (1, 2, 3) and c >= 0
+    assert v in (1, 2, 3, 4) and c >= 0
     assert a.get_state()[0] == ref.get_state()[0]
     assert torch.equal(a.get_spins(), ref.get_spins())
     assert torch.equal(a.get_temp_map(), ref.get_temp_map())
