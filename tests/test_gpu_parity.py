@@ -888,6 +888,7 @@ def test_autotune_keeps_the_chain(hsg):
     a.sweep(2)
     v, c = a.autotune(n_sweeps=2, restore=True)
     assert v in (1, 2, 3, 4) and c >= 0
+    assert a.get_tuning()[:2] == (v, c) and a.get_tuning()[2] in (0, 1)
     assert a.get_state()[0] == ref.get_state()[0]
     assert torch.equal(a.get_spins(), ref.get_spins())
     assert torch.equal(a.get_temp_map(), ref.get_temp_map())
