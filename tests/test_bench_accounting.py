@@ -56,3 +56,35 @@ def test_flop_count_and_ridge():
     upd = g.n_slots * g.N
     assert 2 * upd * 90 / bench.or_bytes_two_pairs([g], "f32") < ridge
     assert upd * 90 / bench.algorithmic_bytes([g], "f32", 1) < ridge
+
+
+def test_counter_traffic_needs_matching_build_and_launch(tmp_path, monkeypatch):
+    """Counter-derived bytes reach roofline.traffic only for the build, workload,
+    spin storage and kernel they were taken with: counters of other code or of
+    another launch say nothing about this one."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "k.md").write_text(
+        "# summary\n\ntraffic: build_id=abc workload=batched storage=f32 kernel=k_or_quad_stream "
+        "bytes_per_launch=3383000000 fetch_kib=1 fetch_scale=2.0 write_kib=1 write_scale=1.0\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    found = bench.measured_traffic("abc", "batched", "f32", "k_or_quad_stream")
+    assert found == (3383000000.0, os.path.join("profiles", "k.md"))
+    for args in (("abd", "batched", "f32", "k_or_quad_stream"), ("abc", "field", "f32", "k_or_quad_stream"),
+                 ("abc", "batched", "f16", "k_or_quad_stream"), ("abc", "batched", "f32", "k_pair_stream")):
+        assert bench.measured_traffic(*args) == (None, None), args
+
+
+def test_committed_profile_traffic_line_is_parseable():
+    """The committed summary of the dominant kernel carries one traffic line with
+    every key the benchmark matches on."""
+    import glob
+    lines = []
+    for fn in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        with open(fn) as f:
+            lines += [l for l in f if l.startswith("traffic:")]
+    assert len(lines) >= 1
+    for l in lines:
+        kv = dict(t.split("=", 1) for t in l[len("traffic:"):].split() if "=" in t)
+        assert {"build_id", "workload", "storage", "kernel", "bytes_per_launch"} <= set(kv)
+        assert float(kv["bytes_per_launch"]) > 0
