@@ -1041,15 +1041,23 @@ hsg_status overlapped_sweeps(hsg_lattice *h, int32_t n_sweeps, hipStream_t s)
     for (int k = 0; k < n_sweeps && st == HSG_OK; ++k) {
         const bool pt = h->pt_every > 0 && ((h->t + 1) % (uint64_t)h->pt_every) == 0;
         if (k > 0) e = hipStreamWaitEvent(s, h->ev[2], 0);  // half 0's heat bath after half 1's
-        if (e != hipSuccess) return hip_fail(e, "overlap wait");
+        if (e != hipSuccess) {
+            st = hip_fail(e, "overlap wait");
+            break;
+        }
         st = enqueue_half_sweep(h, 0, pt, s, h->ev[1]);
         if (st != HSG_OK) break;
         e = hipStreamWaitEvent(s2, h->ev[1], 0);  // half 1's heat bath after half 0's
-        if (e != hipSuccess) return hip_fail(e, "overlap wait");
+        if (e != hipSuccess) {
+            st = hip_fail(e, "overlap wait");
+            break;
+        }
         st = enqueue_half_sweep(h, 1, pt, s2, h->ev[2]);
         if (st == HSG_OK) h->t += 1;
     }
-    e = hipEventRecord(h->ev[3], s2);  // join: the caller's stream continues after both halves
+    // join, also after an error: the caller's stream continues after all that
+    // the second stream was given
+    e = hipEventRecord(h->ev[3], s2);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev[3], 0);
     if (e != hipSuccess && st == HSG_OK) st = hip_fail(e, "overlap join");
     return st;
