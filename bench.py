@@ -248,6 +248,8 @@ def main():
                     help="before the timed run, time every launch choice over this many sweeps "
                          "(hsg_autotune, the state restored afterwards) and keep the fastest; "
                          "0 = the library's default choice")
+    ap.add_argument("--kernel-variant", type=int, default=None, choices=[0, 1, 2, 3, 4],
+                    help="fix the kernel variant (hsg_set_kernel) after any tuning")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-launches", type=int, default=40)
@@ -290,6 +292,8 @@ def main():
         t_tune = time.perf_counter()
         lat.autotune(n_sweeps=args.autotune, restore=True)
         log(f"autotune over {args.autotune} sweeps per choice: {time.perf_counter() - t_tune:.1f} s")
+    if args.kernel_variant is not None:
+        lat.set_kernel(args.kernel_variant)
     if args.two_streams is not None:
         lat.set_overlap(args.two_streams)
     elif args.autotune <= 0 and args.config == "uneven":
