@@ -227,7 +227,9 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
  * pair in one launch where the whole plane fits a work-group (L <= 32), else
  * as 2; 4 = as 3, and the over-relaxation pairs of a sweep two by two in one
  * launch (four half-sweeps per read and write of the spins) where eleven
- * staged planes fit the work-group's LDS; 0 = automatic (currently 4). */
+ * staged planes fit the work-group's LDS; 0 = automatic (currently 4, but 3
+ * for quantised-angle storage, whose two-pair launch is slower than two fused
+ * pairs). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
 /* Tuning (results do not depend on it): 1 = where every lattice size runs

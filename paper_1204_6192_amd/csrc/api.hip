@@ -354,6 +354,9 @@ size_t fused_lds_bytes(const Group &g, int fuse)
 bool use_quad(const hsg_lattice *h, const Group &g)
 {
     if (h->kernel_variant != 0 && h->kernel_variant != 4) return false;
+    // automatic choice: quantised angles are decoded and re-encoded at every
+    // stage, which costs the two-pair launch more than the bytes it saves
+    if (h->kernel_variant == 0 && h->storage == HSG_STORE_QANGLE) return false;
     return use_pair(h, g) && fused_lds_bytes(g, 2) <= h->max_lds;
 }
 
