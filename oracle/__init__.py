@@ -31,6 +31,15 @@ Functions and what pins them (details in the tests):
 * ``Oracle.pt_exchange``-- acceptance frequency against min(1, e^Delta);
 * ``Oracle.measure_overlap`` -- q^2 = 1 for identical aligned copies, O(3)
                            invariance, trace identity.
+* ``stats_record`` / ``Oracle`` run statistics -- hand-built temperature-map
+                           sequences with hand-counted round trips, sums of
+                           listed energies, U_L and C_L of two-valued series;
+* ``Oracle.measure_chi4`` -- the four-replica double sums of Eq. (10): an FFT of
+                           the local-overlap fields, identical replicas (chi_1 =
+                           chi_2 = chi_3, N^2 at k = 0, 0 elsewhere),
+                           independent random replicas at infinite temperature
+                           (chi_1 / N averages 1/3 at every k, chi_2 and chi_3
+                           average 0).
 """
 
 from __future__ import annotations
@@ -113,6 +122,9 @@ def lib():
         L.hsgo_set_noise.argtypes = [C.c_double, C.c_uint64]
         L.hsgo_oct_encode.argtypes = [dp, i32p]
         L.hsgo_oct_decode.argtypes = [i32p, dp]
+        L.hsgo_stats_record.argtypes = [P(Cfg), dp, i32p, dp, dp, i32p, i32p, u32p]
+        L.hsgo_stats_finish.argtypes = [P(Cfg), dp, dp, dp, C.c_uint64, dp, dp]
+        L.hsgo_chi4.argtypes = [P(Cfg), dp, i32p, dp]
         _lib = L
     return _lib
 
@@ -210,6 +222,63 @@ def store_roundtrip(mode: str, s) -> np.ndarray:
     return s
 
 
+def stats_record(cfg, E, slot_at_temp, st) -> None:
+    """Record one sweep's energies E [D][O][T] (by slot) and maps into the
+    statistics dict st (arrays made by new_stats)."""
+    E = np.ascontiguousarray(E, dtype=np.float64)
+    sat = np.ascontiguousarray(slot_at_temp, dtype=np.int32)
+    lib().hsgo_stats_record(C.byref(cfg), _p(E, C.c_double), _p(sat, C.c_int32),
+                            _p(st["sum_e"], C.c_double), _p(st["sum_e2"], C.c_double),
+                            _p(st["end"], C.c_int32), _p(st["seen_low"], C.c_int32),
+                            _p(st["trips"], C.c_uint32))
+    st["n"] += 1
+
+
+def new_stats(n_samples, n_copies, n_temps):
+    shape = (n_samples, n_copies, n_temps)
+    return {"sum_e": np.zeros(shape), "sum_e2": np.zeros(shape),
+            "end": np.full(shape, -1, dtype=np.int32), "seen_low": np.zeros(shape, dtype=np.int32),
+            "trips": np.zeros(shape, dtype=np.uint32), "n": 0}
+
+
+def stats_finish(cfg, temps, st):
+    """(U_L, C_L) per ladder and rung, [D][O][T], from the recorded sums."""
+    temps = np.ascontiguousarray(temps, dtype=np.float64)
+    U = np.zeros_like(st["sum_e"])
+    Cv = np.zeros_like(st["sum_e"])
+    lib().hsgo_stats_finish(C.byref(cfg), _p(temps, C.c_double), _p(st["sum_e"], C.c_double),
+                            _p(st["sum_e2"], C.c_double), int(st["n"]), _p(U, C.c_double),
+                            _p(Cv, C.c_double))
+    return U, Cv
+
+
+def sweep_parallel(oracles, n_sweeps: int, threads: int) -> None:
+    """n_sweeps of several full-lattice, float32-storage oracles without noise
+    probes (each an independent chain) on `threads` host threads at once (the
+    C sweeps release the interpreter lock). The storage and noise settings are
+    global to the C library and stay at their defaults throughout."""
+    import concurrent.futures
+    for o in oracles:
+        if o.tiles is not None or o.storage != "f32" or o.noise[0] != 0.0 or o.stats is not None:
+            raise ValueError("sweep_parallel takes plain float32 full-lattice chains only")
+    lib().hsgo_set_storage_mode(0)
+    lib().hsgo_set_noise(0.0, 0)
+
+    def run(o):
+        t = np.array([o.t], dtype=np.uint64)
+        Jp, Hp = o._args()
+        rc = lib().hsgo_sweep(C.byref(o.cfg), Jp, Hp, _p(o.spins, C.c_double),
+                              _p(o.slot_at_temp, C.c_int32), _p(o.beta, C.c_double),
+                              _p(o.E, C.c_double), _p(t, C.c_uint64), int(n_sweeps),
+                              _p(o.accepts, C.c_uint64))
+        if rc != 0:
+            raise RuntimeError("oracle sweep failed")
+        o.t = int(t[0])
+
+    with concurrent.futures.ThreadPoolExecutor(max(1, int(threads))) as ex:
+        list(ex.map(run, oracles))
+
+
 # ---------------------------------------------------------------- group model
 class Oracle:
     """Serial float64 model of one lattice-size group; mirrors the C-ABI calls.
@@ -251,6 +320,7 @@ class Oracle:
         self.t = 0
         self.pt_calls = 0
         self.noise = (0.0, 0)  # sensitivity probe: (relative amplitude, stream seed)
+        self.stats = None      # run statistics (enable_stats)
 
     @classmethod
     def from_group(cls, g, *, seed, n_hb=1, n_or=4, pt_every=1, storage="f32", tiles=None,
@@ -284,10 +354,27 @@ class Oracle:
             lib().hsgo_set_noise(eps, (seed * 1_000_003 + self.t * 7919 + self.pt_calls)
                                  & 0xFFFFFFFFFFFFFFFF)
 
+    def enable_stats(self) -> None:
+        """Record run statistics (per-rung sums of E and E^2, round trips) after
+        every following sweep."""
+        self.stats = new_stats(self.cfg.n_samples, self.cfg.n_copies, self.cfg.n_temps)
+
+    def get_stats(self):
+        """(sums [D][O][T][2] of E and E^2 by rung, round trips [D][O][T] by slot,
+        sweeps recorded, U_L [D][O][T], C_L [D][O][T])."""
+        st = self.stats
+        U, Cv = stats_finish(self.cfg, self.temps, st)
+        return np.stack([st["sum_e"], st["sum_e2"]], axis=-1), st["trips"].copy(), st["n"], U, Cv
+
     def sweep(self, n_sweeps: int = 1, tile_order=None) -> None:
         """n_sweeps sweeps of the full-lattice checkerboard chain, or of the
         tile-local chain when the oracle was made with tiles (then tile_order
-        optionally permutes the visits of each coarse parity's tiles)."""
+        optionally permutes the visits of each coarse parity's tiles). With
+        statistics enabled, each sweep is recorded after its tempering pass."""
+        if self.stats is not None and n_sweeps > 1:
+            for _ in range(n_sweeps):
+                self.sweep(1, tile_order)
+            return
         lib().hsgo_set_storage_mode(STORAGE_MODES[self.storage])
         self._noise_on()
         t = np.array([self.t], dtype=np.uint64)
@@ -312,6 +399,8 @@ class Oracle:
         if rc != 0:
             raise RuntimeError("oracle sweep failed: temperature map is not a permutation")
         self.t = int(t[0])
+        if self.stats is not None and n_sweeps == 1:
+            stats_record(self.cfg, self.E, self.slot_at_temp, self.stats)
 
     def half_sweep(self, kind: int, parity: int, rep: int = 0, order=None) -> None:
         lib().hsgo_set_storage_mode(STORAGE_MODES[self.storage])
@@ -369,6 +458,17 @@ class Oracle:
         lib().hsgo_pair_overlaps(C.byref(self.cfg), _p(self.spins, C.c_double),
                                  _p(self.slot_at_temp, C.c_int32), _p(q, C.c_double))
         return q
+
+    def measure_chi4(self) -> np.ndarray:
+        """[n_samples][n_temps][4][5]: the four-replica double sums chi_1, chi_2,
+        chi_3 of Eq. (10) (copies 0..3 at each rung) for k = 0, k_x, k_y, k_z:
+        Re chi_1, Re chi_2, Im chi_2, Re chi_3, Im chi_3. O(N^2): small L only."""
+        if self.cfg.n_copies < 4:
+            raise ValueError("the four-replica estimators need n_copies >= 4")
+        out = np.zeros((self.cfg.n_samples, self.cfg.n_temps, 4, 5), dtype=np.float64)
+        lib().hsgo_chi4(C.byref(self.cfg), _p(self.spins, C.c_double),
+                        _p(self.slot_at_temp, C.c_int32), _p(out, C.c_double))
+        return out
 
     def hb_words(self, d, o, slot, rep, parity, i):
         w = np.zeros(2, dtype=np.uint32)

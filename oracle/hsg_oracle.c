@@ -790,3 +790,125 @@ void hsgo_hb_draw_many(const double h[3], double beta, const uint32_t key[2], in
         hsgo_hb_draw(h, beta, r[0], r[1], out + 3 * q);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Run statistics (§2: U_L and C_L; §4: tunnelling events of the tempering).  */
+/* ------------------------------------------------------------------------ */
+/* Called once after every sweep (after its tempering pass). For every ladder
+ * (sample d, copy o) and rung k, the energy of the configuration now at rung k
+ * is added to sum_e[(d O + o) T + k] and its square to sum_e2[...]; the
+ * internal energy U_L(T_k) is then sum_e / n and the specific heat
+ * C_L(T_k) = (sum_e2 / n - U_L^2) / T_k^2 over the n sweeps recorded.
+ *
+ * A tunnelling event (a round trip) is a closed loop of one replica between
+ * the end points of the ladder: lowest rung, highest rung, lowest rung again.
+ * Per replica (slot) the oracle keeps which end it visited last, end[...] in
+ * {-1 (none yet), 0 (lowest), 1 (highest)}, and whether it has ever been at
+ * the lowest rung, seen_low[...]. Arriving at the lowest rung with the highest
+ * as the last end visited, after an earlier visit to the lowest, closes one
+ * loop. A ladder with one rung has no loops. */
+void hsgo_stats_record(const hsgo_cfg *c, const double *E, const int32_t *slot_at_temp,
+                       double *sum_e, double *sum_e2, int32_t *end, int32_t *seen_low,
+                       uint32_t *trips)
+{
+    const int T = c->n_temps;
+    for (int d = 0; d < c->n_samples; ++d)
+        for (int o = 0; o < c->n_copies; ++o) {
+            const int64_t lad = (int64_t)d * c->n_copies + o;
+            const int32_t *row = slot_at_temp + lad * T;
+            for (int k = 0; k < T; ++k) {
+                const double e = E[lad * T + row[k]];
+                sum_e[lad * T + k] += e;
+                sum_e2[lad * T + k] += e * e;
+            }
+            if (T < 2) continue;
+            for (int s = 0; s < T; ++s) {
+                const int64_t r = lad * T + s;
+                if (row[0] == s) {
+                    if (end[r] == 1 && seen_low[r]) trips[r] += 1u;
+                    end[r] = 0;
+                    seen_low[r] = 1;
+                } else if (row[T - 1] == s) {
+                    end[r] = 1;
+                }
+            }
+        }
+}
+
+/* U_L(T_k) and C_L(T_k) of every ladder from the sums of n recorded sweeps. */
+void hsgo_stats_finish(const hsgo_cfg *c, const double *temps, const double *sum_e,
+                       const double *sum_e2, uint64_t n, double *U, double *C)
+{
+    const int T = c->n_temps;
+    const int64_t n_lad = (int64_t)c->n_samples * c->n_copies;
+    for (int64_t lad = 0; lad < n_lad; ++lad)
+        for (int k = 0; k < T; ++k) {
+            const int64_t r = lad * T + k;
+            const double u = sum_e[r] / (double)n;
+            U[r] = u;
+            C[r] = (sum_e2[r] / (double)n - u * u) / (temps[k] * temps[k]);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Four-replica estimators of the connected spin-glass susceptibility in a    */
+/* field, Eqs. (9)-(11).                                                      */
+/* ------------------------------------------------------------------------ */
+/* For every sample d and rung k, with copies 0, 1, 2, 3 at that rung as the
+ * replicas (1), (2), (3), (4), the three double sums of Eq. (10) over all
+ * ordered site pairs (i, j) and spin components (mu, nu), written out term by
+ * term:
+ *   chi_1(k) = sum_{i,j} sum_{mu,nu} s_i^mu(1) s_j^nu(1) s_i^mu(2) s_j^nu(2) e^{i k.(R_i - R_j)}
+ *   chi_2(k) = sum_{i,j} sum_{mu,nu} s_i^mu(1) s_j^nu(1) s_i^mu(3) s_j^nu(4) e^{i k.(R_i - R_j)}
+ *   chi_3(k) = sum_{i,j} sum_{mu,nu} s_i^mu(1) s_j^nu(2) s_i^mu(3) s_j^nu(4) e^{i k.(R_i - R_j)}
+ * for k = 0 and k = (2 pi / L) e_a, a = x, y, z. Eq. (11) assembles
+ * chi_SG(k) = [chi_1 - 2 chi_2 + chi_3] / N from their thermal and disorder
+ * averages. O(N^2) per rung: for small lattices only.
+ * out[((d T + k) 4 + w) 5 + m], w = 0 (k = 0), 1, 2, 3 (k_x, k_y, k_z):
+ *   m = 0: Re chi_1; m = 1, 2: Re, Im chi_2; m = 3, 4: Re, Im chi_3.
+ * (chi_1 is real; its imaginary part is not stored.) Needs n_copies >= 4. */
+void hsgo_chi4(const hsgo_cfg *c, const double *spins, const int32_t *slot_at_temp,
+               double *out)
+{
+    const int L = c->L, O = c->n_copies, T = c->n_temps;
+    const int64_t N = (int64_t)L * L * L;
+    const double w0 = HSGO_TWO_PI / (double)L;
+    for (int d = 0; d < c->n_samples; ++d)
+        for (int k = 0; k < T; ++k) {
+            const double *r[4];
+            for (int a = 0; a < 4; ++a)
+                r[a] = slot_ptr(c, (double *)spins, d, a,
+                                slot_at_temp[((int64_t)d * O + a) * T + k]);
+            for (int w = 0; w < 4; ++w) {
+                double re1 = 0.0, re2 = 0.0, im2 = 0.0, re3 = 0.0, im3 = 0.0;
+                for (int64_t i = 0; i < N; ++i)
+                    for (int64_t j = 0; j < N; ++j) {
+                        double phase = 0.0;
+                        if (w > 0) {
+                            const int64_t ri = w == 1 ? i % L : w == 2 ? (i / L) % L : i / ((int64_t)L * L);
+                            const int64_t rj = w == 1 ? j % L : w == 2 ? (j / L) % L : j / ((int64_t)L * L);
+                            phase = w0 * (double)(ri - rj);
+                        }
+                        const double cs = cos(phase), sn = sin(phase);
+                        double t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                        for (int mu = 0; mu < 3; ++mu)
+                            for (int nu = 0; nu < 3; ++nu) {
+                                t1 += r[0][mu * N + i] * r[0][nu * N + j] * r[1][mu * N + i] * r[1][nu * N + j];
+                                t2 += r[0][mu * N + i] * r[0][nu * N + j] * r[2][mu * N + i] * r[3][nu * N + j];
+                                t3 += r[0][mu * N + i] * r[1][nu * N + j] * r[2][mu * N + i] * r[3][nu * N + j];
+                            }
+                        re1 += t1 * cs;
+                        re2 += t2 * cs;
+                        im2 += t2 * sn;
+                        re3 += t3 * cs;
+                        im3 += t3 * sn;
+                    }
+                double *o = out + (((int64_t)d * T + k) * 4 + w) * 5;
+                o[0] = re1;
+                o[1] = re2;
+                o[2] = im2;
+                o[3] = re3;
+                o[4] = im3;
+            }
+        }
+}
