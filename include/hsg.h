@@ -116,7 +116,9 @@ typedef struct hsg_lattice hsg_lattice;
 /* Sizes of the four caller-owned device buffers for `desc`. Host only. */
 hsg_status hsg_query_sizes(const hsg_desc *desc, hsg_sizes *out);
 
-/* Validate `desc`, bind the buffers and pack the canonical inputs into them.
+/* Validate `desc`, bind the buffers and pack the canonical inputs into them
+ * (the inputs of one execution round, Sec. 3.2: spins, couplings, fields and
+ * temperatures; the random-number state is the seed plus the sweep counter).
  * d_spins0, d_J (and d_H if any group has a field) are read on `stream` and
  * may be freed once the stream has passed this call. d_state, d_couplings,
  * d_field (may be NULL if field_bytes == 0) and d_scratch must stay allocated
@@ -129,9 +131,10 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
 /* n_sweeps >= 0 full sweeps (see the header comment), asynchronous. */
 hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream);
 
-/* One checkerboard half-sweep of every replica: kind 0 = heat bath, 1 = over-
- * relaxation; parity 0 or 1; rep = heat-bath repetition index for the counter.
- * Uses the current sweep counter and does not advance it. */
+/* One checkerboard half-sweep of every replica (the sub-lattice update of
+ * Sec. 3.1): kind 0 = heat bath, Eq. (2), 1 = over-relaxation, Eq. (3); parity
+ * 0 or 1; rep = heat-bath repetition index for the counter. Uses the current
+ * sweep counter and does not advance it. */
 hsg_status hsg_half_sweep(hsg_lattice *h, int32_t kind, int32_t parity, int32_t rep,
                           hsg_stream_t stream);
 
@@ -148,9 +151,10 @@ hsg_status hsg_pair_sweep(hsg_lattice *h, int32_t kind, int32_t rep, hsg_stream_
  * HSG_E_INVALID for a NULL handle or n_pairs outside 1..1000. */
 hsg_status hsg_or_pairs(hsg_lattice *h, int32_t n_pairs, hsg_stream_t stream);
 
-/* One standalone tempering pass over every ladder using the energies of the
- * last sweep (or of the last hsg_measure_energy); advances the standalone-call
- * counter. */
+/* One standalone tempering pass, Eq. (4), over every ladder (rung pairs from
+ * the lowest temperature up, temperatures permuted, spins kept) using the
+ * energies of the last sweep (or of the last hsg_measure_energy); advances the
+ * standalone-call counter. */
 hsg_status hsg_pt_exchange(hsg_lattice *h, hsg_stream_t stream);
 
 /* Recompute the float64 energy of Eq. (1) of every replica into d_E
@@ -195,6 +199,43 @@ hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream);
  * Uses the scratch buffer; stream-ordered. */
 hsg_status hsg_measure_pair_overlaps(hsg_lattice *h, double *d_q, hsg_stream_t stream);
 
+/* Four-replica estimators of the connected spin-glass susceptibility in a
+ * field, Eqs. (9)-(11): with copies 0, 1, 2, 3 at each rung as the replicas
+ * (1), (2), (3), (4), the double sums of Eq. (10)
+ *   chi_1(k) = sum_{i,j} sum_{mu,nu} s_i^mu(1) s_j^nu(1) s_i^mu(2) s_j^nu(2) e^{i k.(R_i - R_j)},
+ *   chi_2(k): the same with s_i^mu(3) s_j^nu(4) in place of the second pair,
+ *   chi_3(k): s_i^mu(1) s_j^nu(2) s_i^mu(3) s_j^nu(4),
+ * of the current configurations (one entry of their time series), for k = 0
+ * and k = (2 pi / L) e_a, a = x, y, z. Eq. (11) assembles chi_SG(k) =
+ * [chi_1 - 2 chi_2 + chi_3]_J / N from their thermal averages. Output d_chi
+ * (device, caller-owned, float64) is [group][sample][rung][4][5]: for k = 0,
+ * k_x, k_y, k_z: chi_1, Re chi_2, Im chi_2, Re chi_3, Im chi_3 (chi_1 is real).
+ * Computed from the copy-pair sums of hsg_measure_pair_overlaps (the double
+ * sums factorise), in float64. Needs n_copies >= 4 in every group
+ * (HSG_E_INVALID) and L <= 1024 (HSG_E_UNSUPPORTED). Uses the scratch buffer;
+ * stream-ordered. */
+hsg_status hsg_measure_chi(hsg_lattice *h, double *d_chi, hsg_stream_t stream);
+
+/* Per-sweep time series (the paper records time series of the measured
+ * quantities and copies them to the host, Sec. 3.2; the internal energy U_L
+ * of the model section is their average). With d_series (device,
+ * caller-owned, float64, capacity records) every following sweep of
+ * hsg_sweep writes, after its tempering pass, one record at position
+ * t - t0 (t the sweep's counter, t0 the counter at this call): for each group
+ * in order, the energy of the configuration at every rung [sample][copy][rung],
+ * then, where the group has n_copies >= 2, the overlap q^2 of Eq. (5) between
+ * copies 0 and 1 [sample][rung]. Records past `capacity` (or before t0, after
+ * hsg_set_state moved the counter back) are not written. *record_doubles
+ * (host, may be NULL) receives the doubles per record. d_series = NULL with
+ * capacity = 0 switches the series off. While a series is on, sweeps run on
+ * one stream (hsg_set_overlap has no effect). HSG_E_INVALID for a NULL handle
+ * or a pointer / capacity mismatch; HSG_E_SIZE for capacity >= 2^31. */
+hsg_status hsg_set_series(hsg_lattice *h, double *d_series, int64_t capacity, int64_t *record_doubles);
+
+/* Records of the series written so far (host, no synchronisation):
+ * min(t - t0, capacity), 0 when no series is set. */
+hsg_status hsg_get_series_count(const hsg_lattice *h, int64_t *n_records);
+
 /* Decode the spins into the canonical float32 layout (renormalised). */
 hsg_status hsg_get_spins(const hsg_lattice *h, float *d_spins, hsg_stream_t stream);
 
@@ -210,8 +251,10 @@ hsg_status hsg_set_temp_map(hsg_lattice *h, const int32_t *d_slot_at_temp, hsg_s
  * for k = 0..n_temps-2 (device). */
 hsg_status hsg_get_pt_accepts(const hsg_lattice *h, uint64_t *d_accepts, hsg_stream_t stream);
 
-/* Generator position for checkpoint / resume. get_ returns host values; set_
- * also writes the device copy of the sweep counter, ordered on `stream`. */
+/* Generator position for checkpoint / resume (the random-number state that
+ * one execution round of Sec. 3.2 hands to the next). get_ returns host
+ * values; set_ also writes the device copy of the sweep counter, ordered on
+ * `stream`. */
 hsg_status hsg_get_state(const hsg_lattice *h, uint64_t *sweep_counter, uint64_t *pt_calls,
                          uint64_t *seed);
 hsg_status hsg_set_state(hsg_lattice *h, uint64_t sweep_counter, uint64_t pt_calls,
@@ -252,6 +295,23 @@ hsg_status hsg_set_overlap(hsg_lattice *h, int32_t enable);
  * written to its non-NULL host output. HSG_E_INVALID for a NULL handle. */
 hsg_status hsg_get_tuning(const hsg_lattice *h, int32_t *variant, int32_t *slots_per_item, int32_t *overlap);
 
+/* Tuning (results do not depend on it): geometry of the z-march kernels of
+ * lattice-size group `group` (the tile shape of the local-update kernel; the
+ * paper scans tile sizes for speed, Sec. 4). tile_y = rows per work-group: L
+ * (whole planes, the only choice where L * L / 4 <= 256 threads fit a
+ * work-group, i.e. L <= 32) or a divisor of L below it with L / 4 * tile_y <=
+ * 256 (row bands with two halo rows; one of the four tallest); z_slabs = 1, 2,
+ * 4 or 8 slabs of at least 8 planes that a single-pass launch splits the
+ * z-march into. tile_y = z_slabs = 0 restores the default (the tallest band,
+ * slabs until a launch has about 4096 work-groups). Fused pairs and two-pair
+ * launches always march whole planes in one slab. HSG_E_INVALID for a bad
+ * handle, group or shape; HSG_E_UNSUPPORTED for a group with L % 4 != 0. */
+hsg_status hsg_set_geometry(hsg_lattice *h, int32_t group, int32_t tile_y, int32_t z_slabs);
+
+/* The geometry in force for `group` (0, 0 where L % 4 != 0); either output may
+ * be NULL. */
+hsg_status hsg_get_geometry(const hsg_lattice *h, int32_t group, int32_t *tile_y, int32_t *z_slabs);
+
 /* Arithmetic of the heat-bath draw (Eq. (2)). 0 (default): square roots and
  * divisions from the hardware reciprocal (square root) refined by Newton steps
  * (within one ulp, almost always correctly rounded), the azimuth's sine and
@@ -270,10 +330,11 @@ hsg_status hsg_set_math(hsg_lattice *h, int32_t mode);
  * n_hb heat-bath pairs, then n_or over-relaxation pairs). chain = 1: the
  * tile-local chain of the double checkerboard decomposition (the paper's
  * implementation section and its numbered Monte Carlo procedure): the lattice
- * is cut into tiles of L x tile_y x tile_z sites (0 = L, whole rows along x);
- * every lattice size must have L % 4 == 0, tile edges dividing L and L / edge
- * either 1 or even. A sweep visits the tiles of coarse parity
- * (Y + Z) mod 2 = 0, then those of parity 1; on a visit the tile gets n_hit
+ * is cut into tiles of tile_x x tile_y x tile_z sites (0 = L: whole rows along
+ * x, or whole planes; the paper's optimum is 8 x 8 x 8); every lattice size
+ * must have L % 4 == 0, tile edges dividing L, tile_x a multiple of 4 and
+ * L / edge either 1 or even. A sweep visits the tiles of coarse parity
+ * (X + Y + Z) mod 2 = 0, then those of parity 1; on a visit the tile gets n_hit
  * repetitions of n_or over-relaxation rounds followed by n_hb heat-bath rounds
  * (a round: even sites, then odd sites), with the sites outside the tile held
  * fixed; heat-bath round b of repetition r uses repetition index r n_hb + b of
@@ -283,7 +344,8 @@ hsg_status hsg_set_math(hsg_lattice *h, int32_t mode);
  * after resuming. Errors: HSG_E_INVALID for bad shapes, HSG_E_UNSUPPORTED when
  * a tile does not fit one work-group (at most 1024 site pairs per parity and
  * 64 KiB of staged spins per replica). */
-hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t tile_z, int32_t n_hit);
+hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_x, int32_t tile_y, int32_t tile_z,
+                         int32_t n_hit);
 
 /* Autotuner of the launch configuration (the batching row of the method: tile
  * shape and fusion per lattice size). Times n_sweeps (1..1000) whole sweeps of
@@ -294,7 +356,11 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
  * once), in two rounds over all candidates, and keeps
  * the fastest by best time, where a candidate must be at least 1 % faster
  * than an earlier one in the order above to replace it (the overlap choice is
- * kept too; hsg_get_tuning reports it). Every variant computes the same
+ * kept too; hsg_get_tuning reports it). Then, with that choice in force, it
+ * times the z-march geometries of hsg_set_geometry for every lattice size that
+ * runs single passes, one size after the other, the current geometry first
+ * and replaced only by one at least 1 % faster (hsg_get_geometry reports the
+ * result). Every variant computes the same
  * bits, so the trial sweeps are ordinary sweeps of the chain: with
  * d_backup == NULL the chain advances by them (2 (n_sweeps + 10) per candidate);
  * with d_backup (device, state_bytes of hsg_query_sizes, 256-byte aligned,

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hsg.h"
@@ -42,6 +43,8 @@ hsg_status hip_fail(hipError_t e, const char *what)
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+
+
 // Bytes of stored spin per site: 3 float32, 3 x 16-bit, or one 32-bit angle word.
 int bytes_per_spin(int storage)
 {
@@ -70,47 +73,85 @@ struct Group {
     uint64_t o_J6, o_b64, o_b32, o_Jbits;        // couplings
     uint64_t o_H;                                // field
     uint64_t o_scr;                              // scratch
+    uint64_t o_scr_q;                            // overlap output of the per-sweep series (in scratch)
     int32_t n_pb_sweep;                          // blocks of 256 site pairs per replica
     int32_t n_pb_site;                           // blocks of 256 sites per replica half
     int32_t q_pb, q_chunk;                       // overlap: work-groups per rung pair, sites each
     // z-march geometry (L divisible by 4), see hsg::StreamArgs
     bool stream_ok;
     int32_t s_TY, s_RB, s_rows, s_ytiles, s_zslabs;
+    int32_t s_max_pb;  // most energy partials per replica any allowed geometry makes (scratch sizing)
     // tile-local chain geometry, see hsg::TileArgs (set by hsg_set_chain)
-    int32_t t_TY, t_TZ, t_BY, t_BZ, t_hy, t_hz, t_RY, t_RZ, t_P, t_RB, t_chunks, t_threads;
+    int32_t t_TX, t_TY, t_TZ, t_BX, t_BY, t_BZ, t_hx, t_hy, t_hz, t_RXh, t_RY, t_RZ, t_P, t_RB, t_chunks, t_threads;
     size_t t_lds;
 };
 
-// Work-group shape of the z-march for lattice size L (L % 4 == 0): the whole
-// plane in LDS when L * L / 4 <= 256 threads (several replicas per group for
-// small L), otherwise the tallest row band that fits, with two halo rows.
+// z-march geometry (L % 4 == 0): TY rows per work-group, either the whole plane
+// (TY = L, when L * L / 4 <= 256 threads; several replicas per group for small
+// L) or a row band of TY rows with two halo rows, and the number of z-slabs of
+// a single-pass launch (each slab reads one extra plane at either end). Returns
+// false for a shape the kernels do not take.
+bool apply_geometry(Group &g, int ty, int zslabs)
+{
+    const int P = g.L / 4;
+    if (ty == g.L) {
+        if (P * g.L > hsg::kBlock) return false;
+        g.s_rows = g.L;
+    } else {
+        if (ty < 2 || ty > g.L || g.L % ty != 0 || P * ty > hsg::kBlock || P * g.L <= hsg::kBlock) return false;
+        g.s_rows = ty + 2;
+    }
+    if (zslabs < 1 || zslabs > 8 || (zslabs & (zslabs - 1)) != 0 || g.L % zslabs != 0 ||
+        (zslabs > 1 && g.L / zslabs < 8))
+        return false;
+    g.s_TY = ty;
+    g.s_RB = hsg::kBlock / (P * ty);
+    g.s_ytiles = g.L / ty;
+    g.s_zslabs = zslabs;
+    return true;
+}
+
+// The geometries the autotuner tries for a lattice size: the whole plane where
+// it fits a work-group, else the four tallest row bands; 1, 2, 4 or 8 z-slabs
+// of at least 8 planes. The default comes first.
+std::vector<std::pair<int, int>> geometry_candidates(const Group &g)
+{
+    std::vector<std::pair<int, int>> out;
+    if (!g.stream_ok) return out;
+    const int P = g.L / 4;
+    std::vector<int> tys;
+    if (P * g.L <= hsg::kBlock) {
+        tys.push_back(g.L);
+    } else {
+        for (int c = g.L - 1; c >= 2 && tys.size() < 4; --c)
+            if (g.L % c == 0 && P * c <= hsg::kBlock) tys.push_back(c);
+    }
+    for (int ty : tys)
+        for (int z = 1; z <= 8; z *= 2)
+            if (z == 1 || (g.L % z == 0 && g.L / z >= 8)) out.emplace_back(ty, z);
+    return out;
+}
+
+// Default z-march geometry for lattice size L: the whole plane where it fits,
+// otherwise the tallest row band; single half-sweeps split z into slabs until
+// the launch has about 4096 work-groups, keeping slabs >= 16 planes.
 void stream_geometry(Group &g)
 {
     g.stream_ok = (g.L % 4) == 0;
     if (!g.stream_ok) return;
-    const int P = g.L / 4;
-    if (P * g.L <= hsg::kBlock) {
-        g.s_TY = g.L;
-        g.s_rows = g.L;
-    } else {
-        int ty = 0;
-        for (int c = 2; c <= g.L; ++c)
-            if (g.L % c == 0 && P * c <= hsg::kBlock) ty = c;
-        if (ty < 2) {
-            g.stream_ok = false;
-            return;
-        }
-        g.s_TY = ty;
-        g.s_rows = ty + 2;
+    const std::vector<std::pair<int, int>> cands = geometry_candidates(g);
+    if (cands.empty()) {
+        g.stream_ok = false;
+        return;
     }
-    g.s_RB = hsg::kBlock / (P * g.s_TY);
-    g.s_ytiles = g.L / g.s_TY;
-    // Single half-sweeps split z into slabs (each reads one extra plane at either
-    // end) until the launch has about 4096 work-groups, keeping slabs >= 16 planes.
-    const int64_t base = (g.n_rep + g.s_RB - 1) / g.s_RB * g.s_ytiles;
-    g.s_zslabs = 1;
-    while (base * g.s_zslabs < 4096 && g.L % (2 * g.s_zslabs) == 0 && g.L / (2 * g.s_zslabs) >= 16)
-        g.s_zslabs *= 2;
+    const int ty = cands.front().first;
+    const int rb = hsg::kBlock / ((g.L / 4) * ty);
+    const int64_t base = (g.n_rep + rb - 1) / rb * (g.L / ty);
+    int zs = 1;
+    while (base * zs < 4096 && g.L % (2 * zs) == 0 && g.L / (2 * zs) >= 16 && 2 * zs <= 8) zs *= 2;
+    g.s_max_pb = 1;
+    for (const auto &c : cands) g.s_max_pb = std::max(g.s_max_pb, (g.L / c.first) * c.second);
+    (void)apply_geometry(g, ty, zs);
 }
 
 struct Layout {
@@ -217,13 +258,17 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         if (g.field) fd = align_up(fd + (uint64_t)g.D * 2 * 3 * g.Nh * 4);
         // scratch: the largest of the reductions of this group
         g.o_scr = sc;
-        const int64_t n_pb_stream = g.stream_ok ? (int64_t)g.s_ytiles * g.s_zslabs : 1;
+        const int64_t n_pb_stream = g.stream_ok ? (int64_t)g.s_max_pb : 1;
         const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > n_pb_stream ? g.n_pb_sweep : n_pb_stream) * 8;
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
         const uint64_t k_full = (uint64_t)g.D * g.T * g.q_pb * 84 * 8;  // k modes, same blocks
         const uint64_t p_full = (uint64_t)g.D * g.T * g.q_pb * 7 * (g.O * (g.O - 1) / 2) * 8;  // copy pairs
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
+        // the per-sweep series stages the overlap [D][T][10] after its partials
+        g.o_scr_q = g.o_scr + align_up(q_full);
+        const uint64_t series_need = align_up(q_full) + (uint64_t)g.D * g.T * 10 * 8;
+        if (series_need > need) need = series_need;
         if (q_full > need) need = q_full;
         if (k_full > need) need = k_full;
         if (p_full > need) need = p_full;
@@ -259,8 +304,12 @@ struct hsg_lattice {
     int64_t batch = -1;   // replicas per sweep batch: -1 off, 0 automatic (about 192 MiB of spins)
     bool stats = false;   // accumulate run statistics after every sweep
     uint64_t n_stats = 0;  // sweeps accumulated since the last reset
+    // per-sweep series (hsg_set_series): record of sweep t at position t - series_t0
+    double *series = nullptr;
+    int64_t series_cap = 0, series_rec = 0;
+    uint64_t series_t0 = 0;
     // Markov chain: 0 the full-lattice checkerboard, 1 the tile-local chain
-    int32_t chain = 0, tile_y = 0, tile_z = 0, n_hit = 1;
+    int32_t chain = 0, tile_x = 0, tile_y = 0, tile_z = 0, n_hit = 1;
     bool have_energies = false;
     // hipGraph replay of whole sweeps (tempering every sweep or never)
     bool use_graphs = true;
@@ -628,6 +677,57 @@ hsg_status run_stats(hsg_lattice *h, bool clear, hipStream_t s)
     return HSG_OK;
 }
 
+// Doubles of one sweep's series record: per group the energies by rung
+// [D][O][T], then q^2 [D][T] where the group has two copies or more.
+int64_t series_record(const hsg_lattice *h)
+{
+    int64_t n = 0;
+    for (const Group &g : h->lay.g) n += (int64_t)g.D * g.O * g.T + (g.O >= 2 ? (int64_t)g.D * g.T : 0);
+    return n;
+}
+
+// Append this sweep's record to the series (after tempering; the device counter
+// still holds the sweep's index).
+hsg_status run_series(hsg_lattice *h, hipStream_t s)
+{
+    int64_t off = 0;
+    for (const Group &g : h->lay.g) {
+        hipError_t e = hipSuccess;
+        double *q = nullptr;
+        if (g.O >= 2) {
+            hsg::OverlapArgs a{};
+            a.spins = h->state + g.o_spins;
+            a.slot_at_temp = reinterpret_cast<const int32_t *>(h->state + g.o_sat);
+            a.partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+            q = reinterpret_cast<double *>(h->scratch + g.o_scr_q);
+            a.q = q;
+            a.Nh = g.Nh;
+            a.D = g.D;
+            a.O = g.O;
+            a.T = g.T;
+            a.n_pb = g.q_pb;
+            a.chunk = g.q_chunk;
+            e = hsg::launch_overlap(a, h->storage, s);
+        }
+        hsg::SeriesArgs r{};
+        r.slot_at_temp = reinterpret_cast<const int32_t *>(h->state + g.o_sat);
+        r.E = reinterpret_cast<const double *>(h->state + g.o_E);
+        r.q = q;
+        r.out = h->series + off;
+        r.tptr = dev_counter(h);
+        r.t0 = (uint32_t)h->series_t0;
+        r.capacity = h->series_cap;
+        r.stride = h->series_rec;
+        r.D = g.D;
+        r.O = g.O;
+        r.T = g.T;
+        if (e == hipSuccess) e = hsg::launch_series(r, s);
+        if (e != hipSuccess) return hip_fail(e, "series launch");
+        off += (int64_t)g.D * g.O * g.T + (g.O >= 2 ? (int64_t)g.D * g.T : 0);
+    }
+    return HSG_OK;
+}
+
 // Exact energies of every replica into E (full recomputation), all groups.
 hsg_status run_energy(hsg_lattice *h, hipStream_t s)
 {
@@ -653,6 +753,7 @@ hsg_status run_energy(hsg_lattice *h, hipStream_t s)
 
 int32_t tiles_in_phase(const Group &g, int phase)
 {
+    if (g.t_BX > 1) return g.t_BZ * g.t_BY * (g.t_BX / 2);
     if (g.t_BY > 1) return g.t_BZ * (g.t_BY / 2);
     if (g.t_BZ > 1) return g.t_BZ / 2;
     return phase == 0 ? 1 : 0;
@@ -676,12 +777,16 @@ hsg_status run_tile_sweep(hsg_lattice *h, hipStream_t s)
             a.Nh = g.Nh;
             a.L = g.L;
             a.Lh = g.L / 2;
+            a.TX = g.t_TX;
             a.TY = g.t_TY;
             a.TZ = g.t_TZ;
+            a.BX = g.t_BX;
             a.BY = g.t_BY;
             a.BZ = g.t_BZ;
+            a.hx = g.t_hx;
             a.hy = g.t_hy;
             a.hz = g.t_hz;
+            a.RXh = g.t_RXh;
             a.RY = g.t_RY;
             a.RZ = g.t_RZ;
             a.P = g.t_P;
@@ -713,6 +818,7 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
         hsg_status st = run_tile_sweep(h, s);
         if (st == HSG_OK && pt) st = run_pt(h, 0u, 1u, s);
         if (st == HSG_OK && h->stats) st = run_stats(h, false, s);
+        if (st == HSG_OK && h->series) st = run_series(h, s);
         if (st != HSG_OK) return st;
         const hipError_t e = hsg::launch_advance(dev_counter(h), s);
         if (e != hipSuccess) return hip_fail(e, "counter launch");
@@ -760,6 +866,10 @@ hsg_status enqueue_sweep(hsg_lattice *h, bool pt, hipStream_t s)
     }
     if (h->stats) {
         hsg_status st = run_stats(h, false, s);
+        if (st != HSG_OK) return st;
+    }
+    if (h->series) {
+        hsg_status st = run_series(h, s);
         if (st != HSG_OK) return st;
     }
     const hipError_t e = hsg::launch_advance(dev_counter(h), s);
@@ -935,7 +1045,7 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
 // the same counters as in one stream, so the results are the same bits.
 bool overlap_ok(const hsg_lattice *h)
 {
-    if (!h->overlap || h->chain != 0) return false;
+    if (!h->overlap || h->chain != 0 || h->series != nullptr) return false;
     for (const Group &g : h->lay.g) {
         if (!use_stream(h, g) || g.D < 2 || batch_of(h, g) > 0) return false;
     }
@@ -1257,6 +1367,60 @@ hsg_status hsg_measure_pair_overlaps(hsg_lattice *h, double *d_q, hsg_stream_t s
     return HSG_OK;
 }
 
+hsg_status hsg_measure_chi(hsg_lattice *h, double *d_chi, hsg_stream_t stream)
+{
+    if (h == nullptr || d_chi == nullptr) return fail(HSG_E_INVALID, "handle and d_chi are required");
+    for (const Group &g : h->lay.g) {
+        if (g.O < 4) return fail(HSG_E_INVALID, "the four-replica estimators need n_copies >= 4 in every group");
+        if (g.L > 1024) return fail(HSG_E_UNSUPPORTED, "the four-replica estimators need L <= 1024");
+    }
+    int64_t off = 0;
+    for (const Group &g : h->lay.g) {
+        hsg::PairOvArgs a{};
+        a.spins = h->state + g.o_spins;
+        a.slot_at_temp = reinterpret_cast<const int32_t *>(h->state + g.o_sat);
+        a.partials = reinterpret_cast<double *>(h->scratch + g.o_scr);
+        a.q = nullptr;
+        a.chi = d_chi + off;
+        a.Nh = g.Nh;
+        a.L = g.L;
+        a.D = g.D;
+        a.O = g.O;
+        a.T = g.T;
+        a.n_pb = g.q_pb;
+        a.chunk = 2 * g.q_chunk;
+        const hipError_t e = hsg::launch_pair_overlaps(a, h->storage, S(stream));
+        if (e != hipSuccess) return hip_fail(e, "measure_chi");
+        off += (int64_t)g.D * g.T * 4 * 5;
+    }
+    return HSG_OK;
+}
+
+hsg_status hsg_set_series(hsg_lattice *h, double *d_series, int64_t capacity, int64_t *record_doubles)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if ((d_series == nullptr) != (capacity == 0) || capacity < 0)
+        return fail(HSG_E_INVALID, "d_series and capacity must both be set (capacity > 0) or both be 0");
+    if (capacity > 0x7FFFFFFFll) return fail(HSG_E_SIZE, "capacity = %lld exceeds 2^31 - 1", (long long)capacity);
+    h->series = d_series;
+    h->series_cap = capacity;
+    h->series_rec = series_record(h);
+    h->series_t0 = h->t;
+    drop_graphs(h);
+    if (record_doubles) *record_doubles = h->series_rec;
+    return HSG_OK;
+}
+
+hsg_status hsg_get_series_count(const hsg_lattice *h, int64_t *n_records)
+{
+    if (h == nullptr || n_records == nullptr) return fail(HSG_E_INVALID, "handle and n_records are required");
+    int64_t n = 0;
+    if (h->series != nullptr && h->t > h->series_t0)
+        n = (int64_t)std::min<uint64_t>(h->t - h->series_t0, (uint64_t)h->series_cap);
+    *n_records = n;
+    return HSG_OK;
+}
+
 hsg_status hsg_get_spins(const hsg_lattice *h, float *d_spins, hsg_stream_t stream)
 {
     if (h == nullptr || d_spins == nullptr) return fail(HSG_E_INVALID, "handle and d_spins are required");
@@ -1381,6 +1545,38 @@ hsg_status hsg_get_tuning(const hsg_lattice *h, int32_t *variant, int32_t *slots
     return HSG_OK;
 }
 
+hsg_status hsg_set_geometry(hsg_lattice *h, int32_t group, int32_t tile_y, int32_t z_slabs)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (group < 0 || group >= (int32_t)h->lay.g.size())
+        return fail(HSG_E_INVALID, "group = %d, need 0..%zu", group, h->lay.g.size() - 1);
+    Group &g = h->lay.g[group];
+    if (!g.stream_ok) return fail(HSG_E_UNSUPPORTED, "group %d: L = %d runs no z-march (L %% 4 != 0)", group, g.L);
+    if (tile_y == 0 && z_slabs == 0) {
+        stream_geometry(g);
+    } else {
+        const std::pair<int, int> want(tile_y, z_slabs);
+        const std::vector<std::pair<int, int>> gc = geometry_candidates(g);
+        if (std::find(gc.begin(), gc.end(), want) == gc.end())
+            return fail(HSG_E_INVALID, "group %d (L = %d): tile_y = %d, z_slabs = %d is not one of its z-march geometries",
+                        group, g.L, tile_y, z_slabs);
+        (void)apply_geometry(g, tile_y, z_slabs);
+    }
+    drop_graphs(h);
+    return HSG_OK;
+}
+
+hsg_status hsg_get_geometry(const hsg_lattice *h, int32_t group, int32_t *tile_y, int32_t *z_slabs)
+{
+    if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
+    if (group < 0 || group >= (int32_t)h->lay.g.size())
+        return fail(HSG_E_INVALID, "group = %d, need 0..%zu", group, h->lay.g.size() - 1);
+    const Group &g = h->lay.g[group];
+    if (tile_y) *tile_y = g.stream_ok ? g.s_TY : 0;
+    if (z_slabs) *z_slabs = g.stream_ok ? g.s_zslabs : 0;
+    return HSG_OK;
+}
+
 hsg_status hsg_set_math(hsg_lattice *h, int32_t mode)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
@@ -1439,7 +1635,7 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
         return fail(HSG_E_SIZE, "the trial sweeps would pass the sweep counter limit 2^32");
 
     hipStream_t s = S(stream);
-    const uint64_t t0 = h->t, pt0 = h->pt_calls;
+    const uint64_t t0 = h->t, pt0 = h->pt_calls, n_stats0 = h->n_stats;
     const bool have_e0 = h->have_energies;
     const int32_t var0 = h->kernel_variant, slots0 = h->slots_per_item;
     const bool ov0 = h->overlap;
@@ -1487,11 +1683,58 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
             best_ms = best[k];
             pick = cands[k];
         }
-    for (auto &x : ev)
-        if (x) (void)hipEventDestroy(x);
     h->kernel_variant = st == HSG_OK ? pick.variant : var0;
     h->slots_per_item = st == HSG_OK ? pick.slots : slots0;
     h->overlap = st == HSG_OK ? pick.overlap : ov0;
+    // Second stage, with that choice in force: the z-march geometry (row-band
+    // height and z-slabs) of each lattice size that runs single passes, one
+    // size after the other, the current geometry first and kept unless another
+    // is at least 1 % faster.
+    std::vector<std::pair<int, int>> geo0;
+    for (const Group &g : h->lay.g) geo0.emplace_back(g.s_TY, g.s_zslabs);
+    for (size_t gi = 0; gi < h->lay.g.size() && st == HSG_OK; ++gi) {
+        Group &g = h->lay.g[gi];
+        if (!use_stream(h, g) || use_pair(h, g)) continue;
+        std::vector<std::pair<int, int>> gc = geometry_candidates(g);
+        const std::pair<int, int> cur(g.s_TY, g.s_zslabs);
+        gc.erase(std::remove(gc.begin(), gc.end(), cur), gc.end());
+        gc.insert(gc.begin(), cur);
+        if (gc.size() < 2) continue;
+        if (h->t + need * gc.size() * kRounds > 0x100000000ull) break;  // no room left in the counter map
+        std::vector<float> gbest(gc.size(), -1.0f);
+        for (size_t q = 0; q < kRounds * gc.size() && st == HSG_OK; ++q) {
+            const size_t k = q % gc.size();
+            (void)apply_geometry(g, gc[k].first, gc[k].second);
+            drop_graphs(h);
+            st = hsg_sweep(h, kGraphSweeps + 2, stream);
+            if (st != HSG_OK) break;
+            e = hipEventRecord(ev[0], s);
+            if (e == hipSuccess) st = hsg_sweep(h, n_sweeps, stream);
+            if (st != HSG_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+            if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+            if (e != hipSuccess) {
+                st = hip_fail(e, "autotune: timing");
+                break;
+            }
+            if (gbest[k] < 0.0f || ms < gbest[k]) gbest[k] = ms;
+        }
+        size_t kb = 0;
+        for (size_t k = 1; k < gc.size(); ++k)
+            if (gbest[k] >= 0.0f && gbest[k] < 0.99f * gbest[kb]) kb = k;
+        (void)apply_geometry(g, gc[kb].first, gc[kb].second);
+    }
+    if (st != HSG_OK) {  // on error the previous tuning is kept
+        h->kernel_variant = var0;
+        h->slots_per_item = slots0;
+        h->overlap = ov0;
+        for (size_t gi = 0; gi < h->lay.g.size(); ++gi)
+            (void)apply_geometry(h->lay.g[gi], geo0[gi].first, geo0[gi].second);
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
     drop_graphs(h);
     if (d_backup != nullptr) {
         e = hipMemcpyAsync(h->state, d_backup, h->lay.sz.state_bytes, hipMemcpyDeviceToDevice, s);
@@ -1499,6 +1742,7 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
         if (e != hipSuccess && st == HSG_OK) st = hip_fail(e, "autotune: restoring the state");
         h->t = t0;
         h->pt_calls = pt0;
+        h->n_stats = n_stats0;
         h->have_energies = have_e0;
     }
     if (st != HSG_OK) return st;
@@ -1507,7 +1751,8 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
     return HSG_OK;
 }
 
-hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t tile_z, int32_t n_hit)
+hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_x, int32_t tile_y, int32_t tile_z,
+                         int32_t n_hit)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
     if (chain != 0 && chain != 1) return fail(HSG_E_INVALID, "chain = %d, need 0 or 1", chain);
@@ -1516,7 +1761,7 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
         drop_graphs(h);
         return HSG_OK;
     }
-    if (tile_y < 0 || tile_z < 0) return fail(HSG_E_INVALID, "tile edges must be >= 0");
+    if (tile_x < 0 || tile_y < 0 || tile_z < 0) return fail(HSG_E_INVALID, "tile edges must be >= 0");
     if (n_hit < 1 || n_hit * h->n_hb > 16)
         return fail(HSG_E_INVALID, "n_hit = %d: need n_hit >= 1 and n_hit * n_hb <= 16", n_hit);
     std::vector<Group> gs = h->lay.g;
@@ -1524,24 +1769,32 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
         Group &g = gs[k];
         const int L = g.L;
         if (L % 4 != 0) return fail(HSG_E_UNSUPPORTED, "group %zu: the tile chain needs L %% 4 == 0 (L = %d)", k, L);
-        const int ty = tile_y == 0 ? L : tile_y, tz = tile_z == 0 ? L : tile_z;
-        if (ty > L || tz > L || L % ty != 0 || L % tz != 0)
-            return fail(HSG_E_INVALID, "group %zu: tile edges %d, %d must divide L = %d", k, ty, tz, L);
-        const int by = L / ty, bz = L / tz;
-        if ((by != 1 && (by & 1)) || (bz != 1 && (bz & 1)))
-            return fail(HSG_E_INVALID, "group %zu: L / tile edge must be 1 or even (L = %d, tiles %d, %d)", k, L, ty, tz);
+        const int tx = tile_x == 0 ? L : tile_x, ty = tile_y == 0 ? L : tile_y, tz = tile_z == 0 ? L : tile_z;
+        if (tx > L || ty > L || tz > L || L % tx != 0 || L % ty != 0 || L % tz != 0)
+            return fail(HSG_E_INVALID, "group %zu: tile edges %d, %d, %d must divide L = %d", k, tx, ty, tz, L);
+        if (tx % 4 != 0)
+            return fail(HSG_E_INVALID, "group %zu: the tile edge along x (%d) must be a multiple of 4", k, tx);
+        const int bx = L / tx, by = L / ty, bz = L / tz;
+        if ((bx != 1 && (bx & 1)) || (by != 1 && (by & 1)) || (bz != 1 && (bz & 1)))
+            return fail(HSG_E_INVALID, "group %zu: L / tile edge must be 1 or even (L = %d, tiles %d, %d, %d)", k, L,
+                        tx, ty, tz);
+        g.t_TX = tx;
         g.t_TY = ty;
         g.t_TZ = tz;
+        g.t_BX = bx;
         g.t_BY = by;
         g.t_BZ = bz;
+        g.t_hx = bx > 1 ? 1 : 0;
         g.t_hy = by > 1 ? 1 : 0;
         g.t_hz = bz > 1 ? 1 : 0;
+        g.t_RXh = tx / 2 + 4 * g.t_hx;
         g.t_RY = ty + 2 * g.t_hy;
         g.t_RZ = tz + 2 * g.t_hz;
-        g.t_P = tz * ty * (L / 4);
-        const size_t per_rep = (size_t)2 * 3 * g.t_RZ * g.t_RY * (L / 2) * sizeof(float);
+        g.t_P = tz * ty * (tx / 4);
+        const size_t per_rep = (size_t)2 * 3 * g.t_RZ * g.t_RY * g.t_RXh * sizeof(float);
         if (g.t_P > 1024 || per_rep > 64 * 1024)
-            return fail(HSG_E_UNSUPPORTED, "group %zu: tile %d x %d x %d is too large for one work-group", k, L, ty, tz);
+            return fail(HSG_E_UNSUPPORTED, "group %zu: tile %d x %d x %d is too large for one work-group", k, tx, ty,
+                        tz);
         // replicas per work-group: up to 1024 threads and 64 KiB of LDS
         int rb = std::min<int64_t>(1024 / g.t_P, (int64_t)(64 * 1024 / per_rep));
         rb = std::max(1, std::min(rb, g.O * g.T));
@@ -1552,6 +1805,7 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_y, int32_t 
     }
     h->lay.g = gs;
     h->chain = 1;
+    h->tile_x = tile_x;
     h->tile_y = tile_y;
     h->tile_z = tile_z;
     h->n_hit = n_hit;

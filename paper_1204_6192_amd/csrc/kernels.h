@@ -58,11 +58,13 @@ struct StreamArgs {
     uint32_t key0, key1, uid_base;
 };
 // Tile-local chain: one launch visits every tile of coarse parity `phase` of
-// one group. Tiles are L x TY x TZ sites; BY = L / TY, BZ = L / TZ tiles per
-// axis; hy, hz = 1 when that axis is tiled (one halo row / plane), else 0;
-// RY = TY + 2 hy, RZ = TZ + 2 hz staged rows and planes; P = TZ TY L / 4 site
-// pairs per parity of a tile; RB replicas of one sample per work-group, in
-// n_chunks chunks per sample. Blocks: [sample][tile of the phase][chunk].
+// one group. Tiles are TX x TY x TZ sites; BX = L / TX, BY = L / TY, BZ = L / TZ
+// tiles per axis; hx, hy, hz = 1 when that axis is tiled (a halo of one site
+// row / plane; in x two half-indices on either side, to keep pairs aligned),
+// else 0; RXh = TX / 2 + 4 hx staged half-indices per row, RY = TY + 2 hy rows,
+// RZ = TZ + 2 hz planes; P = TZ TY TX / 4 site pairs per parity of a tile; RB
+// replicas of one sample per work-group, in n_chunks chunks per sample.
+// Blocks: [sample][tile of the phase][chunk].
 struct TileArgs {
     void *spins;
     const float *J6;
@@ -72,7 +74,7 @@ struct TileArgs {
     const float *beta32;
     const uint32_t *tptr;
     int64_t Nh;
-    int32_t L, Lh, TY, TZ, BY, BZ, hy, hz, RY, RZ, P, RB, n_chunks;
+    int32_t L, Lh, TX, TY, TZ, BX, BY, BZ, hx, hy, hz, RXh, RY, RZ, P, RB, n_chunks;
     int32_t phase, n_tiles_phase, n_blocks;
     int32_t n_or, n_hb, n_hit;
     int32_t slots_per_sample, T;
@@ -181,14 +183,34 @@ hipError_t launch_kmodes(const KmodeArgs &a, int storage, hipStream_t s);
 
 // Copy-pair local-overlap sums: partials [D T][n_pb][7 P], q [D T][P][7],
 // P = O (O - 1) / 2 pairs a < b in the order (0,1), (0,2), ..., (1,2), ...
+// q may be nullptr. With chi != nullptr (O >= 4) the sums of copies 0..3 also
+// give the four-replica estimators, chi [D T][4 wave vectors][5]: chi_1, Re and
+// Im chi_2, Re and Im chi_3 (each with the factor N^2 of the double sums).
 struct PairOvArgs {
     const void *spins;
     const int32_t *slot_at_temp;
     double *partials;
     double *q;
+    double *chi;
     int64_t Nh;
     int32_t L, D, O, T, n_pb, chunk;
 };
+
+// Per-sweep record of one group into a caller-owned series: at position
+// p = *tptr - t0 (skipped when p >= capacity), out[p stride + m] holds the
+// energies by rung [D][O][T], then (q != nullptr) q^2 [D][T] from the overlap
+// output q [D][T][10].
+struct SeriesArgs {
+    const int32_t *slot_at_temp;
+    const double *E;
+    const double *q;
+    double *out;
+    const uint32_t *tptr;
+    uint32_t t0;
+    int64_t capacity, stride;
+    int32_t D, O, T;
+};
+hipError_t launch_series(const SeriesArgs &a, hipStream_t s);
 hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s);
 
 hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,

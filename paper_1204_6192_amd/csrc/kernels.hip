@@ -813,16 +813,41 @@ __global__ __launch_bounds__(kBlock) void k_pair_overlaps(PairOvArgs a)
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
-// One block per (sample, rung): output m adds the n_pb partials in order.
+// One block per (sample, rung): output m adds the n_pb partials in order. With
+// chi, four threads then form the four-replica estimators of Eq. (10) from the
+// pair sums of copies 0..3: the double sum over (i, j) of each factorises into
+// N A_ab(k) times N conj(A_cd(k)), so chi_1 = N^2 |A_01|^2, chi_2 = N^2 A_02
+// conj(A_03), chi_3 = N^2 A_02 conj(A_13).
 __global__ __launch_bounds__(256) void k_pair_overlaps_finish(PairOvArgs a)
 {
+    __shared__ double A[7 * 120];
     const int64_t dk = blockIdx.x;
-    const int n = 7 * (a.O * (a.O - 1) / 2);
+    const int O = a.O;
+    const int n = 7 * (O * (O - 1) / 2);
     for (int m = threadIdx.x; m < n; m += blockDim.x) {
         double v = 0.0;
         for (int pb = 0; pb < a.n_pb; ++pb) v += a.partials[(dk * a.n_pb + pb) * (int64_t)n + m];
-        a.q[dk * n + m] = v / (double)(2 * a.Nh);
+        v = v / (double)(2 * a.Nh);
+        if (a.q) a.q[dk * n + m] = v;
+        A[m] = v;
     }
+    if (a.chi == nullptr) return;
+    __syncthreads();
+    const int w = threadIdx.x;
+    if (w >= 4) return;
+    // pair (p, q), p < q, sits at p O - p (p + 1) / 2 + q - p - 1
+    const int i01 = 0, i02 = 1, i03 = 2, i13 = O;
+    auto re = [&](int pair) { return w == 0 ? A[7 * pair] : A[7 * pair + 1 + 2 * (w - 1)]; };
+    auto im = [&](int pair) { return w == 0 ? 0.0 : A[7 * pair + 2 + 2 * (w - 1)]; };
+    const double N = (double)(2 * a.Nh), N2 = N * N;
+    const double r01 = re(i01), m01 = im(i01), r02 = re(i02), m02 = im(i02);
+    const double r03 = re(i03), m03 = im(i03), r13 = re(i13), m13 = im(i13);
+    double *out = a.chi + (dk * 4 + w) * 5;
+    out[0] = N2 * (r01 * r01 + m01 * m01);
+    out[1] = N2 * (r02 * r03 + m02 * m03);
+    out[2] = N2 * (m02 * r03 - r02 * m03);
+    out[3] = N2 * (r02 * r13 + m02 * m13);
+    out[4] = N2 * (m02 * r13 - r02 * m13);
 }
 
 hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s)
@@ -842,6 +867,31 @@ hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_pair_overlaps_finish, dim3((unsigned)((int64_t)a.D * a.T)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- time series
+__global__ __launch_bounds__(256) void k_series(SeriesArgs a)
+{
+    const uint32_t p = *a.tptr - a.t0;
+    if ((int64_t)p >= a.capacity) return;
+    const int64_t nE = (int64_t)a.D * a.O * a.T;
+    const int64_t nq = a.q ? (int64_t)a.D * a.T : 0;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double *out = a.out + (int64_t)p * a.stride;
+    if (g < nE) {
+        const int64_t lad = g / a.T;  // (d, o); g - lad T is the rung
+        out[g] = a.E[lad * a.T + a.slot_at_temp[g]];
+    } else if (g < nE + nq) {
+        out[g] = a.q[(g - nE) * 10 + 9];
+    }
+}
+
+hipError_t launch_series(const SeriesArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.D * a.O * a.T + (a.q ? (int64_t)a.D * a.T : 0);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_series, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,12 +1,13 @@
 // tile_chain.hip -- the tile-local chain of the double checkerboard decomposition.
 //
-// The lattice is cut into tiles of L x TY x TZ sites: whole rows along x (so
-// every row of a tile is one contiguous run of each parity array), TY rows and
-// TZ planes. Tiles carry the coarse parity (Y + Z) mod 2 of their tile
-// coordinates; with L / TY and L / TZ each 1 or even, tiles of one coarse
-// parity never share a face. One launch visits every tile of one coarse
-// parity of every replica of a group. A work-group stages RB replicas of one
-// sample's tile, with a one-site halo in y and z, in LDS (both parities), then
+// The lattice is cut into tiles of TX x TY x TZ sites: whole rows along x
+// (TX = L: every row of a tile is one contiguous run of each parity array) or
+// cubes such as the paper's 8^3 (TX a multiple of 4). Tiles carry the coarse
+// parity (X + Y + Z) mod 2 of their tile coordinates; with L / TX, L / TY and
+// L / TZ each 1 or even, tiles of one coarse parity never share a face. One
+// launch visits every tile of one coarse parity of every replica of a group.
+// A work-group stages RB replicas of one sample's tile, with a one-site halo
+// along every tiled axis, in LDS (both parities), then
 // runs n_hit repetitions of n_or over-relaxation rounds and n_hb heat-bath
 // rounds, a round being the even sites of the tile, then the odd sites (the
 // numbered procedure of the paper's implementation section, with the tile
@@ -75,15 +76,24 @@ __device__ __forceinline__ void load_raw_pair(const typename Codec<STORE>::T *p,
     }
 }
 
-// Tile coordinates (Y, Z) of the q-th tile of coarse parity `phase`, in the
-// order Z, then Y.
-__device__ __forceinline__ void phase_tile(int q, int phase, int BY, int &Y, int &Z)
+// Tile coordinates (X, Y, Z) of the q-th tile of coarse parity `phase`, in the
+// order Z, then Y, then X. The first tiled axis (an even count of tiles) takes
+// the parity; the axes before it hold one tile.
+__device__ __forceinline__ void phase_tile(int q, int phase, int BX, int BY, int &X, int &Y, int &Z)
 {
-    if (BY > 1) {
+    if (BX > 1) {
+        const int per = BX / 2;
+        const int yz = q / per;
+        Y = yz % BY;
+        Z = yz / BY;
+        X = 2 * (q - yz * per) + ((Y + Z + phase) & 1);
+    } else if (BY > 1) {
         const int per = BY / 2;
+        X = 0;
         Z = q / per;
         Y = 2 * (q - Z * per) + ((Z + phase) & 1);
     } else {
+        X = 0;
         Y = 0;
         Z = 2 * q + phase;
     }
@@ -124,12 +134,13 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
     const int rest = b / a.n_chunks;
     const int q = rest % a.n_tiles_phase;
     const int d = rest / a.n_tiles_phase;  // sample
-    int Y, Z;
-    phase_tile(q, a.phase, a.BY, Y, Z);
+    int X, Y, Z;
+    phase_tile(q, a.phase, a.BX, a.BY, X, Y, Z);
     const int y0 = Y * a.TY, z0 = Z * a.TZ;
-    const int L = a.L, Lh = a.Lh, RY = a.RY, RZ = a.RZ;
+    const int L = a.L, Lh = a.Lh, RXh = a.RXh, RY = a.RY, RZ = a.RZ;
+    const int xs = a.hx ? (X * a.TX / 2 - 2 + Lh) % Lh : 0;  // half-index of LDS column 0
     const uint32_t Nh = (uint32_t)a.Nh;
-    const int cs = RZ * RY * Lh;  // floats per component of one parity of one replica
+    const int cs = RZ * RY * RXh;  // floats per component of one parity of one replica
     const int tid = threadIdx.x;
     const int P = a.P;  // site pairs per parity of the tile
     const int rb = tid / P;
@@ -140,7 +151,7 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
     T *base = (T *)a.spins + r * 2 * C::kPlanes * (int64_t)Nh;
 
     // stage the tile and its halo, both parities, of every replica of the block
-    const int Lq = Lh / 2;  // site pairs per row and parity
+    const int Lq = RXh / 2;  // staged site pairs per row and parity
     const int n_pairs = a.RB * 2 * RZ * RY * Lq;
     for (int e = tid; e < n_pairs; e += blockDim.x) {
         int k = e;
@@ -158,14 +169,18 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
         z = z < 0 ? z + L : (z >= L ? z - L : z);
         const int64_t rep = (int64_t)d * a.slots_per_sample + chunk * a.RB + rr;
         const T *src = (const T *)a.spins + (rep * 2 + par) * C::kPlanes * (int64_t)Nh;
+        int xh = xs + 2 * xp;  // even, so the pair does not straddle the periodic wrap
+        xh = xh >= Lh ? xh - Lh : xh;
         v3 s0, s1;
-        C::load_pair(src, Nh, (uint32_t)((z * L + y) * Lh + 2 * xp), s0, s1);
-        lds_put_pair(lds, ((rr * 2 + par) * 3 * RZ + lz) * RY * Lh + ly * Lh + 2 * xp, cs, s0, s1);
+        C::load_pair(src, Nh, (uint32_t)((z * L + y) * Lh + xh), s0, s1);
+        lds_put_pair(lds, ((rr * 2 + par) * 3 * RZ + lz) * RY * RXh + ly * RXh + 2 * xp, cs, s0, s1);
     }
 
     // my pair, its couplings and field (both parities)
-    const int xh0 = 2 * (qp % Lq);
-    const int lyi = (qp / Lq) % a.TY, lzi = qp / (Lq * a.TY);
+    const int TXq = a.TX / 4;  // site pairs per tile row and parity
+    const int lx0 = 2 * (qp % TXq) + 2 * a.hx;  // my first half-index in the LDS row
+    const int xh0 = X * a.TX / 2 + 2 * (qp % TXq);
+    const int lyi = (qp / TXq) % a.TY, lzi = qp / (TXq * a.TY);
     const int y = y0 + lyi, z = z0 + lzi;
     const int ly = lyi + a.hy, lz = lzi + a.hz;
     const int lym = ly == 0 ? RY - 1 : ly - 1, lyp = ly + 1 == RY ? 0 : ly + 1;  // wrap only without halo
@@ -203,18 +218,20 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
     const uint32_t tsweep = *a.tptr;
     __syncthreads();
 
-    auto at = [&](int par, int pz, int py, int xh) { return ((rb * 2 + par) * 3 * RZ + pz) * RY * Lh + py * Lh + xh; };
+    auto at = [&](int par, int pz, int py, int lx) { return ((rb * 2 + par) * 3 * RZ + pz) * RY * RXh + py * RXh + lx; };
     auto rd = [&](int w) { return v3{lds[w], lds[w + cs], lds[w + 2 * cs]}; };
     auto half_round = [&](int kind, int p, uint32_t rep) {
         if (active) {
             const int qo = 1 - p;
             const int o = (y + z + p) & 1;  // x = 2 x/2 + o on this row
-            const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
-            const v3 c0 = rd(at(qo, lz, ly, xh0)), c1 = rd(at(qo, lz, ly, xh0 + 1)), ex = rd(at(qo, lz, ly, xe));
-            const v3 ym0 = rd(at(qo, lz, lym, xh0)), ym1 = rd(at(qo, lz, lym, xh0 + 1));
-            const v3 yp0 = rd(at(qo, lz, lyp, xh0)), yp1 = rd(at(qo, lz, lyp, xh0 + 1));
-            const v3 zm0 = rd(at(qo, lzm, ly, xh0)), zm1 = rd(at(qo, lzm, ly, xh0 + 1));
-            const v3 zp0 = rd(at(qo, lzp, ly, xh0)), zp1 = rd(at(qo, lzp, ly, xh0 + 1));
+            // the x-neighbour that is not one of my two positions (periodic only
+            // when the row is whole; with a halo it lies inside the staged row)
+            const int xe = o ? (lx0 + 2 == RXh ? 0 : lx0 + 2) : (lx0 == 0 ? RXh - 1 : lx0 - 1);
+            const v3 c0 = rd(at(qo, lz, ly, lx0)), c1 = rd(at(qo, lz, ly, lx0 + 1)), ex = rd(at(qo, lz, ly, xe));
+            const v3 ym0 = rd(at(qo, lz, lym, lx0)), ym1 = rd(at(qo, lz, lym, lx0 + 1));
+            const v3 yp0 = rd(at(qo, lz, lyp, lx0)), yp1 = rd(at(qo, lz, lyp, lx0 + 1));
+            const v3 zm0 = rd(at(qo, lzm, ly, lx0)), zm1 = rd(at(qo, lzm, ly, lx0 + 1));
+            const v3 zp0 = rd(at(qo, lzp, ly, lx0)), zp1 = rd(at(qo, lzp, ly, lx0 + 1));
             v3 nb0[6], nb1[6];  // neighbours in the order +x, -x, +y, -y, +z, -z
             if (o) {
                 nb0[0] = c1; nb0[1] = c0;
@@ -227,7 +244,7 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
             nb0[3] = ym0; nb1[3] = ym1;
             nb0[4] = zp0; nb1[4] = zp1;
             nb0[5] = zm0; nb1[5] = zm1;
-            const int w = at(p, lz, ly, xh0);
+            const int w = at(p, lz, ly, lx0);
             v3 s0, s1;
             if (kind == 1) {
                 const v3 old0 = rd(w), old1 = rd(w + 1);
@@ -269,7 +286,7 @@ __global__ __launch_bounds__(1024) void k_tile_visit(TileArgs a)
                 s0 = own_raw[par][0];
                 s1 = own_raw[par][1];
             } else {
-                lds_get_pair(lds, at(par, lz, ly, xh0), cs, s0, s1);
+                lds_get_pair(lds, at(par, lz, ly, lx0), cs, s0, s1);
             }
             C::store_pair(base + (int64_t)par * C::kPlanes * Nh, Nh, j0, s0, s1);
         }

@@ -96,12 +96,17 @@ _SIG = {
     "hsg_autotune": [_vp, _i32, _vp, _vp, _vp, _vp],
     "hsg_measure_pair_overlaps": [_vp, _vp, _vp],
     "hsg_measure_kmodes": [_vp, _vp, _vp],
+    "hsg_measure_chi": [_vp, _vp, _vp],
+    "hsg_set_series": [_vp, _vp, _i64, _vp],
+    "hsg_get_series_count": [_vp, _vp],
     "hsg_set_batch": [_vp, _i64],
     "hsg_set_stats": [_vp, _i32],
     "hsg_reset_stats": [_vp, _vp],
     "hsg_get_stats": [_vp, _vp, _vp, _vp, _vp],
-    "hsg_set_chain": [_vp, _i32, _i32, _i32, _i32],
+    "hsg_set_chain": [_vp, _i32, _i32, _i32, _i32, _i32],
     "hsg_set_math": [_vp, _i32],
+    "hsg_set_geometry": [_vp, _i32, _i32, _i32],
+    "hsg_get_geometry": [_vp, _i32, _vp, _vp],
     "hsg_set_graphs": [_vp, _i32],
     "hsg_sync": [_vp, _vp],
     "hsg_debug_philox": [_vp, _vp, _vp, _i64, _vp],
@@ -264,6 +269,39 @@ class Lattice:
         check(lib.hsg_measure_pair_overlaps(self.h, _ptr(q), _stream(self.stream)))
         return q
 
+    def measure_chi(self, out=None):
+        """[sum over groups of n_samples * n_temps * 4 * 5] float64: chi_1, Re chi_2,
+        Im chi_2, Re chi_3, Im chi_3 of Eq. (10) for k = 0, k_x, k_y, k_z (copies
+        0..3; layout in hsg_measure_chi)."""
+        n = sum(g.n_samples * g.n_temps * 20 for g in self.groups)
+        q = out if out is not None else self.torch.empty(n, dtype=self.torch.float64,
+                                                          device=self.device)
+        check(lib.hsg_measure_chi(self.h, _ptr(q), _stream(self.stream)))
+        return q
+
+    def set_series(self, capacity: int):
+        """Record every following sweep (energies by rung, q^2 by rung) into a new
+        device buffer of `capacity` records; 0 switches the series off. Returns
+        the buffer, [capacity, record] float64, or None."""
+        if capacity <= 0:
+            check(lib.hsg_set_series(self.h, None, 0, None))
+            self.series = None
+            return None
+        rec = sum(g.n_samples * g.n_copies * g.n_temps + (g.n_samples * g.n_temps if g.n_copies >= 2 else 0)
+                  for g in self.groups)
+        buf = self.torch.full((int(capacity), rec), float("nan"), dtype=self.torch.float64,
+                              device=self.device)
+        n = C.c_int64()
+        check(lib.hsg_set_series(self.h, _ptr(buf), int(capacity), C.byref(n)))
+        assert n.value == rec
+        self.series = buf
+        return buf
+
+    def get_series_count(self) -> int:
+        n = C.c_int64()
+        check(lib.hsg_get_series_count(self.h, C.byref(n)))
+        return int(n.value)
+
     def get_spins(self):
         s = self.torch.empty(self.n_spins * 3, dtype=self.torch.float32, device=self.device)
         check(lib.hsg_get_spins(self.h, _ptr(s), _stream(self.stream)))
@@ -329,10 +367,10 @@ class Lattice:
         del backup
         return v.value, c.value
 
-    def set_chain(self, chain: int, tile_y: int = 0, tile_z: int = 0, n_hit: int = 1) -> None:
+    def set_chain(self, chain: int, tile_y: int = 0, tile_z: int = 0, n_hit: int = 1, tile_x: int = 0) -> None:
         """0: full-lattice checkerboard (default); 1: the tile-local chain with tiles
-        of L x tile_y x tile_z sites (0 = L) and n_hit repetitions per visit."""
-        check(lib.hsg_set_chain(self.h, int(chain), int(tile_y), int(tile_z), int(n_hit)))
+        of tile_x x tile_y x tile_z sites (0 = L) and n_hit repetitions per visit."""
+        check(lib.hsg_set_chain(self.h, int(chain), int(tile_x), int(tile_y), int(tile_z), int(n_hit)))
 
     def set_batch(self, replicas: int) -> None:
         """Replicas per sweep batch: -1 off, 0 automatic, > 0 explicit."""
@@ -353,6 +391,16 @@ class Lattice:
         n = C.c_uint64()
         check(lib.hsg_get_stats(self.h, _ptr(sums), _ptr(trips), C.byref(n), _stream(self.stream)))
         return sums, trips, int(n.value)
+
+    def set_geometry(self, group: int, tile_y: int = 0, z_slabs: int = 0) -> None:
+        """z-march rows per work-group and z-slabs of group `group` (0, 0: default)."""
+        check(lib.hsg_set_geometry(self.h, int(group), int(tile_y), int(z_slabs)))
+
+    def get_geometry(self, group: int):
+        """(rows per work-group, z-slabs) of the z-march of group `group`."""
+        ty, zs = C.c_int32(), C.c_int32()
+        check(lib.hsg_get_geometry(self.h, int(group), C.byref(ty), C.byref(zs)))
+        return ty.value, zs.value
 
     def set_math(self, mode: int) -> None:
         """0: library transcendentals in the heat bath (default); 1: hardware ones."""

@@ -164,6 +164,9 @@ CONFIGS = {
                    couplings="gaussian", field=None, storage="bf16", sweeps=0, k=3),
     "large": dict(groups=[dict(L=128, n_samples=1, t=(0.10, 0.30, 32))],
                   couplings="bimodal", field=None, storage="qangle", sweeps=0, k=4),
+    # the paper's timing workload: 256 systems of L = 32 at T = 100 (one rung)
+    "table1": dict(groups=[dict(L=32, n_samples=128, t=(100.0, 100.0, 1))],
+                   couplings="gaussian", field=None, storage="f32", sweeps=0, k=5),
 }
 
 
