@@ -43,15 +43,49 @@ def test_unfused_and_compressed_bytes():
     assert bench.algorithmic_bytes([gb], "qangle", 1) == 64 * 128 ** 3 * 12 + 128 ** 3 * 1
 
 
+def test_method_bytes_per_update():
+    """The method's bytes per update (one HBM pass per half-sweep: 2 b_s per
+    heat-bath update, 3 b_s per over-relaxation update, couplings and field once
+    per sample per half-sweep) for 1 HB + 4 OR: batched float32 33.975 B; the
+    random field at float16 17.55 B; the uneven batch at bfloat16 17.55 B; the
+    large system with quantised angles and one sign bit per bond 11.21 B; and
+    36.375 B per over-relaxation update of the batched workload."""
+    g = _group(32, 64, 2, 32)
+    assert bench.method_bytes_per_update([g], "f32", 1, 4) == pytest.approx(33.6 + 24 / 64, rel=1e-12)
+    assert bench.method_bytes_per_update([g], "f32", 1, 4, kind=1) == pytest.approx(36 + 24 / 64, rel=1e-12)
+    f = _group(64, 16, 2, 24, field=True)
+    assert bench.method_bytes_per_update([f], "f16", 1, 4) == pytest.approx(16.8 + 36 / 48, rel=1e-12)
+    un = [_group(L, 32, 2, 16) for L in (12, 16, 24, 32, 48)]
+    assert bench.method_bytes_per_update(un, "bf16", 1, 4) == pytest.approx(16.8 + 24 / 32, rel=1e-12)
+    lg = _group(128, 1, 2, 32, coupling_kind=1)
+    assert bench.method_bytes_per_update([lg], "qangle", 1, 4) == pytest.approx(11.2 + 0.75 / 64, rel=1e-12)
+
+
+def test_fusion_follows_the_kernel_variant():
+    """The fused-pair and two-pair accounting applies only where the chosen
+    kernel variant runs those kernels."""
+    g = _group(32, 64, 2, 32)
+    assert bench.fused(g, 0) and bench.fused(g, 3) and bench.fused(g, 4)
+    assert not bench.fused(g, 1) and not bench.fused(g, 2)
+    assert not bench.fused(_group(36, 1, 2, 2), 4)
+    assert bench.quad([g], 4, "f32", 4) and bench.quad([g], 0, "f32", 4) and bench.quad([g], 4, "qangle", 4)
+    assert not bench.quad([g], 0, "qangle", 4) and not bench.quad([g], 3, "f32", 4)
+    assert not bench.quad([g], 4, "f32", 1)
+    N, R, D = 32 ** 3, 4096, 64
+    assert bench.algorithmic_bytes([g], "f32", 1, variant=2) == R * N * 36 + D * N * 24
+
+
 def test_flop_count_and_ridge():
     """90 FP32 flops per over-relaxation update (an FMA counting two): the local
     field 18 FMA, h.h and s.h (a product and two FMA each), 2 (s.h) times the
     reciprocal, the reflection 3 FMA and the compensated renormalisation (36).
-    Both over-relaxation kernels of the batched workload lie below the ridge of
-    the published peaks."""
+    The ridge uses the FP32 vector peak without packed instructions (78.6
+    TFLOP/s: 256 CUs x 64 lanes x 2 flops x 2.4 GHz), as the library is built.
+    Both over-relaxation kernels of the batched workload lie below it."""
     assert bench.OR_FLOPS_PER_UPDATE == 36 + 5 + 5 + 2 + 6 + 36 == 90
+    assert bench.PEAK_FP32_TFLOPS == pytest.approx(256 * 64 * 2 * 2.4e9 / 1e12, rel=1e-3)
     ridge = bench.PEAK_FP32_TFLOPS * 1e12 / (bench.PEAK_HBM_GBS * 1e9)
-    assert ridge == pytest.approx(19.66, rel=1e-3)
+    assert ridge == pytest.approx(9.825, rel=1e-3)
     g = _group(32, 64, 2, 32)
     upd = g.n_slots * g.N
     assert 2 * upd * 90 / bench.or_bytes_two_pairs([g], "f32") < ridge
