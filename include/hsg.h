@@ -162,6 +162,19 @@ hsg_status hsg_pt_exchange(hsg_lattice *h, hsg_stream_t stream);
  * a following hsg_pt_exchange uses. */
 hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream);
 
+/* hsg_measure_energy without the caller's scratch buffer, for callers that
+ * cannot allocate device memory (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc). Same kernels and results, bit for
+ * bit; the per-work-group float64 partials go to a fixed device array of
+ * 16 MiB inside the library, one per device, held until the process ends.
+ * Allocates nothing (no hipMalloc, hipFree or allocating library call). Every
+ * call on a device shares that array: calls that overlap on one device (other
+ * streams, other handles, other threads) race and must be ordered by the
+ * caller. The partials need n_replicas of the largest group x ceil(L^3 / 512)
+ * x 8 bytes; HSG_E_SIZE when that exceeds 16 MiB, HSG_E_INVALID for a NULL
+ * handle or d_E. */
+hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t stream);
+
 /* Copy the energies computed at the end of the last sweep into d_E [n_replicas]. */
 hsg_status hsg_get_energies(const hsg_lattice *h, double *d_E, hsg_stream_t stream);
 

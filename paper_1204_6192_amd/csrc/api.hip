@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -43,7 +44,35 @@ hsg_status hip_fail(hipError_t e, const char *what)
 constexpr uint64_t kAlign = 256;
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+}  // namespace
 
+// Fixed device scratch of the allocation-free energy measurement
+// (hsg_measure_energy_static): one copy per device, held until the process
+// ends. In host code `scratch` only names the symbol; its device address comes
+// from hipGetSymbolAddress, resolved once per device (static_scratch_ptr).
+constexpr size_t kStaticScratchBytes = 16u << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (current), resolved on first use.
+hipError_t static_scratch_ptr(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 // Bytes of stored spin per site: 3 float32, 3 x 16-bit, or one 32-bit angle word.
 int bytes_per_spin(int storage)
@@ -300,6 +329,7 @@ struct hsg_lattice {
     // over-relaxation pairs fused two by two
     int32_t kernel_variant = 0;
     size_t max_lds = 64 * 1024;  // LDS bytes per work-group the device allows
+    int device = 0;              // the device current at init (the buffers live there)
     bool hw_math = false;        // heat bath with the hardware transcendentals (kernel kind 2)
     int64_t batch = -1;   // replicas per sweep batch: -1 off, 0 automatic (about 192 MiB of spins)
     bool stats = false;   // accumulate run statistics after every sweep
@@ -966,9 +996,17 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
     h->scratch = static_cast<char *>(d_scratch);
     {
         int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess &&
             hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
             h->max_lds = (size_t)v;
+        h->device = dev;
+        void *p = nullptr;
+        if (e == hipSuccess) e = static_scratch_ptr(dev, &p);  // once per device, with the device current
+        if (e != hipSuccess) {
+            delete h;
+            return hip_fail(e, "init: device scratch address");
+        }
     }
     hipStream_t s = S(stream);
     {
@@ -1270,6 +1308,42 @@ hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream)
         if (e == hipSuccess)
             e = hipMemcpyAsync(d_E + g.rep0, E, (size_t)g.n_rep * 8, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return hip_fail(e, "measure_energy");
+    }
+    h->have_energies = true;
+    return HSG_OK;
+}
+
+hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t stream)
+{
+    if (h == nullptr || d_E == nullptr) return fail(HSG_E_INVALID, "handle and d_E are required");
+    for (const Group &g : h->lay.g) {
+        const uint64_t need = (uint64_t)g.n_rep * g.n_pb_site * sizeof(double);
+        if (need > kStaticScratchBytes)
+            return fail(HSG_E_SIZE, "group of L = %d needs %llu bytes of energy partials, the fixed scratch holds %zu",
+                        g.L, (unsigned long long)need, kStaticScratchBytes);
+    }
+    void *p = nullptr;
+    hipError_t e = static_scratch_ptr(h->device, &p);
+    if (e != hipSuccess) return hip_fail(e, "measure_energy_static: device scratch address");
+    hipStream_t s = S(stream);
+    for (const Group &g : h->lay.g) {  // the groups run one after the other on the stream: one region suffices
+        hsg::EnergyArgs a{};
+        a.spins = h->state + g.o_spins;
+        a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+        a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+        a.partials = static_cast<double *>(p);
+        a.Nh = g.Nh;
+        a.n_rep = g.n_rep;
+        a.L = g.L;
+        a.Lh = g.L / 2;
+        a.slots_per_sample = g.O * g.T;
+        a.n_pb = g.n_pb_site;
+        e = hsg::launch_energy(a, h->storage, s);
+        double *E = reinterpret_cast<double *>(h->state + g.o_E);
+        if (e == hipSuccess) e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, E, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_E + g.rep0, E, (size_t)g.n_rep * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "measure_energy_static");
     }
     h->have_energies = true;
     return HSG_OK;

@@ -80,6 +80,7 @@ _SIG = {
     "hsg_or_pairs": [_vp, _i32, _vp],
     "hsg_pt_exchange": [_vp, _vp],
     "hsg_measure_energy": [_vp, _vp, _vp],
+    "hsg_measure_energy_static": [_vp, _vp, _vp],
     "hsg_get_energies": [_vp, _vp, _vp],
     "hsg_measure_overlap": [_vp, _vp, _vp],
     "hsg_get_spins": [_vp, _vp, _vp],
@@ -233,6 +234,14 @@ class Lattice:
     def measure_energy(self):
         E = self.torch.empty(self.n_replicas, dtype=self.torch.float64, device=self.device)
         check(lib.hsg_measure_energy(self.h, _ptr(E), _stream(self.stream)))
+        return E
+
+    def measure_energy_static(self, out=None):
+        """hsg_measure_energy through the library's fixed device scratch (no
+        caller scratch, no allocation inside the call)."""
+        E = out if out is not None else self.torch.empty(self.n_replicas, dtype=self.torch.float64,
+                                                          device=self.device)
+        check(lib.hsg_measure_energy_static(self.h, _ptr(E), _stream(self.stream)))
         return E
 
     def get_energies(self):
