@@ -63,15 +63,16 @@ def log(*a):
 
 def fused(g, variant=0):
     """Both half-sweeps of a pair run as one z-march when the kernel variant allows
-    it (0 automatic, 3, 4) and the whole plane fits a work-group (L <= 32)."""
-    return variant in (0, 3, 4) and g.L % 4 == 0 and g.L * g.L // 4 <= 256
+    it (0 automatic, 3, 4, and 5, whose per-call passes run as 4) and the whole
+    plane fits a work-group (L <= 32)."""
+    return variant in (0, 3, 4, 5) and g.L % 4 == 0 and g.L * g.L // 4 <= 256
 
 
 def quad(groups, variant, storage, n_or):
-    """Two over-relaxation pairs run as one z-march in every group: variant 4, or
+    """Two over-relaxation pairs run as one z-march in every group: variant 4 (or 5), or
     the automatic choice except for quantised angles (whose two-pair launch is
     slower than two fused pairs), where every pair fuses."""
-    if n_or < 2 or not (variant == 4 or (variant == 0 and storage != "qangle")):
+    if n_or < 2 or not (variant in (4, 5) or (variant == 0 and storage != "qangle")):
         return False
     return all(fused(g, variant) for g in groups)
 
@@ -462,7 +463,7 @@ def main():
                     help="before the timed run, time every launch choice over this many sweeps "
                          "(hsg_autotune, the state restored afterwards) and keep the fastest; "
                          "0 = the library's default choice")
-    ap.add_argument("--kernel-variant", type=int, default=None, choices=[0, 1, 2, 3, 4],
+    ap.add_argument("--kernel-variant", type=int, default=None, choices=[0, 1, 2, 3, 4, 5],
                     help="fix the kernel variant (hsg_set_kernel) after any tuning")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -96,7 +96,7 @@ typedef struct {
     int32_t n_groups;             /* 1..64 */
     int32_t storage;              /* HSG_STORE_* */
     int32_t n_hb;                 /* heat-bath half-sweep pairs per sweep, 0..16 */
-    int32_t n_or;                 /* over-relaxation pairs per sweep, 0..64; n_hb + n_or >= 1 */
+    int32_t n_or;                 /* over-relaxation pairs per sweep, 0..1000; n_hb + n_or >= 1 */
     int32_t pt_every;             /* tempering after every pt_every-th sweep; 0 = never */
     int32_t reserved;             /* must be 0 */
     uint64_t seed;                /* Philox key */
@@ -283,9 +283,16 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item);
  * pair in one launch where the whole plane fits a work-group (L <= 32), else
  * as 2; 4 = as 3, and the over-relaxation pairs of a sweep two by two in one
  * launch (four half-sweeps per read and write of the spins) where eleven
- * staged planes fit the work-group's LDS; 0 = automatic (currently 4, but 3
- * for quantised-angle storage, whose two-pair launch is slower than two fused
- * pairs). */
+ * staged planes fit the work-group's LDS; 5 = where every replica of a sample
+ * of every lattice size fits one work-group's LDS (L <= 12; the paper's
+ * per-block shared-memory tiles, Sec. 3.1, taken to a whole sample) and no
+ * series is recorded, hsg_sweep runs whole sweeps in one launch (up to 256
+ * per launch), a sample per work-group: the half-sweeps, the energies, the
+ * tempering walk (Eq. (4)) and the statistics, the spins staying in LDS;
+ * otherwise, and for the per-call entry points, as 4; 0 = automatic
+ * (currently 4, but 3 for quantised-angle storage, whose two-pair launch is
+ * slower than two fused pairs). Energies computed in a variant-5 launch equal
+ * the others' to rounding (another summation order). */
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant);
 
 /* Tuning (results do not depend on it): 1 = where every lattice size runs
@@ -373,8 +380,9 @@ hsg_status hsg_set_chain(hsg_lattice *h, int32_t chain, int32_t tile_x, int32_t 
  * times the z-march geometries of hsg_set_geometry for every lattice size that
  * runs single passes, one size after the other, the current geometry first
  * and replaced only by one at least 1 % faster (hsg_get_geometry reports the
- * result). Every variant computes the same
- * bits, so the trial sweeps are ordinary sweeps of the chain: with
+ * result). Every variant computes the same spins and temperature maps bit
+ * for bit (variant 5 the energies to rounding, another summation order), so
+ * the trial sweeps are ordinary sweeps of the chain: with
  * d_backup == NULL the chain advances by them (2 (n_sweeps + 10) per candidate);
  * with d_backup (device, state_bytes of hsg_query_sizes, 256-byte aligned,
  * caller-owned) the state is saved first and restored afterwards, so the chain

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsg.so")
 SOURCES = ["api.hip", "kernels.hip", "sweep_stream.hip", "sweep_stream_s0.hip", "sweep_stream_s1.hip",
-           "sweep_stream_s2.hip", "sweep_stream_s3.hip", "tile_chain.hip"]
+           "sweep_stream_s2.hip", "sweep_stream_s3.hip", "tile_chain.hip", "resident.hip"]
 ARCH = os.environ.get("HSG_OFFLOAD_ARCH", "gfx950")
 
 

@@ -198,7 +198,7 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
     if (desc->storage < HSG_STORE_F32 || desc->storage > HSG_STORE_QANGLE)
         return fail(HSG_E_INVALID, "storage = %d is not an HSG_STORE_* value", desc->storage);
     if (desc->n_hb < 0 || desc->n_hb > 16) return fail(HSG_E_SIZE, "n_hb = %d, need 0..16", desc->n_hb);
-    if (desc->n_or < 0 || desc->n_or > 64) return fail(HSG_E_SIZE, "n_or = %d, need 0..64", desc->n_or);
+    if (desc->n_or < 0 || desc->n_or > 1000) return fail(HSG_E_SIZE, "n_or = %d, need 0..1000", desc->n_or);
     if (desc->n_hb + desc->n_or < 1) return fail(HSG_E_INVALID, "a sweep needs n_hb + n_or >= 1");
     if (desc->pt_every < 0) return fail(HSG_E_INVALID, "pt_every = %d < 0", desc->pt_every);
     lay.g.clear();
@@ -432,7 +432,7 @@ size_t fused_lds_bytes(const Group &g, int fuse)
 // eleven staged planes fit the work-group's LDS.
 bool use_quad(const hsg_lattice *h, const Group &g)
 {
-    if (h->kernel_variant != 0 && h->kernel_variant != 4) return false;
+    if (h->kernel_variant != 0 && h->kernel_variant != 4 && h->kernel_variant != 5) return false;
     // automatic choice: quantised angles are decoded and re-encoded at every
     // stage, which costs the two-pair launch more than the bytes it saves
     if (h->kernel_variant == 0 && h->storage == HSG_STORE_QANGLE) return false;
@@ -641,6 +641,75 @@ int64_t batch_of(const hsg_lattice *h, const Group &g)
     return b < g.n_rep ? b : 0;
 }
 
+
+// Threads and replica groups of the resident launch for group g: G replica
+// groups of Nh / 2 threads each, at most 512 threads; 0 when a sample does
+// not fit.
+unsigned resident_threads(const hsg_lattice *h, const Group &g, int32_t *groups)
+{
+    const int64_t Q = g.Nh / 2;
+    const int R = g.O * g.T;
+    if (Q < 1 || Q > 512) return 0;
+    if (hsg::resident_lds_bytes(h->storage, g.Nh, R) > h->max_lds) return 0;
+    const int G = (int)std::min<int64_t>(R, 512 / Q);
+    if (groups) *groups = G;
+    return (unsigned)((G * Q + 63) / 64 * 64);
+}
+
+// Whole sweeps a sample per work-group with the spins in LDS (kernel variant
+// 5), where every lattice size allows it and no per-sweep series is recorded.
+bool use_resident(const hsg_lattice *h)
+{
+    if (h->kernel_variant != 5 || h->chain != 0 || h->series != nullptr) return false;
+    for (const Group &g : h->lay.g)
+        if (resident_threads(h, g, nullptr) == 0) return false;
+    return true;
+}
+
+// n sweeps of every group with the resident kernel, then the device counter.
+hsg_status run_resident(hsg_lattice *h, int32_t n, hipStream_t s)
+{
+    for (const Group &g : h->lay.g) {
+        hsg::ResidentArgs a{};
+        int32_t G = 1;
+        const unsigned threads = resident_threads(h, g, &G);
+        a.spins = h->state + g.o_spins;
+        a.J6 = reinterpret_cast<const float *>(h->coup + g.o_J6);
+        a.Hp = g.field ? reinterpret_cast<const float *>(h->field + g.o_H) : nullptr;
+        a.slot_at_temp = reinterpret_cast<int32_t *>(h->state + g.o_sat);
+        a.temp_of_slot = reinterpret_cast<int32_t *>(h->state + g.o_tos);
+        a.E = reinterpret_cast<double *>(h->state + g.o_E);
+        a.beta32 = reinterpret_cast<const float *>(h->coup + g.o_b32);
+        a.beta64 = reinterpret_cast<const double *>(h->coup + g.o_b64);
+        a.accepts = reinterpret_cast<unsigned long long *>(h->state + g.o_acc);
+        a.stat_sum = reinterpret_cast<double *>(h->state + g.o_ssum);
+        a.stat_flag = reinterpret_cast<int32_t *>(h->state + g.o_sflag);
+        a.stat_trips = reinterpret_cast<uint32_t *>(h->state + g.o_strips);
+        a.tptr = dev_counter(h);
+        a.Nh = g.Nh;
+        a.L = g.L;
+        a.Lh = g.L / 2;
+        a.D = g.D;
+        a.O = g.O;
+        a.T = g.T;
+        a.slots_per_sample = g.O * g.T;
+        a.groups = G;
+        a.n_sweeps = n;
+        a.n_hb = h->n_hb;
+        a.n_or = h->n_or;
+        a.pt_every = h->pt_every;
+        a.stats = h->stats ? 1 : 0;
+        a.key0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+        a.key1 = (uint32_t)(h->seed >> 32);
+        a.uid_base = g.uid_base;
+        const size_t lds = hsg::resident_lds_bytes(h->storage, g.Nh, g.O * g.T);
+        const hipError_t e = hsg::launch_resident(a, h->storage, g.field, h->hw_math, threads, lds, s);
+        if (e != hipSuccess) return hip_fail(e, "resident sweep launch");
+    }
+    const hipError_t e = hsg::launch_set_u32(dev_counter(h), (uint32_t)(h->t + (uint64_t)n), s);
+    if (e != hipSuccess) return hip_fail(e, "counter launch");
+    return HSG_OK;
+}
 
 // purpose 1: in-sweep pass, counter read from the device; 2: standalone pass.
 hsg_status run_pt(hsg_lattice *h, uint32_t ctr1, uint32_t purpose, hipStream_t s)
@@ -1083,7 +1152,7 @@ hsg_status hsg_init_lattice(const hsg_desc *desc, const float *d_spins0, const f
 // the same counters as in one stream, so the results are the same bits.
 bool overlap_ok(const hsg_lattice *h)
 {
-    if (!h->overlap || h->chain != 0 || h->series != nullptr) return false;
+    if (!h->overlap || h->chain != 0 || h->series != nullptr || use_resident(h)) return false;
     for (const Group &g : h->lay.g) {
         if (!use_stream(h, g) || g.D < 2 || batch_of(h, g) > 0) return false;
     }
@@ -1223,7 +1292,16 @@ hsg_status hsg_sweep(hsg_lattice *h, int32_t n_sweeps, hsg_stream_t stream)
     hipStream_t s = S(stream);
     const bool graphs = h->use_graphs && h->pt_every <= 1;
     int done = 0;
-    if (n_sweeps > 0 && overlap_ok(h)) {
+    if (n_sweeps > 0 && use_resident(h)) {
+        constexpr int kMaxPerLaunch = 256;  // bounded launches for long runs
+        while (done < n_sweeps) {
+            const int n = std::min(kMaxPerLaunch, n_sweeps - done);
+            hsg_status st = run_resident(h, n, s);
+            if (st != HSG_OK) return st;
+            done += n;
+            h->t += (uint64_t)n;
+        }
+    } else if (n_sweeps > 0 && overlap_ok(h)) {
         hsg_status st = overlapped_sweeps(h, n_sweeps, s);
         if (st != HSG_OK) return st;
         done = n_sweeps;
@@ -1596,7 +1674,7 @@ hsg_status hsg_set_tuning(hsg_lattice *h, int32_t slots_per_item)
 hsg_status hsg_set_kernel(hsg_lattice *h, int32_t variant)
 {
     if (h == nullptr) return fail(HSG_E_INVALID, "handle is NULL");
-    if (variant < 0 || variant > 4) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..4", variant);
+    if (variant < 0 || variant > 5) return fail(HSG_E_INVALID, "kernel variant = %d, need 0..5", variant);
     h->kernel_variant = variant;
     drop_graphs(h);
     return HSG_OK;
@@ -1693,6 +1771,13 @@ hsg_status hsg_autotune(hsg_lattice *h, int32_t n_sweeps, void *d_backup, int32_
             cands.push_back({v, 0, false});
         if (any_stream) cands.push_back({v, gather_used ? slot_opts.back() : 0, true});
     };
+    {
+        const int32_t v0 = h->kernel_variant;
+        h->kernel_variant = 5;
+        const bool resident = use_resident(h);
+        h->kernel_variant = v0;
+        if (resident) cands.push_back({5, 0, false});
+    }
     if (any_pair) {
         const int32_t v0 = h->kernel_variant;
         h->kernel_variant = 4;

@@ -54,6 +54,7 @@ struct StreamArgs {
     int32_t n_zslabs, zlen;
     int32_t slots_per_sample, T;
     const uint32_t *tptr;  // device sweep counter
+    uint32_t t_offset;     // added to it (sweeps of a persistent launch; 0 otherwise)
     uint32_t rep, parity;
     uint32_t key0, key1, uid_base;
 };
@@ -130,6 +131,36 @@ struct StatsArgs {
     int32_t D, O, T;
 };
 hipError_t launch_stats(const StatsArgs &a, bool clear, hipStream_t s);
+
+
+// Whole sweeps of small lattices, a sample per work-group with its spins in LDS
+// (resident.hip): n_sweeps sweeps of the D samples of one group, each with
+// n_hb heat-bath pairs, n_or over-relaxation pairs, the energy of the last
+// pass, tempering when (t + 1) % pt_every == 0 and (stats) the run statistics;
+// t = *tptr + i for sweep i. The caller advances the device counter. `groups`
+// replica groups of Nh / 2 threads each; launch with groups * Nh / 2 <= threads.
+struct ResidentArgs {
+    void *spins;
+    const float *J6;
+    const float *Hp;
+    int32_t *slot_at_temp, *temp_of_slot;  // [D][O][T]
+    double *E;                             // [D][O][T] by slot
+    const float *beta32;
+    const double *beta64;
+    unsigned long long *accepts;           // [D][O][T-1]
+    double *stat_sum;                      // [D][O][T][2]
+    int32_t *stat_flag;
+    uint32_t *stat_trips;
+    const uint32_t *tptr;
+    int64_t Nh;
+    int32_t L, Lh, D, O, T, slots_per_sample, groups;
+    int32_t n_sweeps, n_hb, n_or, pt_every, stats;
+    uint32_t key0, key1, uid_base;
+};
+// LDS bytes a work-group of the resident kernel needs.
+size_t resident_lds_bytes(int storage, int64_t Nh, int32_t slots_per_sample);
+hipError_t launch_resident(const ResidentArgs &a, int storage, bool field, bool hw, unsigned threads, size_t lds,
+                           hipStream_t s);
 
 struct PackArgs {
     void *spins_int;

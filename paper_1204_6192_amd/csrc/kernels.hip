@@ -8,6 +8,7 @@
 // layout conversion between the canonical and internal arrays.
 #include "device.h"
 #include "kernels.h"
+#include "ladder.h"
 
 namespace hsg {
 
@@ -191,32 +192,12 @@ hipError_t launch_reduce_partials(const double *partials, int n_pb, int64_t n_re
 }
 
 // ---------------------------------------------------------------- tempering
-// One thread per (sample, copy) ladder walks k = 0 .. T-2 from the lowest
-// temperature; float64 acceptance exponent (Eq. (4)); temperatures move.
+// One thread per (sample, copy) ladder (pt_ladder in ladder.h).
 __global__ __launch_bounds__(64) void k_pt(PtArgs a)
 {
     const int64_t lad = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (lad >= (int64_t)a.D * a.O) return;
-    const int d = (int)(lad / a.O), o = (int)(lad - (int64_t)d * a.O);
-    int32_t *sat = a.slot_at_temp + lad * a.T;
-    int32_t *tos = a.temp_of_slot + lad * a.T;
-    const double *E = a.E + lad * a.T;
-    const uint32_t ctr1 = a.tptr ? *a.tptr : a.ctr1;
-    for (int k = 0; k + 1 < a.T; ++k) {
-        const int32_t sa = sat[k], sb = sat[k + 1];
-        const double delta = (a.beta64[k + 1] - a.beta64[k]) * (E[sb] - E[sa]);
-        const u32x4 r = philox4x32_10(
-            u32x4{(uint32_t)k, ctr1, ((uint32_t)o << 8) | (a.purpose << 20), a.uid_base + (uint32_t)d}, a.key0,
-            a.key1);
-        const double u = u53(r.x, r.y);
-        if (delta >= 0.0 || u <= exp(delta)) {
-            sat[k] = sb;
-            sat[k + 1] = sa;
-            tos[sb] = k;
-            tos[sa] = k + 1;
-            a.accepts[lad * (a.T - 1) + k] += 1ull;
-        }
-    }
+    pt_ladder(a, lad, a.tptr ? *a.tptr : a.ctr1);
 }
 
 hipError_t launch_pt(const PtArgs &a, hipStream_t s)
@@ -228,30 +209,12 @@ hipError_t launch_pt(const PtArgs &a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- run statistics
-// After a sweep: per ladder, the energy of the configuration at each rung is
-// added to float64 sums of E and E^2 (for U_L and C_L), and a replica that
-// reaches the lowest rung after visiting the highest since its last visit to
-// the lowest completes a round trip. flag per slot: 0 none yet, 1 at the lowest
-// rung since, 2 reached the highest rung after that.
+// One thread per ladder (stats_ladder in ladder.h).
 __global__ __launch_bounds__(64) void k_stats(StatsArgs a)
 {
     const int64_t lad = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (lad >= (int64_t)a.D * a.O) return;
-    const int32_t *sat = a.slot_at_temp + lad * a.T;
-    const double *E = a.E + lad * a.T;
-    double *sum = a.sum + lad * a.T * 2;
-    for (int k = 0; k < a.T; ++k) {
-        const double e = E[sat[k]];
-        sum[2 * k] += e;
-        sum[2 * k + 1] += e * e;
-    }
-    if (a.T < 2) return;
-    int32_t *flag = a.flag + lad * a.T;
-    uint32_t *trips = a.trips + lad * a.T;
-    const int32_t lo = sat[0], hi = sat[a.T - 1];
-    if (flag[lo] == 2) trips[lo] += 1u;
-    flag[lo] = 1;
-    if (flag[hi] == 1) flag[hi] = 2;
+    stats_ladder(a, lad);
 }
 
 __global__ __launch_bounds__(256) void k_stats_clear(StatsArgs a)

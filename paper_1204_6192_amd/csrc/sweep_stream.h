@@ -80,7 +80,7 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     const float *Ho = field ? a.Hp + (d * 2 + (1 - p)) * 3 * (int64_t)Nh : nullptr;
     float beta = 0.0f;
     uint32_t c2 = 0, uid = 0;
-    const uint32_t tsweep = *a.tptr;
+    const uint32_t tsweep = *a.tptr + a.t_offset;
     if (active) {
         beta = a.beta32[a.temp_of_slot[r]];
         const int o = sis / a.T, ts = sis - o * a.T;
@@ -372,7 +372,7 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
     }
     float beta = 0.0f;
     uint32_t c2A = 0, c2B = 0, uid = 0;
-    const uint32_t tsweep = *a.tptr;
+    const uint32_t tsweep = *a.tptr + a.t_offset;
     if (active) {
         beta = a.beta32[a.temp_of_slot[r]];
         const int o = sis / a.T, ts = sis - o * a.T;
