@@ -361,6 +361,11 @@ struct Codec<0> {  // float32: stored renormalised, read as is
     {
         return v3{p[j], p[cs + j], p[2 * cs + j]};
     }
+    // the same with 32-bit byte offsets from a uniform base (3 cs sizeof(T) < 2^32)
+    __device__ static __forceinline__ v3 load32(const T *p, uint32_t cs, uint32_t j)
+    {
+        return v3{*elem<true>(p, j), *elem<true>(p, cs + j), *elem<true>(p, 2 * cs + j)};
+    }
     __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
     {
         p[j] = s.x;
@@ -412,6 +417,11 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
         return normalise_rsq(v3{__half2float(p[j]), __half2float(p[cs + j]), __half2float(p[2 * cs + j])});
+    }
+    __device__ static __forceinline__ v3 load32(const T *p, uint32_t cs, uint32_t j)
+    {
+        return normalise_rsq(v3{__half2float(*elem<true>(p, j)), __half2float(*elem<true>(p, cs + j)),
+                                __half2float(*elem<true>(p, 2 * cs + j))});
     }
     __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
     {
@@ -474,6 +484,11 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
     __device__ static __forceinline__ v3 load(const T *p, int64_t cs, int64_t j)
     {
         return normalise_rsq(v3{bf16_to_f32(p[j]), bf16_to_f32(p[cs + j]), bf16_to_f32(p[2 * cs + j])});
+    }
+    __device__ static __forceinline__ v3 load32(const T *p, uint32_t cs, uint32_t j)
+    {
+        return normalise_rsq(v3{bf16_to_f32(*elem<true>(p, j)), bf16_to_f32(*elem<true>(p, cs + j)),
+                                bf16_to_f32(*elem<true>(p, 2 * cs + j))});
     }
     __device__ static __forceinline__ void store(T *p, int64_t cs, int64_t j, v3 s)
     {
@@ -566,6 +581,7 @@ struct Codec<3> {
     using T = uint32_t;
     static constexpr int kPlanes = 1;
     __device__ static __forceinline__ v3 load(const T *p, int64_t, int64_t j) { return oct_decode(p[j]); }
+    __device__ static __forceinline__ v3 load32(const T *p, uint32_t, uint32_t j) { return oct_decode(*elem<true>(p, j)); }
     __device__ static __forceinline__ void store(T *p, int64_t, int64_t j, v3 s) { p[j] = oct_encode(s); }
     __device__ static __forceinline__ v3 stored_value(v3 s) { return oct_decode(oct_encode(s)); }
     template <bool B32 = false>

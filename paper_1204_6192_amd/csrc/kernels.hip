@@ -563,24 +563,32 @@ struct KGroup<2> {
     static constexpr int first = 63, count = 21;
 };
 
-template <int STORE>
-__device__ __forceinline__ v3 load_site(const typename Codec<STORE>::T *rep, int64_t Nh, int L, int x, int y, int z)
+// The spin at (x, y, z), every coordinate in 0 .. L - 1 (L <= 1024, so the
+// half-index fits 32 bits). B32: the replica's spins span less than 4 GiB, so
+// every access is the (uniform) replica base plus a 32-bit byte offset.
+template <int STORE, bool B32>
+__device__ __forceinline__ v3 load_site(const typename Codec<STORE>::T *rep, int64_t Nh, uint32_t L, uint32_t x,
+                                        uint32_t y, uint32_t z)
 {
-    x = x < 0 ? x + L : (x >= L ? x - L : x);
-    y = y < 0 ? y + L : (y >= L ? y - L : y);
-    z = z < 0 ? z + L : (z >= L ? z - L : z);
-    const int p = (x + y + z) & 1;
-    const int64_t j = ((int64_t)z * L + y) * (L / 2) + (x >> 1);
-    return Codec<STORE>::load(rep + (int64_t)p * Codec<STORE>::kPlanes * Nh, Nh, j);
+    const uint32_t p = (x + y + z) & 1u;
+    const uint32_t j = (z * L + y) * (L >> 1) + (x >> 1);
+    if constexpr (B32)
+        return Codec<STORE>::load32(rep, (uint32_t)Nh, (p ? (uint32_t)Codec<STORE>::kPlanes * (uint32_t)Nh : 0u) + j);
+    else
+        return Codec<STORE>::load(rep + (p ? (int64_t)Codec<STORE>::kPlanes * Nh : 0), Nh, (int64_t)j);
 }
 
-__device__ __forceinline__ double chirality(v3 u, v3 v, v3 w)  // u . (v x w)
+// u . (v x w) in float64: each product of two float32 components is exact, so
+// every component of v x w is rounded once; the dot product uses fused
+// multiply-adds.
+__device__ __forceinline__ double chirality(v3 u, v3 v, v3 w)
 {
     const double vx = v.x, vy = v.y, vz = v.z, wx = w.x, wy = w.y, wz = w.z;
-    return (double)u.x * (vy * wz - vz * wy) + (double)u.y * (vz * wx - vx * wz) + (double)u.z * (vx * wy - vy * wx);
+    const double cx = fma(vy, wz, -(vz * wy)), cy = fma(vz, wx, -(vx * wz)), cz = fma(vx, wy, -(vy * wx));
+    return fma((double)u.x, cx, fma((double)u.y, cy, (double)u.z * cz));
 }
 
-template <int STORE, int G>
+template <int STORE, int G, bool B32>
 __global__ __launch_bounds__(kBlock) void k_kmodes(KmodeArgs a)
 {
     using C = Codec<STORE>;
@@ -607,48 +615,107 @@ __global__ __launch_bounds__(kBlock) void k_kmodes(KmodeArgs a)
     double acc[K];
 #pragma unroll
     for (int m = 0; m < K; ++m) acc[m] = 0.0;
-    const int64_t i_end = ((int64_t)(pb + 1) * a.chunk < N) ? (int64_t)(pb + 1) * a.chunk : N;
-    for (int64_t i = (int64_t)pb * a.chunk + threadIdx.x; i < i_end; i += kBlock) {
-        const int x = (int)(i % L), y = (int)((i / L) % L), z = (int)(i / ((int64_t)L * L));
-        const v3 sa0 = load_site<STORE>(A, Nh, L, x, y, z), sb0 = load_site<STORE>(B, Nh, L, x, y, z);
-        if (G < 2) {
-            const double xa[3] = {sa0.x, sa0.y, sa0.z}, ya[3] = {sb0.x, sb0.y, sb0.z};
-            const int R0 = G == 0 ? x : y, R1 = G == 0 ? x : z;
-            const double c0 = cph[R0], s0 = sph[R0], c1 = cph[R1], s1 = sph[R1];
+    // N = L^3 <= 2^30: the site index and its coordinates fit 32 bits. The
+    // coordinates of the thread's first site come from one division; then they
+    // advance by kBlock sites per iteration with carries.
+    const uint32_t Lu = (uint32_t)L, LL = Lu * Lu;
+    const uint32_t i_end = (uint32_t)(((int64_t)(pb + 1) * a.chunk < N) ? (int64_t)(pb + 1) * a.chunk : N);
+    const uint32_t i0 = (uint32_t)((int64_t)pb * a.chunk) + threadIdx.x;
+    uint32_t x = i0 % Lu, y = (i0 / Lu) % Lu, z = i0 / LL;
+    const uint32_t sx = (uint32_t)kBlock % Lu, sy = ((uint32_t)kBlock / Lu) % Lu, sz = (uint32_t)kBlock / LL;
+    // U sites per iteration, their loads issued before any is used (several
+    // sites' loads in flight per wave); the sums still take the sites in order.
+    // A site past the end reads site 0 of the replica (valid memory) and is not
+    // counted.
+    constexpr int U = G < 2 ? 4 : 2;
+    for (uint32_t i = i0; i < i_end; i += U * kBlock) {
+        uint32_t cx[U], cy[U], cz[U];
+        bool ok[U];
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
+        for (int u = 0; u < U; ++u) {
+            ok[u] = i + (uint32_t)u * kBlock < i_end;
+            cx[u] = ok[u] ? x : 0u;
+            cy[u] = ok[u] ? y : 0u;
+            cz[u] = ok[u] ? z : 0u;
+            x += sx;
+            uint32_t c = x >= Lu ? 1u : 0u;
+            x -= c * Lu;
+            y += sy + c;
+            c = y >= Lu ? 1u : 0u;
+            y -= c * Lu;
+            z += sz + c;
+        }
+        v3 sa0[U], sb0[U];
 #pragma unroll
-                for (int n = 0; n < 3; ++n) {
-                    const double f = xa[m] * ya[n];
-                    const int mn = 3 * m + n;
-                    if (G == 0) {
-                        acc[mn] += f;
-                        acc[9 + 2 * mn] += f * c0;
-                        acc[9 + 2 * mn + 1] += f * s0;
-                    } else {
-                        acc[2 * mn] += f * c0;
-                        acc[2 * mn + 1] += f * s0;
-                        acc[18 + 2 * mn] += f * c1;
-                        acc[18 + 2 * mn + 1] += f * s1;
+        for (int u = 0; u < U; ++u) {
+            sa0[u] = load_site<STORE, B32>(A, Nh, Lu, cx[u], cy[u], cz[u]);
+            sb0[u] = load_site<STORE, B32>(B, Nh, Lu, cx[u], cy[u], cz[u]);
+        }
+        if constexpr (G < 2) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) continue;
+                const double xa[3] = {sa0[u].x, sa0[u].y, sa0[u].z}, ya[3] = {sb0[u].x, sb0[u].y, sb0[u].z};
+                const uint32_t R0 = G == 0 ? cx[u] : cy[u], R1 = G == 0 ? cx[u] : cz[u];
+                const double c0 = cph[R0], s0 = sph[R0], c1 = cph[R1], s1 = sph[R1];
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+#pragma unroll
+                    for (int n = 0; n < 3; ++n) {
+                        const double f = xa[m] * ya[n];
+                        const int mn = 3 * m + n;
+                        if (G == 0) {
+                            acc[mn] += f;
+                            acc[9 + 2 * mn] += f * c0;
+                            acc[9 + 2 * mn + 1] += f * s0;
+                        } else {
+                            acc[2 * mn] += f * c0;
+                            acc[2 * mn + 1] += f * s0;
+                            acc[18 + 2 * mn] += f * c1;
+                            acc[18 + 2 * mn + 1] += f * s1;
+                        }
                     }
-                }
+            }
         } else {
-            const double cx = cph[x], sx = sph[x], cy = cph[y], sy = sph[y], cz = cph[z], sz = sph[z];
+            // the neighbours along each axis: (+, -) of replicas A and B
+            v3 na[U][3][2], nb[U][3][2];
 #pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const int dx = al == 0, dy = al == 1, dz = al == 2;
-                const double ka = chirality(load_site<STORE>(A, Nh, L, x + dx, y + dy, z + dz), sa0,
-                                            load_site<STORE>(A, Nh, L, x - dx, y - dy, z - dz));
-                const double kb = chirality(load_site<STORE>(B, Nh, L, x + dx, y + dy, z + dz), sb0,
-                                            load_site<STORE>(B, Nh, L, x - dx, y - dy, z - dz));
-                const double g = ka * kb;
-                acc[7 * al] += g;
-                acc[7 * al + 1] += g * cx;
-                acc[7 * al + 2] += g * sx;
-                acc[7 * al + 3] += g * cy;
-                acc[7 * al + 4] += g * sy;
-                acc[7 * al + 5] += g * cz;
-                acc[7 * al + 6] += g * sz;
+            for (int u = 0; u < U; ++u) {
+                const uint32_t X = cx[u], Y = cy[u], Z = cz[u];
+                const uint32_t xp = X + 1 == Lu ? 0 : X + 1, xm = X == 0 ? Lu - 1 : X - 1;
+                const uint32_t yp = Y + 1 == Lu ? 0 : Y + 1, ym = Y == 0 ? Lu - 1 : Y - 1;
+                const uint32_t zp = Z + 1 == Lu ? 0 : Z + 1, zm = Z == 0 ? Lu - 1 : Z - 1;
+                na[u][0][0] = load_site<STORE, B32>(A, Nh, Lu, xp, Y, Z);
+                na[u][0][1] = load_site<STORE, B32>(A, Nh, Lu, xm, Y, Z);
+                na[u][1][0] = load_site<STORE, B32>(A, Nh, Lu, X, yp, Z);
+                na[u][1][1] = load_site<STORE, B32>(A, Nh, Lu, X, ym, Z);
+                na[u][2][0] = load_site<STORE, B32>(A, Nh, Lu, X, Y, zp);
+                na[u][2][1] = load_site<STORE, B32>(A, Nh, Lu, X, Y, zm);
+                nb[u][0][0] = load_site<STORE, B32>(B, Nh, Lu, xp, Y, Z);
+                nb[u][0][1] = load_site<STORE, B32>(B, Nh, Lu, xm, Y, Z);
+                nb[u][1][0] = load_site<STORE, B32>(B, Nh, Lu, X, yp, Z);
+                nb[u][1][1] = load_site<STORE, B32>(B, Nh, Lu, X, ym, Z);
+                nb[u][2][0] = load_site<STORE, B32>(B, Nh, Lu, X, Y, zp);
+                nb[u][2][1] = load_site<STORE, B32>(B, Nh, Lu, X, Y, zm);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!ok[u]) continue;
+                const double cx0 = cph[cx[u]], snx = sph[cx[u]], cy0 = cph[cy[u]], sny = sph[cy[u]];
+                const double cz0 = cph[cz[u]], snz = sph[cz[u]];
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    const double ka = chirality(na[u][al][0], sa0[u], na[u][al][1]);
+                    const double kb = chirality(nb[u][al][0], sb0[u], nb[u][al][1]);
+                    const double g = ka * kb;
+                    acc[7 * al] += g;
+                    acc[7 * al + 1] = fma(g, cx0, acc[7 * al + 1]);
+                    acc[7 * al + 2] = fma(g, snx, acc[7 * al + 2]);
+                    acc[7 * al + 3] = fma(g, cy0, acc[7 * al + 3]);
+                    acc[7 * al + 4] = fma(g, sny, acc[7 * al + 4]);
+                    acc[7 * al + 5] = fma(g, cz0, acc[7 * al + 5]);
+                    acc[7 * al + 6] = fma(g, snz, acc[7 * al + 6]);
+                }
             }
         }
     }
@@ -679,9 +746,18 @@ template <int STORE>
 static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
 {
     const dim3 grid((unsigned)((int64_t)a.D * a.T * a.n_pb)), block(kBlock);
-    hipLaunchKernelGGL((k_kmodes<STORE, 0>), grid, block, 0, s, a);
-    hipLaunchKernelGGL((k_kmodes<STORE, 1>), grid, block, 0, s, a);
-    hipLaunchKernelGGL((k_kmodes<STORE, 2>), grid, block, 0, s, a);
+    // a replica's spins within 4 GiB: 32-bit offsets from its base
+    const bool b32 = 2 * (uint64_t)Codec<STORE>::kPlanes * (uint64_t)a.Nh * sizeof(typename Codec<STORE>::T) <
+                     (1ull << 32);
+    if (b32) {
+        hipLaunchKernelGGL((k_kmodes<STORE, 0, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_kmodes<STORE, 1, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_kmodes<STORE, 2, true>), grid, block, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_kmodes<STORE, 0, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_kmodes<STORE, 1, false>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_kmodes<STORE, 2, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
