@@ -226,7 +226,12 @@ __device__ __forceinline__ void acc3(v3 &h, float J, v3 s)
 // azimuth from the hardware sin/cos of revolutions (absolute error about
 // 1.2e-7, one float32 spacing at 1). Both take e^z and ln X from the hardware
 // 2^x and log2 with extended-precision scaling (exp_nonpos, log_normal).
-template <bool HW>
+//
+// RENORM = false (compressed storage) skips the final renormalisation: the
+// codec rounds the spin to 2^-11 or coarser and renormalises it on load, so a
+// norm error of a few float32 ulps changes nothing but rare roundings at a
+// code boundary (as float32 arithmetic against float64 already does).
+template <bool HW, bool RENORM = true>
 __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t w1)
 {
     const float u1 = u24(w0);
@@ -312,13 +317,15 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
     const float ta = st * cp, tb = st * sp;
     v3 s{fmaf(c, n.x, fmaf(ta, e1.x, tb * e2.x)), fmaf(c, n.y, fmaf(ta, e1.y, tb * e2.y)),
          fmaf(c, n.z, fmaf(ta, e1.z, tb * e2.z))};
-    return renorm_unit(s);
+    return RENORM ? renorm_unit(s) : s;
 }
 
 // ---------------------------------------------------------------- Eq. (3)
 // Reflection of s about the local field; a zero field (|h|^2 below 1e-30)
 // leaves s unchanged. The spin must be a unit vector to float32 precision (the
-// reflection keeps |s|).
+// reflection keeps |s|). RENORM = false (compressed storage, which renormalises
+// on load) skips the final renormalisation, as in heat_bath.
+template <bool RENORM = true>
 __device__ __forceinline__ v3 over_relax(v3 s, v3 h)
 {
     const float hh = dot3(h, h);
@@ -330,7 +337,7 @@ __device__ __forceinline__ v3 over_relax(v3 s, v3 h)
     rh = fmaf(rh, fmaf(-hh, rh, 1.0f), rh);
     const float f = 2.0f * dot3(s, h) * rh;
     v3 r{fmaf(f, h.x, -s.x), fmaf(f, h.y, -s.y), fmaf(f, h.z, -s.z)};
-    return renorm_unit(r);
+    return RENORM ? renorm_unit(r) : r;
 }
 
 // ---------------------------------------------------------------- storage

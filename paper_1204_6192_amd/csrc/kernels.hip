@@ -118,9 +118,9 @@ __global__ __launch_bounds__(kBlock) void k_half_sweep(SweepArgs a)
                 }
                 v3 s1;
                 if (KIND != 1)
-                    s1 = heat_bath<KIND == 2>(h, beta, k ? r.z : r.x, k ? r.w : r.y);
+                    s1 = heat_bath<KIND == 2, STORE == 0>(h, beta, k ? r.z : r.x, k ? r.w : r.y);
                 else
-                    s1 = over_relax(C::load(own, Nh, j), h);
+                    s1 = over_relax<STORE == 0>(C::load(own, Nh, j), h);
                 C::store(own, Nh, j, s1);
                 if (ENERGY) {
                     // each bond has exactly one endpoint on this parity (the odd one)

@@ -151,8 +151,8 @@ __global__ __launch_bounds__(512) void k_resident_sweeps(ResidentArgs a)
                         }
                     }
                     v3 s1;
-                    if constexpr (kind == 0) s1 = heat_bath<HW>(h, beta, k ? r.z : r.x, k ? r.w : r.y);
-                    else s1 = over_relax(C::load(own, Nh, j), h);
+                    if constexpr (kind == 0) s1 = heat_bath<HW, STORE == 0>(h, beta, k ? r.z : r.x, k ? r.w : r.y);
+                    else s1 = over_relax<STORE == 0>(C::load(own, Nh, j), h);
                     C::store(own, Nh, j, s1);
                     if constexpr (energy) {
                         // each bond has exactly one endpoint on this (odd) parity

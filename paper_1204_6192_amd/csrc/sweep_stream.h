@@ -24,9 +24,10 @@
 
 namespace hsg {
 
-// UNI: every wave holds a single replica (TY * P a multiple of 64), so the
-// replica's base addresses are wave-uniform and live in scalar registers, and
-// the per-lane addressing is 32-bit.
+// UNI: every wave holds a single replica (TY * P a multiple of 64) and L <= 512,
+// so the replica's base addresses are wave-uniform and live in scalar
+// registers, and every load and store takes such a base (one per coupling
+// plane) plus the lane's 32-bit byte offset: no 64-bit address arithmetic.
 // FIELD / JB: some group of the launch has a field / sign-bit couplings (each
 // group is then checked at run time); UNI: every group of the launch is UNI.
 template <int STORE, int KIND, bool FIELD, bool ENERGY, bool UNI, bool JB>
@@ -78,6 +79,9 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     const uint8_t *Jbb = jbits ? a.Jbits + (d * 2 + p) * (int64_t)Nh : nullptr;
     const float *Hb = field ? a.Hp + (d * 2 + p) * 3 * (int64_t)Nh : nullptr;
     const float *Ho = field ? a.Hp + (d * 2 + (1 - p)) * 3 * (int64_t)Nh : nullptr;
+    const float *Jp[6];  // one base per coupling plane (uniform with UNI)
+#pragma unroll
+    for (int n = 0; n < 6; ++n) Jp[n] = Jb + n * (int64_t)Nh;
     float beta = 0.0f;
     uint32_t c2 = 0, uid = 0;
     const uint32_t tsweep = *a.tptr + a.t_offset;
@@ -101,11 +105,11 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
     v3 prv0{}, prv1{}, cur0{}, cur1{}, nxt0{}, nxt1{};
     typename C::R nraw, graw, oraw;
     {
-        C::load_pair(oth, Nh, (uint32_t)((((z0 == 0 ? L : z0) - 1) * L + y) * Lh + xh0), prv0, prv1);
-        C::load_pair(oth, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), cur0, cur1);
-        C::load_raw_pair(oth, Nh, (uint32_t)((wrapz(z0 + 1) * L + y) * Lh + xh0), nraw);
-        C::load_raw_pair(oth, Nh, (uint32_t)((z0 * L + hy) * Lh + xh0), graw);
-        C::load_raw_pair(own, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), oraw);
+        C::template load_pair<UNI>(oth, Nh, (uint32_t)((((z0 == 0 ? L : z0) - 1) * L + y) * Lh + xh0), prv0, prv1);
+        C::template load_pair<UNI>(oth, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), cur0, cur1);
+        C::template load_raw_pair<UNI>(oth, Nh, (uint32_t)((wrapz(z0 + 1) * L + y) * Lh + xh0), nraw);
+        C::template load_raw_pair<UNI>(oth, Nh, (uint32_t)((z0 * L + hy) * Lh + xh0), graw);
+        C::template load_raw_pair<UNI>(own, Nh, (uint32_t)((z0 * L + y) * Lh + xh0), oraw);
     }
     double e = 0.0;
 
@@ -116,14 +120,14 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
         C::decode_pair(nraw, nxt0, nxt1);
         v3 old0{}, old1{};
         if (KIND == 1) C::decode_pair(oraw, old0, old1);
-        v3 g0, g1;
-        C::decode_pair(graw, g0, g1);
         if (active) {  // stage plane z (my two positions, and the halo rows) in LDS
             const int w = lo + lrow * Lh + xh0;
             *reinterpret_cast<float2 *>(&lds[w]) = make_float2(cur0.x, cur1.x);
             *reinterpret_cast<float2 *>(&lds[w + cstride]) = make_float2(cur0.y, cur1.y);
             *reinterpret_cast<float2 *>(&lds[w + 2 * cstride]) = make_float2(cur0.z, cur1.z);
-            if (halo) {
+            if (halo) {  // whole rows: a wave without halo rows skips the decoding
+                v3 g0, g1;
+                C::decode_pair(graw, g0, g1);
                 const int hw = lo + hw_row * Lh + xh0;
                 *reinterpret_cast<float2 *>(&lds[hw]) = make_float2(g0.x, g1.x);
                 *reinterpret_cast<float2 *>(&lds[hw + cstride]) = make_float2(g0.y, g1.y);
@@ -131,32 +135,18 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
             }
         }
         float2 jc[6];
-        v3 hs0{0.f, 0.f, 0.f}, hs1{0.f, 0.f, 0.f};
-        if (jbits) {  // +-1 couplings from sign bits (exactly the float values)
-            const uint32_t bits = *reinterpret_cast<const uint16_t *>(Jbb + j0);
-#pragma unroll
-            for (int n = 0; n < 6; ++n)
-                jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
-        } else {
-#pragma unroll
-            for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(Jb + n * Nh + j0);
-        }
-        if (field) {
-            const float2 hx = *reinterpret_cast<const float2 *>(Hb + j0);
-            const float2 hy2 = *reinterpret_cast<const float2 *>(Hb + Nh + j0);
-            const float2 hz = *reinterpret_cast<const float2 *>(Hb + 2 * Nh + j0);
-            hs0 = v3{hx.x, hy2.x, hz.x};
-            hs1 = v3{hx.y, hy2.y, hz.y};
-        }
+        v3 hs0, hs1;  // +-1 couplings come from sign bits (exactly the float values)
+        if constexpr (UNI) load_couplings_planes<JB, FIELD>(Jp, Jbb, Hb, jbits, field, Nh, j0, jc, hs0, hs1);
+        else load_couplings<JB, FIELD>(Jb, Jbb, Hb, jbits, field, Nh, j0, jc, hs0, hs1);
         // Loads for the next step go out last, so that waiting for this step's
         // couplings leaves them in flight. At the end of the slab they repeat
         // planes already read (their values are never used).
         __builtin_amdgcn_sched_barrier(0);
         {
             const int zn = z + 1 < z1 ? z + 1 : z;
-            C::load_raw_pair(oth, Nh, (uint32_t)((wrapz(z + 2 <= z1 ? z + 2 : z1) * L + y) * Lh + xh0), nraw);
-            C::load_raw_pair(oth, Nh, (uint32_t)((zn * L + hy) * Lh + xh0), graw);
-            C::load_raw_pair(own, Nh, (uint32_t)((zn * L + y) * Lh + xh0), oraw);
+            C::template load_raw_pair<UNI>(oth, Nh, (uint32_t)((wrapz(z + 2 <= z1 ? z + 2 : z1) * L + y) * Lh + xh0), nraw);
+            C::template load_raw_pair<UNI>(oth, Nh, (uint32_t)((zn * L + hy) * Lh + xh0), graw);
+            C::template load_raw_pair<UNI>(own, Nh, (uint32_t)((zn * L + y) * Lh + xh0), oraw);
         }
         u32x4 rr{0u, 0u, 0u, 0u};
         if (KIND != 1 && active) rr = philox4x32_10(u32x4{j0 >> 1, tsweep, c2, uid}, a.key0, a.key1);
@@ -206,22 +196,22 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
             }
             v3 s0, s1;
             if (KIND != 1) {
-                s0 = heat_bath<KIND == 2>(h0, beta, rr.x, rr.y);
-                s1 = heat_bath<KIND == 2>(h1, beta, rr.z, rr.w);
+                s0 = heat_bath<KIND == 2, STORE == 0>(h0, beta, rr.x, rr.y);
+                s1 = heat_bath<KIND == 2, STORE == 0>(h1, beta, rr.z, rr.w);
             } else {
-                s0 = over_relax(old0, h0);
-                s1 = over_relax(old1, h1);
+                s0 = over_relax<STORE == 0>(old0, h0);
+                s1 = over_relax<STORE == 0>(old1, h1);
             }
-            C::store_pair(own, Nh, j0, s0, s1);
+            C::template store_pair<UNI>(own, Nh, j0, s0, s1);
             if (ENERGY) {
                 // each bond has exactly one endpoint on this (odd) parity
                 const v3 v0 = C::stored_value(s0), v1 = C::stored_value(s1);
                 e -= (double)v0.x * hx0 + (double)v0.y * hy0 + (double)v0.z * hz0;
                 e -= (double)v1.x * hx1 + (double)v1.y * hy1 + (double)v1.z * hz1;
                 if (field) {  // field term of the even sites at my two half-indices
-                    const float2 fx = *reinterpret_cast<const float2 *>(Ho + j0);
-                    const float2 fy = *reinterpret_cast<const float2 *>(Ho + Nh + j0);
-                    const float2 fz = *reinterpret_cast<const float2 *>(Ho + 2 * Nh + j0);
+                    const float2 fx = *reinterpret_cast<const float2 *>(elem<UNI>(Ho, j0));
+                    const float2 fy = *reinterpret_cast<const float2 *>(elem<UNI>(Ho, Nh + j0));
+                    const float2 fz = *reinterpret_cast<const float2 *>(elem<UNI>(Ho, 2 * Nh + j0));
                     e -= (double)fx.x * cur0.x + (double)fy.x * cur0.y + (double)fz.x * cur0.z;
                     e -= (double)fx.y * cur1.x + (double)fy.y * cur1.y + (double)fz.y * cur1.z;
                 }
@@ -298,11 +288,11 @@ __device__ __forceinline__ double update_pair(const float *lds, int lo, int cstr
         }
     }
     if (KIND != 1) {
-        s0 = heat_bath<KIND == 2>(h0, beta, rr.x, rr.y);
-        s1 = heat_bath<KIND == 2>(h1, beta, rr.z, rr.w);
+        s0 = heat_bath<KIND == 2, STORE == 0>(h0, beta, rr.x, rr.y);
+        s1 = heat_bath<KIND == 2, STORE == 0>(h1, beta, rr.z, rr.w);
     } else {
-        s0 = over_relax(old0, h0);
-        s1 = over_relax(old1, h1);
+        s0 = over_relax<STORE == 0>(old0, h0);
+        s1 = over_relax<STORE == 0>(old1, h1);
     }
     double e = 0.0;
     if (ENERGY) {
@@ -871,7 +861,8 @@ hipError_t launch_stream_s(const MultiStreamArgs &m, int kind, bool energy, int 
     bool field = false, uni = true, jb = false;
     for (int k = 0; k < m.n_groups; ++k) {
         field = field || m.g[k].Hp != nullptr;
-        uni = uni && (m.g[k].TY * m.g[k].P) % 64 == 0;
+        // 32-bit byte offsets within a replica's spins and a sample's couplings: 6 Nh 4 B < 2^32
+        uni = uni && (m.g[k].TY * m.g[k].P) % 64 == 0 && m.g[k].L <= 512;
         jb = jb || m.g[k].Jbits != nullptr;
     }
     const dim3 grid((unsigned)m.n_blocks), block(threads);

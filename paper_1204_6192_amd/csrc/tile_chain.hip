@@ -111,14 +111,14 @@ __device__ __forceinline__ void pair_update(const v3 (&nb0)[6], const v3 (&nb1)[
         acc3(h1, jc[n].y, nb1[n]);
     }
     if (KIND == 1) {
-        s0 = over_relax(old0, h0);
-        s1 = over_relax(old1, h1);
+        s0 = over_relax<STORE == 0>(old0, h0);
+        s1 = over_relax<STORE == 0>(old1, h1);
     } else if (hw) {
-        s0 = heat_bath<true>(h0, beta, rr.x, rr.y);
-        s1 = heat_bath<true>(h1, beta, rr.z, rr.w);
+        s0 = heat_bath<true, STORE == 0>(h0, beta, rr.x, rr.y);
+        s1 = heat_bath<true, STORE == 0>(h1, beta, rr.z, rr.w);
     } else {
-        s0 = heat_bath<false>(h0, beta, rr.x, rr.y);
-        s1 = heat_bath<false>(h1, beta, rr.z, rr.w);
+        s0 = heat_bath<false, STORE == 0>(h0, beta, rr.x, rr.y);
+        s1 = heat_bath<false, STORE == 0>(h1, beta, rr.z, rr.w);
     }
 }
 
