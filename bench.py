@@ -44,10 +44,10 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 78.6
 # FP32 flops one over-relaxation update needs as written (Eq. (3)): the local
 # field 18 FMA (36); h.h and s.h 5 each; 2 (s.h) / (h.h) 2; the reflection 3 FMA
-# (6); the compensated renormalisation 36 (three squares with their rounding
-# errors 9, two error-free sums 12, the deviation from 1 6, the second-order
-# correction 3, the rescaling 6).
-OR_FLOPS_PER_UPDATE = 36 + 5 + 5 + 2 + 6 + 36
+# (6); the renormalisation of float32 spins 15 (|s|^2 - 1 as three FMA 6, the
+# second-order correction 3, the rescaling 6; compressed storage skips it and
+# renormalises on load).
+OR_FLOPS_PER_UPDATE = 36 + 5 + 5 + 2 + 6 + 15
 METRIC = "ns per spin update (HB+OR) & achieved HBM GB/s, FP32 vs batched+compressed"
 STORE_BYTES = {"f32": 12, "f16": 6, "bf16": 6, "qangle": 4}
 # The compressed-storage comparison run after the main workload: the batched
