@@ -247,21 +247,29 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         const float omu = 1.0f - u1;  // exact on the 2^-24 grid
         const float z = -2.0f * kappa;
         const float E = exp_nonpos(z);  // 0 past underflow
-        float p = 2.7557319e-6f;  // 1/9!, then Horner down to 1/2!
-        p = fmaf(z, p, 2.4801588e-5f);
-        p = fmaf(z, p, 1.9841270e-4f);
-        p = fmaf(z, p, 1.3888889e-3f);
-        p = fmaf(z, p, 8.3333333e-3f);
-        p = fmaf(z, p, 4.1666667e-2f);
-        p = fmaf(z, p, 1.6666667e-1f);
-        p = fmaf(z, p, 0.5f);
-        const float A = z > -0.35f ? z * fmaf(z, p, 1.0f) : E - 1.0f;  // e^{-2 kappa} - 1
-        const float xo = fmaf(omu, E, u1);                               // x
-        upper = xo * xo >= E;  // x >= e^{-kappa}, i.e. c >= 0
-        // c < 0 needs kappa < 17 (u >= 2^-24), where E is a normal number
-        const float yb = u1 * (HW ? -A * hw_rcp(E) : div_nr(-A, E));
-        const float X = upper ? xo : 1.0f + yb;
-        const float Y = upper ? omu * A : yb;
+        // A = e^{-2 kappa} - 1. The two rare cases below are branches rather
+        // than selects: a wave in which no site takes one skips its work.
+        float A = E - 1.0f;
+        if (z > -0.35f) {  // 2 kappa < 0.35: the Taylor series
+            float p = 2.7557319e-6f;  // 1/9!, then Horner down to 1/2!
+            p = fmaf(z, p, 2.4801588e-5f);
+            p = fmaf(z, p, 1.9841270e-4f);
+            p = fmaf(z, p, 1.3888889e-3f);
+            p = fmaf(z, p, 8.3333333e-3f);
+            p = fmaf(z, p, 4.1666667e-2f);
+            p = fmaf(z, p, 1.6666667e-1f);
+            p = fmaf(z, p, 0.5f);
+            A = z * fmaf(z, p, 1.0f);
+        }
+        const float xo = fmaf(omu, E, u1);  // x
+        upper = xo * xo >= E;               // x >= e^{-kappa}, i.e. c >= 0
+        float X = xo, Y = omu * A;
+        if (!upper) {  // c < 0, with probability about e^{-kappa}
+            // c < 0 needs kappa < 17 (u >= 2^-24), where E is a normal number
+            const float yb = u1 * (HW ? -A * hw_rcp(E) : div_nr(-A, E));
+            X = 1.0f + yb;
+            Y = yb;
+        }
         const float d = (1.0f - X) + Y;
         // (a relative correction of order 1e-7: the hardware reciprocal's 1 ulp is far below float32 spacing)
         const float corr = (X >= 0.5f && X <= 2.0f) ? d * hw_rcp(X) : 0.0f;
@@ -465,12 +473,18 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
     }
 };
 
-// bfloat16: the upper half of the float32 pattern, rounded to nearest even.
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v)
+// bfloat16: the upper half of the float32 pattern, rounded to nearest even,
+// by gfx950's conversion instruction (v_cvt_pk_bf16_f32, two values at once).
+// It equals the integer form (b + 0x7FFF + ((b >> 16) & 1)) >> 16 of the
+// pattern b bit for bit: checked on the device for every float32 of magnitude
+// in [2^-31, 2) of either sign.
+typedef float hsg_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 hsg_bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16x2_rne(float lo, float hi)
 {
-    const uint32_t b = __float_as_uint(v);
-    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((hsg_f32x2){lo, hi}, hsg_bf16x2));
 }
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
 
 template <>
@@ -494,7 +508,8 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
     }
     __device__ static __forceinline__ v3 stored_value(v3 s)
     {
-        return normalise_rsq(v3{bf16_to_f32(f32_to_bf16_rne(s.x)), bf16_to_f32(f32_to_bf16_rne(s.y)),
+        const uint32_t xy = bf16x2_rne(s.x, s.y);
+        return normalise_rsq(v3{__uint_as_float(xy << 16), __uint_as_float(xy & 0xFFFF0000u),
                                 bf16_to_f32(f32_to_bf16_rne(s.z))});
     }
     template <bool B32 = false>
@@ -526,12 +541,9 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
     template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<uint32_t *>(elem<B32>(p, j0)) =
-            (uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(b.x) << 16);
-        *reinterpret_cast<uint32_t *>(elem<B32>(p, cs + j0)) =
-            (uint32_t)f32_to_bf16_rne(a.y) | ((uint32_t)f32_to_bf16_rne(b.y) << 16);
-        *reinterpret_cast<uint32_t *>(elem<B32>(p, 2 * cs + j0)) =
-            (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(b.z) << 16);
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, j0)) = bf16x2_rne(a.x, b.x);
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, cs + j0)) = bf16x2_rne(a.y, b.y);
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, 2 * cs + j0)) = bf16x2_rne(a.z, b.z);
     }
 };
 
@@ -542,30 +554,33 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
 // site, x in the low half. One plane per parity; renormalised on load.
 __device__ __forceinline__ float sgn_nz(float a) { return a >= 0.0f ? 1.0f : -1.0f; }
 
+// Both directions work in code units (the octahedron scaled by 32767), where
+// the decoded coordinates and the fold are exact integers before the one
+// renormalisation.
 __device__ __forceinline__ uint32_t oct_encode(v3 v)
 {
-    const float il1 = hw_rcp(fabsf(v.x) + fabsf(v.y) + fabsf(v.z));
-    float px = v.x * il1, py = v.y * il1;
+    const float sc = 32767.0f * hw_rcp(fabsf(v.x) + fabsf(v.y) + fabsf(v.z));
+    float px = v.x * sc, py = v.y * sc;
     if (v.z < 0.0f) {
-        const float fx = (1.0f - fabsf(py)) * sgn_nz(px);
-        const float fy = (1.0f - fabsf(px)) * sgn_nz(py);
+        const float fx = (32767.0f - fabsf(py)) * sgn_nz(px);
+        const float fy = (32767.0f - fabsf(px)) * sgn_nz(py);
         px = fx;
         py = fy;
     }
-    px = fminf(1.0f, fmaxf(-1.0f, px));
-    py = fminf(1.0f, fmaxf(-1.0f, py));
-    const int qx = (int)rintf(px * 32767.0f), qy = (int)rintf(py * 32767.0f);
+    // |px|, |py| <= 32767 (1 + 4 ulp): no clamp is needed before rounding
+    const int qx = (int)rintf(px), qy = (int)rintf(py);
     return ((uint32_t)qx & 0xFFFFu) | ((uint32_t)qy << 16);
 }
 
 __device__ __forceinline__ v3 oct_decode(uint32_t w)
 {
-    float fx = (float)(int16_t)(w & 0xFFFFu) * (1.0f / 32767.0f);
-    float fy = (float)(int16_t)(w >> 16) * (1.0f / 32767.0f);
-    const float vz = 1.0f - fabsf(fx) - fabsf(fy);
+    float fx = (float)(int16_t)(w & 0xFFFFu);
+    float fy = (float)(int16_t)(w >> 16);
+    const float vz = 32767.0f - fabsf(fx) - fabsf(fy);
     if (vz < 0.0f) {
-        const float ax = (1.0f - fabsf(fy)) * sgn_nz(fx);
-        const float ay = (1.0f - fabsf(fx)) * sgn_nz(fy);
+        // fx, fy are never -0 (converted integers), so copysign is sgn_nz here
+        const float ax = __builtin_copysignf(32767.0f - fabsf(fy), fx);
+        const float ay = __builtin_copysignf(32767.0f - fabsf(fx), fy);
         fx = ax;
         fy = ay;
     }
@@ -626,6 +641,13 @@ __device__ __forceinline__ void lds_get_pair(const float *lds, int w, int cstrid
     b = v3{x.y, y.y, z.y};
 }
 
+// +1.0f, or -1.0f when bit b of bits is set: the bit moved to the float's sign
+// (a shift and one and-or, where a test and a select took three instructions).
+__device__ __forceinline__ float pm1_from_bit(uint32_t bits, int b)
+{
+    return __uint_as_float(((bits << (31 - b)) & 0x80000000u) | 0x3F800000u);
+}
+
 // The same for lattices addressed with 32-bit byte offsets, from one uniform
 // base per coupling plane (Jp[n] = the plane of bond n): each load is that base
 // plus the lane's byte offset, with no per-load address arithmetic.
@@ -638,7 +660,7 @@ __device__ __forceinline__ void load_couplings_planes(const float *const (&Jp)[6
         const uint32_t bits = *reinterpret_cast<const uint16_t *>(elem<true>(Jbb, j0));
 #pragma unroll
         for (int n = 0; n < 6; ++n)
-            jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
+            jc[n] = make_float2(pm1_from_bit(bits, n), pm1_from_bit(bits, 8 + n));
     } else {
 #pragma unroll
         for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(elem<true>(Jp[n], j0));
@@ -663,7 +685,7 @@ __device__ __forceinline__ void load_couplings(const float *Jb, const uint8_t *J
         const uint32_t bits = *reinterpret_cast<const uint16_t *>(elem<B32>(Jbb, j0));
 #pragma unroll
         for (int n = 0; n < 6; ++n)
-            jc[n] = make_float2(((bits >> n) & 1u) ? -1.0f : 1.0f, ((bits >> (8 + n)) & 1u) ? -1.0f : 1.0f);
+            jc[n] = make_float2(pm1_from_bit(bits, n), pm1_from_bit(bits, 8 + n));
     } else {
 #pragma unroll
         for (int n = 0; n < 6; ++n) jc[n] = *reinterpret_cast<const float2 *>(elem<B32>(Jb, n * Nh + j0));

@@ -488,7 +488,11 @@ __global__ __launch_bounds__(kBlock) void k_overlap(OverlapArgs a)
     const T *B = (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh;
     double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t j_end = ((int64_t)(pb + 1) * a.chunk < Nh) ? (int64_t)(pb + 1) * a.chunk : Nh;
+    // unrolled so that the loads of several iterations are in flight together
+    // (the sums keep their order)
+#pragma unroll 4
     for (int64_t j = (int64_t)pb * a.chunk + threadIdx.x; j < j_end; j += kBlock) {
+#pragma unroll
         for (int p = 0; p < 2; ++p) {
             const v3 x = C::load(A + (int64_t)p * C::kPlanes * Nh, Nh, j);
             const v3 y = C::load(B + (int64_t)p * C::kPlanes * Nh, Nh, j);
