@@ -103,3 +103,37 @@ def test_large_single_lattice_half_sweep(hsg, oracle_lib):
               f"bound {d[worst] / bound[worst]:.2f} at |H_eff| = {hn[worst]:.2e}", flush=True)
         assert d.max() < 1e-4
         assert np.all(d <= bound)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_compressed_store_rounds_to_nearest_even(hsg, oracle_lib, storage):
+    """Spins written in float16 or bfloat16 (the codec's encoder, which for
+    bfloat16 is gfx950's packed conversion) round every component to nearest
+    with ties to even, as the oracle's codec emulation does: half of the
+    components lie exactly half-way between two codes (both parities of the
+    lower code, both signs), the rest anywhere in +-[1/8, 1). Read back, each
+    spin is the renormalised rounded vector to float32 precision; one code step
+    the wrong way would move a component by at least 5e-5 (float16) or 4e-4
+    (bfloat16)."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 75))
+    g = inputs.make_group(rng, 8, 2, 2, inputs.geometric_ladder(0.1, 0.3, 4))
+    lat = hsg.Lattice([g], seed=inputs.PHILOX_KEY_BASE + 75, storage=storage)
+    n = g.n_slots * 3 * g.N
+    # float32 patterns in [1/8, 1) with a random sign
+    bits = rng.integers(0x3E000000, 0x3F800000, size=n, dtype=np.uint64).astype(np.uint32)
+    bits |= (rng.integers(0, 2, size=n, dtype=np.uint32) << 31).astype(np.uint32)
+    tie = rng.integers(0, 2, size=n).astype(bool)
+    if storage == "bf16":  # the 16 dropped bits exactly half a code step
+        bits[tie] = (bits[tie] & np.uint32(0xFFFF0000)) | np.uint32(0x8000)
+        rnd = np.vectorize(oracle_lib.round_bf16)
+    else:  # float16 keeps 10 of the 23 fraction bits (normal range here)
+        bits[tie] = (bits[tie] & np.uint32(0xFFFFE000)) | np.uint32(0x1000)
+        rnd = np.vectorize(oracle_lib.round_f16)
+    v = bits.view(np.float32)
+    lat.set_spins(torch.from_numpy(v.copy()).to(lat.device))
+    got = lat.get_spins().cpu().numpy().astype(np.float64).reshape(g.n_slots, 3, g.N)
+    want = rnd(v.astype(np.float64)).reshape(g.n_slots, 3, g.N)
+    want = want / np.sqrt((want ** 2).sum(axis=1, keepdims=True))
+    err = np.abs(got - want).max()
+    print(f"{storage}: {int(tie.sum())} ties, max |got - want| {err:.2e}", flush=True)
+    assert err < 1e-6

@@ -72,3 +72,43 @@ def test_extended_precision_constants():
         assert h == F32(value)
         assert lo == F32(value - float(h))
         assert abs(float(h) + float(lo) - value) < 2.0 ** -50
+
+
+def test_renormalisation_has_no_drift():
+    """The float32 renormalisation applied after every update (renorm_unit):
+    d = |s|^2 - 1 as a chain of three fused multiply-adds, then s (1 + d (3d/8
+    - 1/2)). Replayed over 200 float32 reflections of 2 * 10^4 random spins
+    about random fields, the mean of |s| - 1 stays at zero within its
+    statistical error (the roundings are unbiased), while plain v / sqrt(v.v)
+    drifts by about 3e-8 (it cannot resolve deviations below the float32
+    spacing at 1). The source is checked to hold the replayed steps."""
+    body = _function("renorm_unit")
+    assert "fmaf(a.x, a.x, fmaf(a.y, a.y, fmaf(a.z, a.z, -1.0f)))" in body
+    assert "d * fmaf(0.375f, d, -0.5f)" in body
+    rng = np.random.default_rng(12)
+    n = 20000
+
+    def chain(x, y, z):
+        d = _fma(x, x, _fma(y, y, _fma(z, z, np.full_like(z, -1))))
+        c = d * _fma(np.full_like(d, 0.375), d, np.full_like(d, -0.5))
+        return _fma(x, c, x), _fma(y, c, y), _fma(z, c, z)
+
+    def plain(x, y, z):
+        r = F32(1) / np.sqrt(x * x + y * y + z * z)
+        return x * r, y * r, z * r
+
+    means = {}
+    for name, fn in (("chain", chain), ("plain", plain)):
+        v = rng.normal(size=(3, n))
+        v /= np.linalg.norm(v, axis=0)
+        x, y, z = (c.astype(F32) for c in v)
+        for _ in range(200):
+            h = rng.normal(size=(3, n)).astype(F32)
+            hh = _fma(h[0], h[0], _fma(h[1], h[1], h[2] * h[2]))
+            f = F32(2) * _fma(x, h[0], _fma(y, h[1], z * h[2])) * (F32(1) / hh)
+            x, y, z = fn(_fma(f, h[0], -x), _fma(f, h[1], -y), _fma(f, h[2], -z))
+        dev = np.sqrt(x.astype(np.float64) ** 2 + y.astype(np.float64) ** 2 + z.astype(np.float64) ** 2) - 1
+        means[name] = (dev.mean(), dev.std() / np.sqrt(n))
+    m, se = means["chain"]
+    assert abs(m) < 5 * se + 1e-11, means
+    assert means["plain"][0] > 1e-8, means
