@@ -237,7 +237,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
     v3 n;
     float omc, opc;  // 1 - c and 1 + c
     bool upper;      // c >= 0: c is taken from 1 - c, else from 1 + c
-    if (hh == 0.0f || !(kappa > 0.0f)) {
+    if (__builtin_expect(hh == 0.0f || !(kappa > 0.0f), 0)) {  // rare: zero field
         n = v3{0.0f, 0.0f, 1.0f};
         omc = 2.0f * (1.0f - u1);  // c = 2 u1 - 1, exact
         opc = 2.0f * u1;
@@ -250,7 +250,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         // A = e^{-2 kappa} - 1. The two rare cases below are branches rather
         // than selects: a wave in which no site takes one skips its work.
         float A = E - 1.0f;
-        if (z > -0.35f) {  // 2 kappa < 0.35: the Taylor series
+        if (__builtin_expect(z > -0.35f, 0)) {  // 2 kappa < 0.35: the Taylor series (rare)
             float p = 2.7557319e-6f;  // 1/9!, then Horner down to 1/2!
             p = fmaf(z, p, 2.4801588e-5f);
             p = fmaf(z, p, 1.9841270e-4f);
@@ -264,7 +264,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
         const float xo = fmaf(omu, E, u1);  // x
         upper = xo * xo >= E;               // x >= e^{-kappa}, i.e. c >= 0
         float X = xo, Y = omu * A;
-        if (!upper) {  // c < 0, with probability about e^{-kappa}
+        if (__builtin_expect(!upper, 0)) {  // c < 0, with probability about e^{-kappa}
             // c < 0 needs kappa < 17 (u >= 2^-24), where E is a normal number
             const float yb = u1 * (HW ? -A * hw_rcp(E) : div_nr(-A, E));
             X = 1.0f + yb;
@@ -282,7 +282,7 @@ __device__ __forceinline__ v3 heat_bath(v3 h, float beta, uint32_t w0, uint32_t 
     const float c = upper ? 1.0f - omc : opc - 1.0f;
     v3 e1, e2;
     const float rxy = fmaf(n.x, n.x, n.y * n.y);
-    if (n.z < 0.0f && rxy == 0.0f) {
+    if (__builtin_expect(n.z < 0.0f && rxy == 0.0f, 0)) {  // n = -z exactly
         e1 = v3{-1.0f, 0.0f, 0.0f};
         e2 = v3{0.0f, 1.0f, 0.0f};
     } else {
