@@ -405,12 +405,23 @@ struct Codec<0> {  // float32: stored renormalised, read as is
         a = v3{r.x.x, r.y.x, r.z.x};
         b = v3{r.x.y, r.y.y, r.z.y};
     }
+    // The codes of a pair, and their store: a stored value is decode_pair of
+    // encode_pair, so a caller that stores and reads back encodes once.
+    __device__ static __forceinline__ R encode_pair(v3 a, v3 b)
+    {
+        return R{make_float2(a.x, b.x), make_float2(a.y, b.y), make_float2(a.z, b.z)};
+    }
+    template <bool B32 = false>
+    __device__ static __forceinline__ void store_raw_pair(T *p, uint32_t cs, uint32_t j0, const R &r)
+    {
+        *reinterpret_cast<float2 *>(elem<B32>(p, j0)) = r.x;
+        *reinterpret_cast<float2 *>(elem<B32>(p, cs + j0)) = r.y;
+        *reinterpret_cast<float2 *>(elem<B32>(p, 2 * cs + j0)) = r.z;
+    }
     template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<float2 *>(elem<B32>(p, j0)) = make_float2(a.x, b.x);
-        *reinterpret_cast<float2 *>(elem<B32>(p, cs + j0)) = make_float2(a.y, b.y);
-        *reinterpret_cast<float2 *>(elem<B32>(p, 2 * cs + j0)) = make_float2(a.z, b.z);
+        store_raw_pair<B32>(p, cs, j0, encode_pair(a, b));
     }
 };
 
@@ -462,14 +473,30 @@ struct Codec<1> {  // float16 components (round to nearest even), renormalised o
         a = normalise_rsq(v3{__low2float(r.x), __low2float(r.y), __low2float(r.z)});
         b = normalise_rsq(v3{__high2float(r.x), __high2float(r.y), __high2float(r.z)});
     }
+    // Each value by the scalar conversion: the compiler would otherwise pair
+    // two of them into gfx950's packed conversion, which rounds results in
+    // float16's subnormal range differently (the empty asm keeps them apart).
+    __device__ static __forceinline__ __half2 pack(float lo, float hi)
+    {
+        __half l = __float2half_rn(lo);
+        asm volatile("" : "+v"(l));
+        return __halves2half2(l, __float2half_rn(hi));
+    }
+    __device__ static __forceinline__ R encode_pair(v3 a, v3 b)
+    {
+        return R{pack(a.x, b.x), pack(a.y, b.y), pack(a.z, b.z)};
+    }
+    template <bool B32 = false>
+    __device__ static __forceinline__ void store_raw_pair(T *p, uint32_t cs, uint32_t j0, const R &r)
+    {
+        *reinterpret_cast<__half2 *>(elem<B32>(p, j0)) = r.x;
+        *reinterpret_cast<__half2 *>(elem<B32>(p, cs + j0)) = r.y;
+        *reinterpret_cast<__half2 *>(elem<B32>(p, 2 * cs + j0)) = r.z;
+    }
     template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<__half2 *>(elem<B32>(p, j0)) = __halves2half2(__float2half_rn(a.x), __float2half_rn(b.x));
-        *reinterpret_cast<__half2 *>(elem<B32>(p, cs + j0)) =
-            __halves2half2(__float2half_rn(a.y), __float2half_rn(b.y));
-        *reinterpret_cast<__half2 *>(elem<B32>(p, 2 * cs + j0)) =
-            __halves2half2(__float2half_rn(a.z), __float2half_rn(b.z));
+        store_raw_pair<B32>(p, cs, j0, encode_pair(a, b));
     }
 };
 
@@ -538,12 +565,21 @@ struct Codec<2> {  // bfloat16 components, renormalised on load
         b = normalise_rsq(v3{__uint_as_float(r.x & 0xFFFF0000u), __uint_as_float(r.y & 0xFFFF0000u),
                              __uint_as_float(r.z & 0xFFFF0000u)});
     }
+    __device__ static __forceinline__ R encode_pair(v3 a, v3 b)
+    {
+        return R{bf16x2_rne(a.x, b.x), bf16x2_rne(a.y, b.y), bf16x2_rne(a.z, b.z)};
+    }
+    template <bool B32 = false>
+    __device__ static __forceinline__ void store_raw_pair(T *p, uint32_t cs, uint32_t j0, const R &r)
+    {
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, j0)) = r.x;
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, cs + j0)) = r.y;
+        *reinterpret_cast<uint32_t *>(elem<B32>(p, 2 * cs + j0)) = r.z;
+    }
     template <bool B32 = false>
     __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
     {
-        *reinterpret_cast<uint32_t *>(elem<B32>(p, j0)) = bf16x2_rne(a.x, b.x);
-        *reinterpret_cast<uint32_t *>(elem<B32>(p, cs + j0)) = bf16x2_rne(a.y, b.y);
-        *reinterpret_cast<uint32_t *>(elem<B32>(p, 2 * cs + j0)) = bf16x2_rne(a.z, b.z);
+        store_raw_pair<B32>(p, cs, j0, encode_pair(a, b));
     }
 };
 
@@ -615,10 +651,16 @@ struct Codec<3> {
         a = oct_decode(r.w.x);
         b = oct_decode(r.w.y);
     }
+    __device__ static __forceinline__ R encode_pair(v3 a, v3 b) { return R{make_uint2(oct_encode(a), oct_encode(b))}; }
     template <bool B32 = false>
-    __device__ static __forceinline__ void store_pair(T *p, uint32_t, uint32_t j0, v3 a, v3 b)
+    __device__ static __forceinline__ void store_raw_pair(T *p, uint32_t, uint32_t j0, const R &r)
     {
-        *reinterpret_cast<uint2 *>(elem<B32>(p, j0)) = make_uint2(oct_encode(a), oct_encode(b));
+        *reinterpret_cast<uint2 *>(elem<B32>(p, j0)) = r.w;
+    }
+    template <bool B32 = false>
+    __device__ static __forceinline__ void store_pair(T *p, uint32_t cs, uint32_t j0, v3 a, v3 b)
+    {
+        store_raw_pair<B32>(p, cs, j0, encode_pair(a, b));
     }
 };
 

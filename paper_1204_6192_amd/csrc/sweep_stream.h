@@ -202,10 +202,12 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
                 s0 = over_relax<STORE == 0>(old0, h0);
                 s1 = over_relax<STORE == 0>(old1, h1);
             }
-            C::template store_pair<UNI>(own, Nh, j0, s0, s1);
+            const typename C::R code = C::encode_pair(s0, s1);
+            C::template store_raw_pair<UNI>(own, Nh, j0, code);
             if (ENERGY) {
-                // each bond has exactly one endpoint on this (odd) parity
-                const v3 v0 = C::stored_value(s0), v1 = C::stored_value(s1);
+                // each bond has exactly one endpoint on this (odd) parity; the stored values
+                v3 v0, v1;
+                C::decode_pair(code, v0, v1);
                 e -= (double)v0.x * hx0 + (double)v0.y * hy0 + (double)v0.z * hz0;
                 e -= (double)v1.x * hx1 + (double)v1.y * hy1 + (double)v1.z * hz1;
                 if (field) {  // field term of the even sites at my two half-indices
@@ -240,12 +242,15 @@ __device__ __forceinline__ void stream_body(const StreamArgs &a, const int lb, f
 // the plane staged in LDS at offset lo (with the thread's own two positions of
 // that plane in c0, c1 and the third x neighbour read from LDS), the z
 // neighbours in registers. Same arithmetic and neighbour order as the
-// single-pass kernels. Returns the energy term of the two sites when ENERGY.
+// single-pass kernels. Gives the codes of the two new spins and their stored
+// values (the codes read back); returns the energy term of the two sites when
+// ENERGY.
 template <int STORE, int KIND, bool ENERGY>
 __device__ __forceinline__ double update_pair(const float *lds, int lo, int cstride, int Lh, int lrow, int lrm,
                                               int lrp, int xh0, int o, v3 c0, v3 c1, v3 zp0, v3 zp1, v3 zm0,
                                               v3 zm1, const float2 (&jc)[6], v3 hs0, v3 hs1, v3 old0, v3 old1,
-                                              u32x4 rr, float beta, v3 &s0, v3 &s1)
+                                              u32x4 rr, float beta, typename Codec<STORE>::R &code, v3 &s0,
+                                              v3 &s1)
 {
     using C = Codec<STORE>;
     const int xe = o ? (xh0 + 2 == Lh ? 0 : xh0 + 2) : (xh0 == 0 ? Lh - 1 : xh0 - 1);
@@ -287,18 +292,21 @@ __device__ __forceinline__ double update_pair(const float *lds, int lo, int cstr
             hz1 = fma((double)jc[n].y, (double)nb1[n].z, hz1);
         }
     }
+    v3 n0, n1;
     if (KIND != 1) {
-        s0 = heat_bath<KIND == 2, STORE == 0>(h0, beta, rr.x, rr.y);
-        s1 = heat_bath<KIND == 2, STORE == 0>(h1, beta, rr.z, rr.w);
+        n0 = heat_bath<KIND == 2, STORE == 0>(h0, beta, rr.x, rr.y);
+        n1 = heat_bath<KIND == 2, STORE == 0>(h1, beta, rr.z, rr.w);
     } else {
-        s0 = over_relax<STORE == 0>(old0, h0);
-        s1 = over_relax<STORE == 0>(old1, h1);
+        n0 = over_relax<STORE == 0>(old0, h0);
+        n1 = over_relax<STORE == 0>(old1, h1);
     }
+    // the codes, and the values that reading them back gives (the stored values)
+    code = C::encode_pair(n0, n1);
+    C::decode_pair(code, s0, s1);
     double e = 0.0;
     if (ENERGY) {
-        const v3 v0 = C::stored_value(s0), v1 = C::stored_value(s1);
-        e -= (double)v0.x * hx0 + (double)v0.y * hy0 + (double)v0.z * hz0;
-        e -= (double)v1.x * hx1 + (double)v1.y * hy1 + (double)v1.z * hz1;
+        e -= (double)s0.x * hx0 + (double)s0.y * hy0 + (double)s0.z * hz0;
+        e -= (double)s1.x * hx1 + (double)s1.y * hy1 + (double)s1.z * hz1;
     }
     return e;
 }
@@ -417,22 +425,21 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
         }
         __syncthreads();
         if (active) {
-            v3 sA0, sA1;
+            v3 sA0, sA1;  // later stages read the stored (rounded) values, as the single passes do
+            typename C::R cA;
             update_pair<STORE, KIND, false>(lds, lA[z & 1], cstride, Lh, ty, lrm, lrp, xh0, (y + z) & 1, o_cur0,
                                             o_cur1, o_nxt0, o_nxt1, o_prv0, o_prv1, jcA, hA0, hA1, oldA0, oldA1, rrA,
-                                            beta, sA0, sA1);
-            C::template store_pair<true>(sp0, Nh, jA, sA0, sA1);
-            // later stages read the stored (rounded) values, as the single passes do
-            sA0 = C::stored_value(sA0);
-            sA1 = C::stored_value(sA1);
+                                            beta, cA, sA0, sA1);
+            C::template store_raw_pair<true>(sp0, Nh, jA, cA);
             lds_put_pair(lds, lB[z & 1] + lrow_w, cstride, sA0, sA1);
             if (z < 2) lds_put_pair(lds, lS[z] + lrow_w, cstride, sA0, sA1);
             if (doB) {
                 v3 sB0, sB1;
+                typename C::R cB;
                 e += update_pair<STORE, KIND, ENERGY>(lds, lB[(z - 1) & 1], cstride, Lh, ty, lrm, lrp, xh0,
                                                       (y + z) & 1, a_m10, a_m11, sA0, sA1, a_m20, a_m21, jcB, hB0,
-                                                      hB1, o_prv0, o_prv1, rrB, beta, sB0, sB1);
-                C::template store_pair<true>(sp1, Nh, jB, sB0, sB1);
+                                                      hB1, o_prv0, o_prv1, rrB, beta, cB, sB0, sB1);
+                C::template store_raw_pair<true>(sp1, Nh, jB, cB);
                 if (ENERGY && field) {  // field on the parity-0 sites at the same half-indices
                     const float2 fx = *reinterpret_cast<const float2 *>(elem<true>(H0, jB));
                     const float2 fy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + jB));
@@ -477,16 +484,17 @@ __device__ __forceinline__ void pair_body(const StreamArgs &a, const int lb, flo
             lds_get_pair(lds, lS[0] + lrow_w, cstride, n00, n01);
             lds_get_pair(lds, lS[1] + lrow_w, cstride, n10, n11);
             v3 sL0, sL1, sZ0, sZ1;
+            typename C::R cL, cZ;
             // plane L - 1: parity-0 neighbours L - 2 (a_m2), L - 1 (a_m1, LDS B), 0 (saved)
             e += update_pair<STORE, KIND, ENERGY>(lds, lB[(L - 1) & 1], cstride, Lh, ty, lrm, lrp, xh0,
                                                   (y + L) & 1, a_m10, a_m11, n00, n01, a_m20, a_m21, jcL, hL0, hL1,
-                                                  o_prv0, o_prv1, rrL, beta, sL0, sL1);
+                                                  o_prv0, o_prv1, rrL, beta, cL, sL0, sL1);
             // plane 0: parity-0 neighbours L - 1 (a_m1), 0 (saved, LDS S0), 1 (saved)
             e += update_pair<STORE, KIND, ENERGY>(lds, lS[0], cstride, Lh, ty, lrm, lrp, xh0, (y + 1) & 1, n00,
                                                   n01, n10, n11, a_m10, a_m11, jc0, hZ0, hZ1, o_cur0, o_cur1, rr0,
-                                                  beta, sZ0, sZ1);
-            C::template store_pair<true>(sp1, Nh, jL, sL0, sL1);
-            C::template store_pair<true>(sp1, Nh, j0, sZ0, sZ1);
+                                                  beta, cZ, sZ0, sZ1);
+            C::template store_raw_pair<true>(sp1, Nh, jL, cL);
+            C::template store_raw_pair<true>(sp1, Nh, j0, cZ);
             if (ENERGY && field) {
                 const float2 fx = *reinterpret_cast<const float2 *>(elem<true>(H0, jL));
                 const float2 fy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + jL));
@@ -703,11 +711,12 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
                     od1 = pick(i <= L - 3, qb[s - 2][2], pick(i == L - 2, h1, fb[s - 2]));
                 }
             }
-            v3 r0, r1;
+            v3 r0, r1;  // the stored values of the new spins
+            typename C::R code;
             if constexpr (s == D - 1) {
                 e += update_pair<STORE, 1, ENERGY>(lds, lo, cstride, Lh, ty, lrm, lrp, xh0, o, c0, c1, zp0, zp1, zm0,
                                                    zm1, jc[s], hs0[s], hs1[s], od0, od1, u32x4{0u, 0u, 0u, 0u}, 0.0f,
-                                                   r0, r1);
+                                                   code, r0, r1);
                 if (ENERGY && field) {  // field on the parity-0 sites at the same half-indices: stage D - 2
                     const float2 fx = *reinterpret_cast<const float2 *>(elem<true>(H0, jw));
                     const float2 fy = *reinterpret_cast<const float2 *>(elem<true>(H0, Nh + jw));
@@ -718,12 +727,10 @@ __device__ __forceinline__ void quad_body(const StreamArgs &a, const int lb, flo
             } else {
                 (void)update_pair<STORE, 1, false>(lds, lo, cstride, Lh, ty, lrm, lrp, xh0, o, c0, c1, zp0, zp1, zm0,
                                                    zm1, jc[s], hs0[s], hs1[s], od0, od1, u32x4{0u, 0u, 0u, 0u}, 0.0f,
-                                                   r0, r1);
+                                                   code, r0, r1);
             }
-            if (s >= D - 2) C::template store_pair<true>((s & 1) ? sp1 : sp0, Nh, jw, r0, r1);
+            if (s >= D - 2) C::template store_raw_pair<true>((s & 1) ? sp1 : sp0, Nh, jw, code);
             if constexpr (s < D - 1) {
-                r0 = C::stored_value(r0);
-                r1 = C::stored_value(r1);
                 lds_put_pair(lds, l_ring(s, K & 1) + lrow_w, cstride, r0, r1);
                 if constexpr (!F) {
                     if (i == 0) lds_put_pair(lds, l_saved(s) + lrow_w, cstride, r0, r1);
