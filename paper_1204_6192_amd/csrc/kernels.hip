@@ -746,6 +746,158 @@ __global__ __launch_bounds__(128) void k_kmodes_finish(KmodeArgs a)
     a.q[dk * 84 + m] = v / (double)(2 * a.Nh);
 }
 
+// The chiral group (G = 2) for lattices whose whole plane fits a work-group
+// (L % 4 == 0, L <= 32): one work-group per (sample, rung) marches over z with
+// plane z of both copies staged in LDS and the planes z - 1, z and z + 1 at the
+// thread's own sites in registers, so that every spin is read from memory once
+// instead of seven times (the gathering kernel's own site and six neighbours).
+// The thread of row y and quarter q owns the sites x = 4q .. 4q + 3. The
+// per-site arithmetic is the gathering kernel's (float64 chiralities, the same
+// phase tables); the sums over sites run in another order, so the two agree to
+// float64 rounding. The sums go to partial block 0, zeros to the others.
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    constexpr int K = KGroup<2>::count;
+    extern __shared__ __align__(16) float plane[];  // [2 buffers][2 copies][3][L][L]
+    __shared__ double red[4][K];
+    __shared__ double cph[32], sph[32];
+    const int L = a.L, Lh = L >> 1, Q = L >> 2, LL = L * L;
+    for (int r = threadIdx.x; r < L; r += blockDim.x) {
+        double sv, cv;
+        sincospi(2.0 * (double)r / (double)L, &sv, &cv);
+        cph[r] = cv;
+        sph[r] = sv;
+    }
+    const int64_t dk = blockIdx.x;  // d * T + k
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int64_t Nh = a.Nh;
+    const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
+    const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
+    const T *R[2] = {(const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh,
+                     (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh};
+    const int tid = threadIdx.x;
+    const bool active = tid < L * Q;
+    const int y = active ? tid / Q : 0, x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    const int ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+    const int xm = x0 == 0 ? L - 1 : x0 - 1, xp = x0 + 4 == L ? 0 : x0 + 4;
+    // my four sites of plane zz of copy c: x0 and x0 + 2 lie on the parity of
+    // y + zz, at half-indices x0 / 2 and x0 / 2 + 1; x0 + 1 and x0 + 3 on the other
+    auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) {
+        const int p0 = (y + zz) & 1;
+        const uint32_t jj = (uint32_t)((zz * L + y) * Lh + (x0 >> 1));
+        C::load_raw_pair(R[c] + (int64_t)p0 * C::kPlanes * Nh, (uint32_t)Nh, jj, e);
+        C::load_raw_pair(R[c] + (int64_t)(1 - p0) * C::kPlanes * Nh, (uint32_t)Nh, jj, f);
+    };
+    auto decode4 = [&](const typename C::R &e, const typename C::R &f, v3 (&s)[4]) {
+        C::decode_pair(e, s[0], s[2]);
+        C::decode_pair(f, s[1], s[3]);
+    };
+    v3 prv[2][4], cur[2][4], nxt[2][4];
+    typename C::R ne[2], nf[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        typename C::R e, f;
+        load4(c, L - 1, e, f);
+        decode4(e, f, prv[c]);
+        load4(c, 0, e, f);
+        decode4(e, f, cur[c]);
+        load4(c, 1, ne[c], nf[c]);
+    }
+    double acc[K];
+#pragma unroll
+    for (int m = 0; m < K; ++m) acc[m] = 0.0;
+    auto lp = [&](int b, int c, int m) { return plane + ((b * 2 + c) * 3 + m) * LL; };
+    __syncthreads();  // the phase tables
+    for (int z = 0; z < L; ++z) {
+        const int b = z & 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            decode4(ne[c], nf[c], nxt[c]);
+            const int zn = z + 2 < L ? z + 2 : z + 2 - L;  // the next step's plane z + 1 (wrapping)
+            load4(c, zn, ne[c], nf[c]);
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    const float4 v = m == 0 ? make_float4(cur[c][0].x, cur[c][1].x, cur[c][2].x, cur[c][3].x)
+                                   : m == 1 ? make_float4(cur[c][0].y, cur[c][1].y, cur[c][2].y, cur[c][3].y)
+                                            : make_float4(cur[c][0].z, cur[c][1].z, cur[c][2].z, cur[c][3].z);
+                    *reinterpret_cast<float4 *>(lp(b, c, m) + y * L + x0) = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (active) {
+            double kap[2][4][3];  // chirality of copy c, site u, axis alpha
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                v3 ypl[4], ymi[4], xl, xr;
+                {
+                    const float4 a0 = *reinterpret_cast<const float4 *>(lp(b, c, 0) + yp * L + x0);
+                    const float4 a1 = *reinterpret_cast<const float4 *>(lp(b, c, 1) + yp * L + x0);
+                    const float4 a2 = *reinterpret_cast<const float4 *>(lp(b, c, 2) + yp * L + x0);
+                    ypl[0] = v3{a0.x, a1.x, a2.x}; ypl[1] = v3{a0.y, a1.y, a2.y};
+                    ypl[2] = v3{a0.z, a1.z, a2.z}; ypl[3] = v3{a0.w, a1.w, a2.w};
+                    const float4 b0 = *reinterpret_cast<const float4 *>(lp(b, c, 0) + ym * L + x0);
+                    const float4 b1 = *reinterpret_cast<const float4 *>(lp(b, c, 1) + ym * L + x0);
+                    const float4 b2 = *reinterpret_cast<const float4 *>(lp(b, c, 2) + ym * L + x0);
+                    ymi[0] = v3{b0.x, b1.x, b2.x}; ymi[1] = v3{b0.y, b1.y, b2.y};
+                    ymi[2] = v3{b0.z, b1.z, b2.z}; ymi[3] = v3{b0.w, b1.w, b2.w};
+                    xl = v3{lp(b, c, 0)[y * L + xm], lp(b, c, 1)[y * L + xm], lp(b, c, 2)[y * L + xm]};
+                    xr = v3{lp(b, c, 0)[y * L + xp], lp(b, c, 1)[y * L + xp], lp(b, c, 2)[y * L + xp]};
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const v3 xplus = u == 3 ? xr : cur[c][u == 3 ? 0 : u + 1];
+                    const v3 xminus = u == 0 ? xl : cur[c][u == 0 ? 0 : u - 1];
+                    kap[c][u][0] = chirality(xplus, cur[c][u], xminus);
+                    kap[c][u][1] = chirality(ypl[u], cur[c][u], ymi[u]);
+                    kap[c][u][2] = chirality(nxt[c][u], cur[c][u], prv[c][u]);
+                }
+            }
+            const double cz0 = cph[z], snz = sph[z], cy0 = cph[y], sny = sph[y];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double cx0 = cph[x0 + u], snx = sph[x0 + u];
+#pragma unroll
+                for (int al = 0; al < 3; ++al) {
+                    const double g = kap[0][u][al] * kap[1][u][al];
+                    acc[7 * al] += g;
+                    acc[7 * al + 1] = fma(g, cx0, acc[7 * al + 1]);
+                    acc[7 * al + 2] = fma(g, snx, acc[7 * al + 2]);
+                    acc[7 * al + 3] = fma(g, cy0, acc[7 * al + 3]);
+                    acc[7 * al + 4] = fma(g, sny, acc[7 * al + 4]);
+                    acc[7 * al + 5] = fma(g, cz0, acc[7 * al + 5]);
+                    acc[7 * al + 6] = fma(g, snz, acc[7 * al + 6]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                prv[c][u] = cur[c][u];
+                cur[c][u] = nxt[c][u];
+            }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = (int)(blockDim.x >> 6);
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) red[wave][m] = v;
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < K * a.n_pb; m += blockDim.x) {
+        const int pb = m / K, mm = m - pb * K;
+        double v = 0.0;
+        if (pb == 0)
+            for (int w = 0; w < n_waves; ++w) v += red[w][mm];
+        a.partials[(dk * a.n_pb + pb) * 84 + KGroup<2>::first + mm] = v;
+    }
+}
+
 template <int STORE>
 static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
 {
@@ -753,10 +905,17 @@ static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
     // a replica's spins within 4 GiB: 32-bit offsets from its base
     const bool b32 = 2 * (uint64_t)Codec<STORE>::kPlanes * (uint64_t)a.Nh * sizeof(typename Codec<STORE>::T) <
                      (1ull << 32);
+    // the chiral group as a z-march where a whole plane fits a work-group
+    const bool march = a.L % 4 == 0 && a.L <= 32;
+    if (march) {
+        const unsigned threads = (unsigned)((a.L * (a.L / 4) + 63) / 64 * 64);
+        const size_t lds = (size_t)2 * 2 * 3 * a.L * a.L * sizeof(float);
+        hipLaunchKernelGGL((k_chiral_stream<STORE>), dim3((unsigned)((int64_t)a.D * a.T)), dim3(threads), lds, s, a);
+    }
     if (b32) {
         hipLaunchKernelGGL((k_kmodes<STORE, 0, true>), grid, block, 0, s, a);
         hipLaunchKernelGGL((k_kmodes<STORE, 1, true>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((k_kmodes<STORE, 2, true>), grid, block, 0, s, a);
+        if (!march) hipLaunchKernelGGL((k_kmodes<STORE, 2, true>), grid, block, 0, s, a);
     } else {
         hipLaunchKernelGGL((k_kmodes<STORE, 0, false>), grid, block, 0, s, a);
         hipLaunchKernelGGL((k_kmodes<STORE, 1, false>), grid, block, 0, s, a);
