@@ -746,15 +746,147 @@ __global__ __launch_bounds__(128) void k_kmodes_finish(KmodeArgs a)
     a.q[dk * 84 + m] = v / (double)(2 * a.Nh);
 }
 
+// The spin-overlap groups (G = 0 and 1, outputs 0 .. 62) in one pass for the
+// lattices the chiral z-march takes (L % 4 == 0, L <= 32): one work-group per
+// (sample, rung), the thread of row y and quarter q holding the sites
+// x = 4q .. 4q + 3 of plane z as z advances, the next plane's loads issued a
+// step ahead. Since x and y stay fixed per thread, the phase factors split:
+// per step the thread adds its four products s^mu(1) s^nu(2) with weights 1,
+// cos kx and sin kx, and accumulates those three sums over z, the first also
+// weighted by cos kz and sin kz; q(k_y) is cos ky and sin ky times the
+// unweighted sum at the end. 45 float64 accumulators replace the 63 of the two
+// gathering passes, and both copies are read once instead of twice. The sums
+// run in another order than the gathering kernel's, so the two agree to
+// float64 rounding. The sums go to partial block 0, zeros to the others.
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    constexpr int K = KGroup<0>::count + KGroup<1>::count;  // 63
+    __shared__ double red[4][K];
+    __shared__ double cph[32], sph[32];
+    const int L = a.L, Lh = L >> 1, Q = L >> 2;
+    for (int r = threadIdx.x; r < L; r += blockDim.x) {
+        double sv, cv;
+        sincospi(2.0 * (double)r / (double)L, &sv, &cv);
+        cph[r] = cv;
+        sph[r] = sv;
+    }
+    const int64_t dk = blockIdx.x;  // d * T + k
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int64_t Nh = a.Nh;
+    const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
+    const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
+    const T *R[2] = {(const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh,
+                     (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh};
+    const int tid = threadIdx.x;
+    const bool active = tid < L * Q;
+    const int y = active ? tid / Q : 0, x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    // the four sites of plane zz of copy c: x0 and x0 + 2 on the parity of
+    // y + zz (half-indices x0 / 2, x0 / 2 + 1), x0 + 1 and x0 + 3 on the other
+    auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) {
+        const int p0 = (y + zz) & 1;
+        const uint32_t jj = (uint32_t)((zz * L + y) * Lh + (x0 >> 1));
+        C::load_raw_pair(R[c] + (int64_t)p0 * C::kPlanes * Nh, (uint32_t)Nh, jj, e);
+        C::load_raw_pair(R[c] + (int64_t)(1 - p0) * C::kPlanes * Nh, (uint32_t)Nh, jj, f);
+    };
+    typename C::R ne[2], nf[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) load4(c, 0, ne[c], nf[c]);
+    double A0[9], Ac[9], As[9], Zc[9], Zs[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) A0[m] = Ac[m] = As[m] = Zc[m] = Zs[m] = 0.0;
+    __syncthreads();  // the phase tables
+    double cx[4], sx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        cx[u] = cph[x0 + u];
+        sx[u] = sph[x0 + u];
+    }
+    for (int z = 0; z < L; ++z) {
+        v3 s[2][4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            C::decode_pair(ne[c], s[c][0], s[c][2]);
+            C::decode_pair(nf[c], s[c][1], s[c][3]);
+            if (z + 1 < L) load4(c, z + 1, ne[c], nf[c]);
+        }
+        if (active) {
+            const double cz = cph[z], sz = sph[z];
+            double av[4][3], bv[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                av[u][0] = s[0][u].x; av[u][1] = s[0][u].y; av[u][2] = s[0][u].z;
+                bv[u][0] = s[1][u].x; bv[u][1] = s[1][u].y; bv[u][2] = s[1][u].z;
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m)
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const int mn = 3 * m + n;
+                    double t0 = 0.0, tc = 0.0, ts = 0.0;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double f = av[u][m] * bv[u][n];
+                        t0 += f;
+                        tc = fma(f, cx[u], tc);
+                        ts = fma(f, sx[u], ts);
+                    }
+                    A0[mn] += t0;
+                    Ac[mn] += tc;
+                    As[mn] += ts;
+                    Zc[mn] = fma(t0, cz, Zc[mn]);
+                    Zs[mn] = fma(t0, sz, Zs[mn]);
+                }
+        }
+    }
+    const double cy = cph[y], sy = sph[y];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = (int)(blockDim.x >> 6);
+#pragma unroll
+    for (int mn = 0; mn < 9; ++mn) {
+        // the output layout of the gathering kernel: group 0 holds q(0) at mn and
+        // q(k_x) at 9 + 2 mn (cos, sin); group 1 q(k_y) at 27 + 2 mn and q(k_z)
+        // at 45 + 2 mn
+        const double v0 = wave_sum(A0[mn]), v1 = wave_sum(Ac[mn]), v2 = wave_sum(As[mn]);
+        const double v3c = wave_sum(cy * A0[mn]), v4 = wave_sum(sy * A0[mn]);
+        const double v5 = wave_sum(Zc[mn]), v6 = wave_sum(Zs[mn]);
+        if (lane == 0) {
+            red[wave][mn] = v0;
+            red[wave][9 + 2 * mn] = v1;
+            red[wave][9 + 2 * mn + 1] = v2;
+            red[wave][27 + 2 * mn] = v3c;
+            red[wave][27 + 2 * mn + 1] = v4;
+            red[wave][45 + 2 * mn] = v5;
+            red[wave][45 + 2 * mn + 1] = v6;
+        }
+    }
+    __syncthreads();
+    for (int m = threadIdx.x; m < K * a.n_pb; m += blockDim.x) {
+        const int pb = m / K, mm = m - pb * K;
+        double v = 0.0;
+        if (pb == 0)
+            for (int w = 0; w < n_waves; ++w) v += red[w][mm];
+        a.partials[(dk * a.n_pb + pb) * 84 + mm] = v;
+    }
+}
+
 // The chiral group (G = 2) for lattices whose whole plane fits a work-group
 // (L % 4 == 0, L <= 32): one work-group per (sample, rung) marches over z with
 // plane z of both copies staged in LDS and the planes z - 1, z and z + 1 at the
 // thread's own sites in registers, so that every spin is read from memory once
 // instead of seven times (the gathering kernel's own site and six neighbours).
 // The thread of row y and quarter q owns the sites x = 4q .. 4q + 3. The
-// per-site arithmetic is the gathering kernel's (float64 chiralities, the same
-// phase tables); the sums over sites run in another order, so the two agree to
-// float64 rounding. The sums go to partial block 0, zeros to the others.
+// chiralities are float64 as in the gathering kernel; along x, pairs of
+// neighbouring sites share one cross product (kappa at x0 and x0 + 1 both use
+// s(x0 + 1) x s(x0), by the cyclic symmetry of the triple product), and the
+// phase factors split as in the overlap march (x and y fixed per thread): per
+// step and axis the thread adds its four products kappa(1) kappa(2) with
+// weights 1, cos kx and sin kx and accumulates those over z, the first also
+// weighted by cos kz and sin kz; q_c(k_y) is cos ky and sin ky times the
+// unweighted sum at the end. The sums run in another order than the gathering
+// kernel's, so the two agree to float64 rounding. The sums go to partial block
+// 0, zeros to the others.
 template <int STORE>
 __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
 {
@@ -806,11 +938,17 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
         decode4(e, f, cur[c]);
         load4(c, 1, ne[c], nf[c]);
     }
-    double acc[K];
+    double P0[3], Pc[3], Ps[3], Zc[3], Zs[3];
 #pragma unroll
-    for (int m = 0; m < K; ++m) acc[m] = 0.0;
+    for (int al = 0; al < 3; ++al) P0[al] = Pc[al] = Ps[al] = Zc[al] = Zs[al] = 0.0;
     auto lp = [&](int b, int c, int m) { return plane + ((b * 2 + c) * 3 + m) * LL; };
     __syncthreads();  // the phase tables
+    double cx[4], sx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        cx[u] = cph[x0 + u];
+        sx[u] = sph[x0 + u];
+    }
     for (int z = 0; z < L; ++z) {
         const int b = z & 1;
 #pragma unroll
@@ -848,30 +986,35 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
                     xl = v3{lp(b, c, 0)[y * L + xm], lp(b, c, 1)[y * L + xm], lp(b, c, 2)[y * L + xm]};
                     xr = v3{lp(b, c, 0)[y * L + xp], lp(b, c, 1)[y * L + xp], lp(b, c, 2)[y * L + xp]};
                 }
+                const v3 (&w)[4] = cur[c];
+                // kappa_x(u) = s(u+1) . (s(u) x s(u-1)); x0 and x0 + 1 share
+                // s(x0+1) x s(x0), x0 + 2 and x0 + 3 share s(x0+3) x s(x0+2)
+                kap[c][0][0] = chirality(xl, w[1], w[0]);
+                kap[c][1][0] = chirality(w[2], w[1], w[0]);
+                kap[c][2][0] = chirality(w[1], w[3], w[2]);
+                kap[c][3][0] = chirality(xr, w[3], w[2]);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const v3 xplus = u == 3 ? xr : cur[c][u == 3 ? 0 : u + 1];
-                    const v3 xminus = u == 0 ? xl : cur[c][u == 0 ? 0 : u - 1];
-                    kap[c][u][0] = chirality(xplus, cur[c][u], xminus);
-                    kap[c][u][1] = chirality(ypl[u], cur[c][u], ymi[u]);
-                    kap[c][u][2] = chirality(nxt[c][u], cur[c][u], prv[c][u]);
+                    kap[c][u][1] = chirality(ypl[u], w[u], ymi[u]);
+                    kap[c][u][2] = chirality(nxt[c][u], w[u], prv[c][u]);
                 }
             }
-            const double cz0 = cph[z], snz = sph[z], cy0 = cph[y], sny = sph[y];
+            const double cz = cph[z], sz = sph[z];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const double cx0 = cph[x0 + u], snx = sph[x0 + u];
+            for (int al = 0; al < 3; ++al) {
+                double t0 = 0.0, tc = 0.0, ts = 0.0;
 #pragma unroll
-                for (int al = 0; al < 3; ++al) {
+                for (int u = 0; u < 4; ++u) {
                     const double g = kap[0][u][al] * kap[1][u][al];
-                    acc[7 * al] += g;
-                    acc[7 * al + 1] = fma(g, cx0, acc[7 * al + 1]);
-                    acc[7 * al + 2] = fma(g, snx, acc[7 * al + 2]);
-                    acc[7 * al + 3] = fma(g, cy0, acc[7 * al + 3]);
-                    acc[7 * al + 4] = fma(g, sny, acc[7 * al + 4]);
-                    acc[7 * al + 5] = fma(g, cz0, acc[7 * al + 5]);
-                    acc[7 * al + 6] = fma(g, snz, acc[7 * al + 6]);
+                    t0 += g;
+                    tc = fma(g, cx[u], tc);
+                    ts = fma(g, sx[u], ts);
                 }
+                P0[al] += t0;
+                Pc[al] += tc;
+                Ps[al] += ts;
+                Zc[al] = fma(t0, cz, Zc[al]);
+                Zs[al] = fma(t0, sz, Zs[al]);
             }
         }
 #pragma unroll
@@ -882,11 +1025,24 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
                 cur[c][u] = nxt[c][u];
             }
     }
+    const double cy = cph[y], sy = sph[y];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = (int)(blockDim.x >> 6);
 #pragma unroll
-    for (int m = 0; m < K; ++m) {
-        const double v = wave_sum(acc[m]);
-        if (lane == 0) red[wave][m] = v;
+    for (int al = 0; al < 3; ++al) {
+        // the gathering kernel's layout: per axis, k = 0, then (cos, sin) of
+        // k_x, k_y, k_z
+        const double v0 = wave_sum(P0[al]), v1 = wave_sum(Pc[al]), v2 = wave_sum(Ps[al]);
+        const double v3c = wave_sum(cy * P0[al]), v4 = wave_sum(sy * P0[al]);
+        const double v5 = wave_sum(Zc[al]), v6 = wave_sum(Zs[al]);
+        if (lane == 0) {
+            red[wave][7 * al] = v0;
+            red[wave][7 * al + 1] = v1;
+            red[wave][7 * al + 2] = v2;
+            red[wave][7 * al + 3] = v3c;
+            red[wave][7 * al + 4] = v4;
+            red[wave][7 * al + 5] = v5;
+            red[wave][7 * al + 6] = v6;
+        }
     }
     __syncthreads();
     for (int m = threadIdx.x; m < K * a.n_pb; m += blockDim.x) {
@@ -905,17 +1061,19 @@ static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
     // a replica's spins within 4 GiB: 32-bit offsets from its base
     const bool b32 = 2 * (uint64_t)Codec<STORE>::kPlanes * (uint64_t)a.Nh * sizeof(typename Codec<STORE>::T) <
                      (1ull << 32);
-    // the chiral group as a z-march where a whole plane fits a work-group
+    // z-marches where a whole plane fits a work-group: the overlap groups in one
+    // pass, the chiral group in another
     const bool march = a.L % 4 == 0 && a.L <= 32;
     if (march) {
         const unsigned threads = (unsigned)((a.L * (a.L / 4) + 63) / 64 * 64);
         const size_t lds = (size_t)2 * 2 * 3 * a.L * a.L * sizeof(float);
-        hipLaunchKernelGGL((k_chiral_stream<STORE>), dim3((unsigned)((int64_t)a.D * a.T)), dim3(threads), lds, s, a);
-    }
-    if (b32) {
+        const dim3 cols((unsigned)((int64_t)a.D * a.T));
+        hipLaunchKernelGGL((k_qk_stream<STORE>), cols, dim3(threads), 0, s, a);
+        hipLaunchKernelGGL((k_chiral_stream<STORE>), cols, dim3(threads), lds, s, a);
+    } else if (b32) {
         hipLaunchKernelGGL((k_kmodes<STORE, 0, true>), grid, block, 0, s, a);
         hipLaunchKernelGGL((k_kmodes<STORE, 1, true>), grid, block, 0, s, a);
-        if (!march) hipLaunchKernelGGL((k_kmodes<STORE, 2, true>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_kmodes<STORE, 2, true>), grid, block, 0, s, a);
     } else {
         hipLaunchKernelGGL((k_kmodes<STORE, 0, false>), grid, block, 0, s, a);
         hipLaunchKernelGGL((k_kmodes<STORE, 1, false>), grid, block, 0, s, a);

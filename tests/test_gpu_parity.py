@@ -280,9 +280,10 @@ def test_kmodes_against_oracle(hsg, oracle_lib, storage):
         o = _oracle_on_gpu_state(oracle_lib, lat, k, g, seed, storage)
         want = o.measure_kmodes().reshape(-1)
         got = q[off:off + n]
-        err = np.abs(got - want).max()
+        dev = np.abs(got - want)
+        err = dev.max()
         print(f"L={g.L}: max |dq| {err:.2e}, max |q| {np.abs(want).max():.2e}", flush=True)
-        assert err < 1e-12
+        assert err < 1e-12, f"L={g.L}: worst output {int(np.argmax(dev)) % 84} of 84"
         off += n
 
 
