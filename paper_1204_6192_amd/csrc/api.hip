@@ -291,7 +291,10 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > n_pb_stream ? g.n_pb_sweep : n_pb_stream) * 8;
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
-        const uint64_t k_full = (uint64_t)g.D * g.T * g.q_pb * 84 * 8;  // k modes, same blocks
+        // k modes: the overlap's blocks, or one partial per band of the z-marches
+        const int k_rows = hsg::kmode_rows(g.L);
+        const int64_t k_pb = k_rows > 0 ? g.L / k_rows : g.q_pb;
+        const uint64_t k_full = (uint64_t)g.D * g.T * k_pb * 84 * 8;
         const uint64_t p_full = (uint64_t)g.D * g.T * g.q_pb * 7 * (g.O * (g.O - 1) / 2) * 8;  // copy pairs
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
         // the per-sweep series stages the overlap [D][T][10] after its partials
@@ -1482,7 +1485,8 @@ hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = g.q_pb;
+        const int rows = hsg::kmode_rows(g.L);
+        a.n_pb = rows > 0 ? g.L / rows : g.q_pb;
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_kmodes(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_kmodes");

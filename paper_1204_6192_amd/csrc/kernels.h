@@ -200,8 +200,10 @@ struct OverlapArgs {
 };
 hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s);
 
-// Wave-vector dependent and chiral overlaps: partials [D T][n_pb][84], q [D T][84];
-// block pb covers canonical sites [pb chunk, (pb + 1) chunk).
+// Wave-vector dependent and chiral overlaps: partials [D T][n_pb][84], q [D T][84].
+// Gathering passes: block pb covers canonical sites [pb chunk, (pb + 1) chunk).
+// z-marches (kmode_rows(L) > 0): partial pb is band pb of kmode_rows(L) rows,
+// and n_pb must be L / kmode_rows(L).
 struct KmodeArgs {
     const void *spins;
     const int32_t *slot_at_temp;
@@ -211,6 +213,20 @@ struct KmodeArgs {
     int32_t L, D, O, T, n_pb, chunk;
 };
 hipError_t launch_kmodes(const KmodeArgs &a, int storage, hipStream_t s);
+
+// Rows per work-group of the k-mode z-marches: four sites per thread, at most
+// kBlock threads, a divisor of L, and the chiral march's LDS (two buffers x two
+// copies x three components x (rows + two halo rows) x L floats) within 64 KiB.
+// 0 where the marches do not apply (L % 4 != 0, or L > 224); the gathering
+// passes run there.
+__host__ __device__ inline int kmode_rows(int L)
+{
+    if (L < 4 || L % 4 != 0 || L / 4 > kBlock) return 0;
+    int ty = kBlock / (L / 4);
+    if (ty > L) ty = L;
+    while (L % ty != 0) --ty;
+    return (int64_t)2 * 2 * 3 * (ty + 2) * L * 4 <= 65536 ? ty : 0;
+}
 
 // Copy-pair local-overlap sums: partials [D T][n_pb][7 P], q [D T][P][7],
 // P = O (O - 1) / 2 pairs a < b in the order (0,1), (0,2), ..., (1,2), ...

@@ -552,6 +552,8 @@ hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
 // (G = 0: q(0) and q(k_x), 27 values; G = 1: q(k_y), q(k_z), 36; G = 2: the
 // chiral overlaps, 21), one grid column each. The phases exp(i 2 pi R / L) come
 // from a per-block table in float64. Products, chiralities and sums are float64.
+// Lattices with kmode_rows(L) > 0 take the two z-marches further below instead
+// of these gathering passes.
 template <int G>
 struct KGroup;
 template <>
@@ -747,17 +749,17 @@ __global__ __launch_bounds__(128) void k_kmodes_finish(KmodeArgs a)
 }
 
 // The spin-overlap groups (G = 0 and 1, outputs 0 .. 62) in one pass for the
-// lattices the chiral z-march takes (L % 4 == 0, L <= 32): one work-group per
-// (sample, rung), the thread of row y and quarter q holding the sites
-// x = 4q .. 4q + 3 of plane z as z advances, the next plane's loads issued a
-// step ahead. Since x and y stay fixed per thread, the phase factors split:
+// lattices the chiral z-march takes (kmode_rows(L) > 0): one work-group per
+// (sample, rung, band of kmode_rows(L) rows), the thread of row y and quarter q
+// holding the sites x = 4q .. 4q + 3 of plane z as z advances, the next
+// plane's loads issued a step ahead. Since x and y stay fixed per thread, the phase factors split:
 // per step the thread adds its four products s^mu(1) s^nu(2) with weights 1,
 // cos kx and sin kx, and accumulates those three sums over z, the first also
 // weighted by cos kz and sin kz; q(k_y) is cos ky and sin ky times the
 // unweighted sum at the end. 45 float64 accumulators replace the 63 of the two
 // gathering passes, and both copies are read once instead of twice. The sums
 // run in another order than the gathering kernel's, so the two agree to
-// float64 rounding. The sums go to partial block 0, zeros to the others.
+// float64 rounding. A work-group's sums go to the partial of its band.
 template <int STORE>
 __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
 {
@@ -765,15 +767,17 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
     using T = typename C::T;
     constexpr int K = KGroup<0>::count + KGroup<1>::count;  // 63
     __shared__ double red[4][K];
-    __shared__ double cph[32], sph[32];
+    __shared__ double cph[224], sph[224];
     const int L = a.L, Lh = L >> 1, Q = L >> 2;
+    const int TY = kmode_rows(L), n_bands = L / TY;
     for (int r = threadIdx.x; r < L; r += blockDim.x) {
         double sv, cv;
         sincospi(2.0 * (double)r / (double)L, &sv, &cv);
         cph[r] = cv;
         sph[r] = sv;
     }
-    const int64_t dk = blockIdx.x;  // d * T + k
+    const int64_t dk = blockIdx.x / n_bands;  // d * T + k
+    const int band = (int)(blockIdx.x - dk * n_bands);
     const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
     const int64_t Nh = a.Nh;
     const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
@@ -781,8 +785,8 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
     const T *R[2] = {(const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh,
                      (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh};
     const int tid = threadIdx.x;
-    const bool active = tid < L * Q;
-    const int y = active ? tid / Q : 0, x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    const bool active = tid < TY * Q;
+    const int y = band * TY + (active ? tid / Q : 0), x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
     // the four sites of plane zz of copy c: x0 and x0 + 2 on the parity of
     // y + zz (half-indices x0 / 2, x0 / 2 + 1), x0 + 1 and x0 + 3 on the other
     auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) {
@@ -862,20 +866,20 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
         }
     }
     __syncthreads();
-    for (int m = threadIdx.x; m < K * a.n_pb; m += blockDim.x) {
-        const int pb = m / K, mm = m - pb * K;
+    for (int m = threadIdx.x; m < K; m += blockDim.x) {
         double v = 0.0;
-        if (pb == 0)
-            for (int w = 0; w < n_waves; ++w) v += red[w][mm];
-        a.partials[(dk * a.n_pb + pb) * 84 + mm] = v;
+        for (int w = 0; w < n_waves; ++w) v += red[w][m];
+        a.partials[(dk * a.n_pb + band) * 84 + m] = v;
     }
 }
 
-// The chiral group (G = 2) for lattices whose whole plane fits a work-group
-// (L % 4 == 0, L <= 32): one work-group per (sample, rung) marches over z with
-// plane z of both copies staged in LDS and the planes z - 1, z and z + 1 at the
+// The chiral group (G = 2) where kmode_rows(L) > 0: one work-group per
+// (sample, rung, band of TY = kmode_rows(L) rows) marches over z with plane z
+// of both copies staged in LDS and the planes z - 1, z and z + 1 at the
 // thread's own sites in registers, so that every spin is read from memory once
 // instead of seven times (the gathering kernel's own site and six neighbours).
+// Where TY < L the rows just above and below the band (halo rows, read by the
+// first 2 L / 4 threads) are staged too, so bands add 2 / TY to the reads.
 // The thread of row y and quarter q owns the sites x = 4q .. 4q + 3. The
 // chiralities are float64 as in the gathering kernel; along x, pairs of
 // neighbouring sites share one cross product (kappa at x0 and x0 + 1 both use
@@ -885,25 +889,30 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
 // weights 1, cos kx and sin kx and accumulates those over z, the first also
 // weighted by cos kz and sin kz; q_c(k_y) is cos ky and sin ky times the
 // unweighted sum at the end. The sums run in another order than the gathering
-// kernel's, so the two agree to float64 rounding. The sums go to partial block
-// 0, zeros to the others.
-template <int STORE>
-__global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
+// kernel's, so the two agree to float64 rounding. A work-group's sums go to
+// the partial of its band.
+template <int STORE, bool BANDED>
+__global__ __launch_bounds__(kBlock, 2) void k_chiral_stream(KmodeArgs a)
 {
     using C = Codec<STORE>;
     using T = typename C::T;
     constexpr int K = KGroup<2>::count;
-    extern __shared__ __align__(16) float plane[];  // [2 buffers][2 copies][3][L][L]
+    // [2 buffers][2 copies][3 components][TY + 2 rows][L]: row 0 the halo row
+    // below the band, rows 1 .. TY the band, row TY + 1 the halo row above
+    extern __shared__ __align__(16) float plane[];
     __shared__ double red[4][K];
-    __shared__ double cph[32], sph[32];
-    const int L = a.L, Lh = L >> 1, Q = L >> 2, LL = L * L;
+    __shared__ double cph[224], sph[224];
+    const int L = a.L, Lh = L >> 1, Q = L >> 2;
+    const int TY = BANDED ? kmode_rows(L) : L, n_bands = L / TY, RL = (TY + 2) * L;
+    constexpr bool banded = BANDED;  // TY < L
     for (int r = threadIdx.x; r < L; r += blockDim.x) {
         double sv, cv;
         sincospi(2.0 * (double)r / (double)L, &sv, &cv);
         cph[r] = cv;
         sph[r] = sv;
     }
-    const int64_t dk = blockIdx.x;  // d * T + k
+    const int64_t dk = blockIdx.x / n_bands;  // d * T + k
+    const int band = (int)(blockIdx.x - dk * n_bands), y0 = band * TY;
     const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
     const int64_t Nh = a.Nh;
     const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
@@ -911,24 +920,36 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
     const T *R[2] = {(const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh,
                      (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh};
     const int tid = threadIdx.x;
-    const bool active = tid < L * Q;
-    const int y = active ? tid / Q : 0, x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
-    const int ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+    const bool active = tid < TY * Q;
+    const int ly = active ? tid / Q : 0, x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    const int y = y0 + ly;
+    // LDS rows of the band row, the row above (y + 1) and the row below (y - 1)
+    const int lr = ly + 1;
+    const int lrp = banded ? lr + 1 : (ly + 1 == L ? 0 : ly + 1) + 1;
+    const int lrm = banded ? lr - 1 : (ly == 0 ? L - 1 : ly - 1) + 1;
     const int xm = x0 == 0 ? L - 1 : x0 - 1, xp = x0 + 4 == L ? 0 : x0 + 4;
-    // my four sites of plane zz of copy c: x0 and x0 + 2 lie on the parity of
-    // y + zz, at half-indices x0 / 2 and x0 / 2 + 1; x0 + 1 and x0 + 3 on the other
-    auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) {
-        const int p0 = (y + zz) & 1;
-        const uint32_t jj = (uint32_t)((zz * L + y) * Lh + (x0 >> 1));
+    // halo rows: threads 0 .. Q - 1 stage the row below the band (LDS row 0),
+    // threads Q .. 2Q - 1 the row above it (LDS row TY + 1)
+    const bool halo = banded && tid < 2 * Q;
+    const bool hlow = tid < Q;
+    const int hy = !halo ? 0 : hlow ? (y0 == 0 ? L - 1 : y0 - 1) : (y0 + TY == L ? 0 : y0 + TY);
+    const int hx0 = !halo ? 0 : 4 * (hlow ? tid : tid - Q), hlr = hlow ? 0 : TY + 1;
+    // the four sites x .. x + 3 (x % 4 == 0) of row yy of plane zz of copy c:
+    // x and x + 2 lie on the parity of yy + zz, at half-indices x / 2 and
+    // x / 2 + 1; x + 1 and x + 3 on the other
+    auto load4r = [&](int c, int zz, int yy, int xx, typename C::R &e, typename C::R &f) {
+        const int p0 = (yy + zz) & 1;
+        const uint32_t jj = (uint32_t)((zz * L + yy) * Lh + (xx >> 1));
         C::load_raw_pair(R[c] + (int64_t)p0 * C::kPlanes * Nh, (uint32_t)Nh, jj, e);
         C::load_raw_pair(R[c] + (int64_t)(1 - p0) * C::kPlanes * Nh, (uint32_t)Nh, jj, f);
     };
+    auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) { load4r(c, zz, y, x0, e, f); };
     auto decode4 = [&](const typename C::R &e, const typename C::R &f, v3 (&s)[4]) {
         C::decode_pair(e, s[0], s[2]);
         C::decode_pair(f, s[1], s[3]);
     };
     v3 prv[2][4], cur[2][4], nxt[2][4];
-    typename C::R ne[2], nf[2];
+    typename C::R ne[2], nf[2], he[2], hf[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         typename C::R e, f;
@@ -937,11 +958,21 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
         load4(c, 0, e, f);
         decode4(e, f, cur[c]);
         load4(c, 1, ne[c], nf[c]);
+        if (BANDED && halo) load4r(c, 0, hy, hx0, he[c], hf[c]);
     }
     double P0[3], Pc[3], Ps[3], Zc[3], Zs[3];
 #pragma unroll
     for (int al = 0; al < 3; ++al) P0[al] = Pc[al] = Ps[al] = Zc[al] = Zs[al] = 0.0;
-    auto lp = [&](int b, int c, int m) { return plane + ((b * 2 + c) * 3 + m) * LL; };
+    auto lp = [&](int b, int c, int m) { return plane + ((b * 2 + c) * 3 + m) * RL; };
+    auto put4 = [&](int b, int c, int row, int xx, const v3 (&v)[4]) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const float4 q = m == 0 ? make_float4(v[0].x, v[1].x, v[2].x, v[3].x)
+                           : m == 1 ? make_float4(v[0].y, v[1].y, v[2].y, v[3].y)
+                                    : make_float4(v[0].z, v[1].z, v[2].z, v[3].z);
+            *reinterpret_cast<float4 *>(lp(b, c, m) + row * L + xx) = q;
+        }
+    };
     __syncthreads();  // the phase tables
     double cx[4], sx[4];
 #pragma unroll
@@ -956,14 +987,12 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
             decode4(ne[c], nf[c], nxt[c]);
             const int zn = z + 2 < L ? z + 2 : z + 2 - L;  // the next step's plane z + 1 (wrapping)
             load4(c, zn, ne[c], nf[c]);
-            if (active) {
-#pragma unroll
-                for (int m = 0; m < 3; ++m) {
-                    const float4 v = m == 0 ? make_float4(cur[c][0].x, cur[c][1].x, cur[c][2].x, cur[c][3].x)
-                                   : m == 1 ? make_float4(cur[c][0].y, cur[c][1].y, cur[c][2].y, cur[c][3].y)
-                                            : make_float4(cur[c][0].z, cur[c][1].z, cur[c][2].z, cur[c][3].z);
-                    *reinterpret_cast<float4 *>(lp(b, c, m) + y * L + x0) = v;
-                }
+            if (active) put4(b, c, lr, x0, cur[c]);
+            if (BANDED && halo) {  // this plane's halo row, then the next plane's load
+                v3 hv[4];
+                decode4(he[c], hf[c], hv);
+                put4(b, c, hlr, hx0, hv);
+                load4r(c, z + 1 < L ? z + 1 : 0, hy, hx0, he[c], hf[c]);
             }
         }
         __syncthreads();
@@ -973,18 +1002,18 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
             for (int c = 0; c < 2; ++c) {
                 v3 ypl[4], ymi[4], xl, xr;
                 {
-                    const float4 a0 = *reinterpret_cast<const float4 *>(lp(b, c, 0) + yp * L + x0);
-                    const float4 a1 = *reinterpret_cast<const float4 *>(lp(b, c, 1) + yp * L + x0);
-                    const float4 a2 = *reinterpret_cast<const float4 *>(lp(b, c, 2) + yp * L + x0);
+                    const float4 a0 = *reinterpret_cast<const float4 *>(lp(b, c, 0) + lrp * L + x0);
+                    const float4 a1 = *reinterpret_cast<const float4 *>(lp(b, c, 1) + lrp * L + x0);
+                    const float4 a2 = *reinterpret_cast<const float4 *>(lp(b, c, 2) + lrp * L + x0);
                     ypl[0] = v3{a0.x, a1.x, a2.x}; ypl[1] = v3{a0.y, a1.y, a2.y};
                     ypl[2] = v3{a0.z, a1.z, a2.z}; ypl[3] = v3{a0.w, a1.w, a2.w};
-                    const float4 b0 = *reinterpret_cast<const float4 *>(lp(b, c, 0) + ym * L + x0);
-                    const float4 b1 = *reinterpret_cast<const float4 *>(lp(b, c, 1) + ym * L + x0);
-                    const float4 b2 = *reinterpret_cast<const float4 *>(lp(b, c, 2) + ym * L + x0);
+                    const float4 b0 = *reinterpret_cast<const float4 *>(lp(b, c, 0) + lrm * L + x0);
+                    const float4 b1 = *reinterpret_cast<const float4 *>(lp(b, c, 1) + lrm * L + x0);
+                    const float4 b2 = *reinterpret_cast<const float4 *>(lp(b, c, 2) + lrm * L + x0);
                     ymi[0] = v3{b0.x, b1.x, b2.x}; ymi[1] = v3{b0.y, b1.y, b2.y};
                     ymi[2] = v3{b0.z, b1.z, b2.z}; ymi[3] = v3{b0.w, b1.w, b2.w};
-                    xl = v3{lp(b, c, 0)[y * L + xm], lp(b, c, 1)[y * L + xm], lp(b, c, 2)[y * L + xm]};
-                    xr = v3{lp(b, c, 0)[y * L + xp], lp(b, c, 1)[y * L + xp], lp(b, c, 2)[y * L + xp]};
+                    xl = v3{lp(b, c, 0)[lr * L + xm], lp(b, c, 1)[lr * L + xm], lp(b, c, 2)[lr * L + xm]};
+                    xr = v3{lp(b, c, 0)[lr * L + xp], lp(b, c, 1)[lr * L + xp], lp(b, c, 2)[lr * L + xp]};
                 }
                 const v3 (&w)[4] = cur[c];
                 // kappa_x(u) = s(u+1) . (s(u) x s(u-1)); x0 and x0 + 1 share
@@ -1045,12 +1074,10 @@ __global__ __launch_bounds__(kBlock) void k_chiral_stream(KmodeArgs a)
         }
     }
     __syncthreads();
-    for (int m = threadIdx.x; m < K * a.n_pb; m += blockDim.x) {
-        const int pb = m / K, mm = m - pb * K;
+    for (int m = threadIdx.x; m < K; m += blockDim.x) {
         double v = 0.0;
-        if (pb == 0)
-            for (int w = 0; w < n_waves; ++w) v += red[w][mm];
-        a.partials[(dk * a.n_pb + pb) * 84 + KGroup<2>::first + mm] = v;
+        for (int w = 0; w < n_waves; ++w) v += red[w][m];
+        a.partials[(dk * a.n_pb + band) * 84 + KGroup<2>::first + m] = v;
     }
 }
 
@@ -1061,15 +1088,19 @@ static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
     // a replica's spins within 4 GiB: 32-bit offsets from its base
     const bool b32 = 2 * (uint64_t)Codec<STORE>::kPlanes * (uint64_t)a.Nh * sizeof(typename Codec<STORE>::T) <
                      (1ull << 32);
-    // z-marches where a whole plane fits a work-group: the overlap groups in one
-    // pass, the chiral group in another
-    const bool march = a.L % 4 == 0 && a.L <= 32;
-    if (march) {
-        const unsigned threads = (unsigned)((a.L * (a.L / 4) + 63) / 64 * 64);
-        const size_t lds = (size_t)2 * 2 * 3 * a.L * a.L * sizeof(float);
-        const dim3 cols((unsigned)((int64_t)a.D * a.T));
+    // z-marches over bands of rows where kmode_rows(L) > 0: the overlap groups
+    // in one pass, the chiral group in another
+    const int rows = kmode_rows(a.L);
+    if (rows > 0) {
+        if (a.n_pb != a.L / rows) return hipErrorInvalidValue;  // one partial per band
+        const unsigned threads = (unsigned)((rows * (a.L / 4) + 63) / 64 * 64);
+        const size_t lds = (size_t)2 * 2 * 3 * (rows + 2) * a.L * sizeof(float);
+        const dim3 cols((unsigned)((int64_t)a.D * a.T * (a.L / rows)));
         hipLaunchKernelGGL((k_qk_stream<STORE>), cols, dim3(threads), 0, s, a);
-        hipLaunchKernelGGL((k_chiral_stream<STORE>), cols, dim3(threads), lds, s, a);
+        if (rows < a.L)
+            hipLaunchKernelGGL((k_chiral_stream<STORE, true>), cols, dim3(threads), lds, s, a);
+        else
+            hipLaunchKernelGGL((k_chiral_stream<STORE, false>), cols, dim3(threads), lds, s, a);
     } else if (b32) {
         hipLaunchKernelGGL((k_kmodes<STORE, 0, true>), grid, block, 0, s, a);
         hipLaunchKernelGGL((k_kmodes<STORE, 1, true>), grid, block, 0, s, a);

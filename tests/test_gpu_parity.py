@@ -260,13 +260,15 @@ def _oracle_on_gpu_state(oracle_lib, lat, k, g, seed, storage):
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "qangle"])
 def test_kmodes_against_oracle(hsg, oracle_lib, storage):
     """q^{mu nu}(k) and the chiral overlaps for k = 0 and the three smallest wave
-    vectors, five lattice sizes in one handle after a few sweeps with
+    vectors, eight lattice sizes in one handle after a few sweeps with
     tempering: the oracle evaluates the same configurations. L = 6 (odd L/2)
-    takes the gathering kernel for the chiral overlaps; L = 4 (the x neighbours
-    are the thread's own sites), 8, 12 and 20 (a partly idle wave) the z-march."""
+    takes the gathering passes; L = 4 (the x neighbours are the thread's own
+    sites), 8, 12 and 20 (a partly idle wave) the z-marches over whole planes;
+    L = 36 (two bands of 18 rows, idle lanes), 48 (three of 16) and 64 (four of
+    16) the z-marches over bands of rows with halo rows."""
     rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 47))
     groups, uid = [], 0
-    for L, D in ((6, 2), (8, 1), (12, 1), (4, 1), (20, 1)):
+    for L, D in ((6, 2), (8, 1), (12, 1), (4, 1), (20, 1), (36, 1), (48, 1), (64, 1)):
         groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.5, 3),
                                         sample_uid_base=uid))
         uid += D
