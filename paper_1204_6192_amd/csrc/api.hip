@@ -844,7 +844,7 @@ hsg_status run_energy(hsg_lattice *h, hipStream_t s)
         a.L = g.L;
         a.Lh = g.L / 2;
         a.slots_per_sample = g.O * g.T;
-        a.n_pb = g.n_pb_site;
+        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_pb_site);
         hipError_t e = hsg::launch_energy(a, h->storage, s);
         if (e == hipSuccess)
             e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
@@ -1382,7 +1382,7 @@ hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream)
         a.L = g.L;
         a.Lh = g.L / 2;
         a.slots_per_sample = g.O * g.T;
-        a.n_pb = g.n_pb_site;
+        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_pb_site);
         hipError_t e = hsg::launch_energy(a, h->storage, s);
         double *E = reinterpret_cast<double *>(h->state + g.o_E);
         if (e == hipSuccess) e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, E, s);
@@ -1418,7 +1418,7 @@ hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t s
         a.L = g.L;
         a.Lh = g.L / 2;
         a.slots_per_sample = g.O * g.T;
-        a.n_pb = g.n_pb_site;
+        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_pb_site);
         e = hsg::launch_energy(a, h->storage, s);
         double *E = reinterpret_cast<double *>(h->state + g.o_E);
         if (e == hipSuccess) e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, E, s);

@@ -187,6 +187,9 @@ struct EnergyArgs {
     int32_t L, Lh, slots_per_sample, n_pb;
 };
 hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s);
+// The partials per replica that launch_energy writes (n_pb): one per band of
+// the z-march where kmode_rows(L) > 0, else one per 256 parity-0 sites.
+int64_t energy_partials(int L, int64_t n_pb_site);
 
 // Overlap of copies 0 and 1 at every rung: partials [d][k][n_pb][9] -> q [d][k][10];
 // work-group pb covers the half-indices [pb * chunk, (pb + 1) * chunk).

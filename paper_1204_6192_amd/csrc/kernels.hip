@@ -454,8 +454,163 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
     if (threadIdx.x == 0) a.partials[rep * a.n_pb + pb] = tot;
 }
 
+// The same energies as a z-march where kmode_rows(L) > 0: one work-group per
+// (replica, band of TY = kmode_rows(L) rows), the thread of row y and quarter q
+// holding the sites x = 4q .. 4q + 3 of plane z as z advances (planes z and
+// z + 1 in registers, the next one loaded a step ahead), plane z staged in LDS
+// with the row above the band. Every bond is counted once, as the +x, +y and +z
+// bonds of each site: s(i) . s(i + a) in float64 from float32 components (exact
+// products), times its coupling, as in k_energy; every spin is read once
+// instead of seven times. The sums run in another order than k_energy's, so
+// the two agree to float64 rounding. A work-group's sum goes to the partial of
+// its band.
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_energy_stream(EnergyArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    // [2 buffers][3 components][TY + 1 rows][L]: rows 0 .. TY - 1 the band,
+    // row TY the row above it
+    extern __shared__ __align__(16) float plane[];
+    __shared__ double red[4];
+    const int L = a.L, Lh = L >> 1, Q = L >> 2;
+    const int TY = kmode_rows(L), n_bands = L / TY, RL = (TY + 1) * L;
+    const int64_t rep = blockIdx.x / n_bands;
+    const int band = (int)(blockIdx.x - rep * n_bands), y0 = band * TY;
+    const int64_t Nh = a.Nh;
+    const int64_t d = rep / a.slots_per_sample;
+    const T *base = (const T *)a.spins + rep * 2 * C::kPlanes * Nh;
+    const float *J6 = a.J6 + d * 2 * 6 * Nh;
+    const float *H = a.Hp != nullptr ? a.Hp + d * 2 * 3 * Nh : nullptr;
+    const int tid = threadIdx.x;
+    const bool active = tid < TY * Q;
+    const int ly = active ? tid / Q : 0, x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    const int y = y0 + ly;
+    const int xp = x0 + 4 == L ? 0 : x0 + 4;
+    // threads 0 .. Q - 1 stage the row above the band (LDS row TY)
+    const bool halo = tid < Q;
+    const int hy = y0 + TY == L ? 0 : y0 + TY, hx0 = halo ? 4 * tid : 0;
+    // the four sites x .. x + 3 of row yy of plane zz: x and x + 2 on the parity
+    // of yy + zz (half-indices x / 2, x / 2 + 1), x + 1 and x + 3 on the other
+    auto load4 = [&](int zz, int yy, int xx, typename C::R &e, typename C::R &f) {
+        const int p0 = (yy + zz) & 1;
+        const uint32_t jj = (uint32_t)((zz * L + yy) * Lh + (xx >> 1));
+        C::load_raw_pair(base + (int64_t)p0 * C::kPlanes * Nh, (uint32_t)Nh, jj, e);
+        C::load_raw_pair(base + (int64_t)(1 - p0) * C::kPlanes * Nh, (uint32_t)Nh, jj, f);
+    };
+    auto decode4 = [&](const typename C::R &e, const typename C::R &f, v3 (&s)[4]) {
+        C::decode_pair(e, s[0], s[2]);
+        C::decode_pair(f, s[1], s[3]);
+    };
+    auto lp = [&](int b, int m) { return plane + (b * 3 + m) * RL; };
+    auto put4 = [&](int b, int row, int xx, const v3 (&v)[4]) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const float4 q = m == 0 ? make_float4(v[0].x, v[1].x, v[2].x, v[3].x)
+                           : m == 1 ? make_float4(v[0].y, v[1].y, v[2].y, v[3].y)
+                                    : make_float4(v[0].z, v[1].z, v[2].z, v[3].z);
+            *reinterpret_cast<float4 *>(lp(b, m) + row * L + xx) = q;
+        }
+    };
+    auto bond = [](v3 s, v3 t) {
+        return (double)s.x * t.x + (double)s.y * t.y + (double)s.z * t.z;
+    };
+    v3 cur[4], nxt[4];
+    typename C::R ne, nf, he, hf;
+    {
+        typename C::R e, f;
+        load4(0, y, x0, e, f);
+        decode4(e, f, cur);
+        load4(1, y, x0, ne, nf);
+        if (halo) load4(0, hy, hx0, he, hf);
+    }
+    double e = 0.0;
+    for (int z = 0; z < L; ++z) {
+        const int b = z & 1;
+        decode4(ne, nf, nxt);
+        const int zn = z + 2 < L ? z + 2 : z + 2 - L;
+        load4(zn, y, x0, ne, nf);
+        if (active) put4(b, ly, x0, cur);
+        if (halo) {
+            v3 hv[4];
+            decode4(he, hf, hv);
+            put4(b, TY, hx0, hv);
+            load4(z + 1 < L ? z + 1 : 0, hy, hx0, he, hf);
+        }
+        // couplings (+x, +y, +z) and field of my sites: x0, x0 + 2 on parity
+        // p0 at half-indices jj, jj + 1; x0 + 1, x0 + 3 on the other parity
+        const int p0 = (y + z) & 1;
+        const int64_t jj = (int64_t)(z * L + y) * Lh + (x0 >> 1);
+        float2 jc[3][2];
+#pragma unroll
+        for (int a3 = 0; a3 < 3; ++a3) {
+            jc[a3][0] = *reinterpret_cast<const float2 *>(J6 + ((int64_t)p0 * 6 + 2 * a3) * Nh + jj);
+            jc[a3][1] = *reinterpret_cast<const float2 *>(J6 + ((int64_t)(1 - p0) * 6 + 2 * a3) * Nh + jj);
+        }
+        __syncthreads();
+        if (active) {
+            const int lyp = ly + 1;  // the row above: in the band, or the staged row TY
+            const float4 a0 = *reinterpret_cast<const float4 *>(lp(b, 0) + lyp * L + x0);
+            const float4 a1 = *reinterpret_cast<const float4 *>(lp(b, 1) + lyp * L + x0);
+            const float4 a2 = *reinterpret_cast<const float4 *>(lp(b, 2) + lyp * L + x0);
+            const v3 yn[4] = {v3{a0.x, a1.x, a2.x}, v3{a0.y, a1.y, a2.y}, v3{a0.z, a1.z, a2.z},
+                              v3{a0.w, a1.w, a2.w}};
+            const v3 xr{lp(b, 0)[ly * L + xp], lp(b, 1)[ly * L + xp], lp(b, 2)[ly * L + xp]};
+            // coupling of site u along axis a3: parity plane u & 1, element u >> 1
+            auto J = [&](int a3, int u) { return (u >> 1) ? jc[a3][u & 1].y : jc[a3][u & 1].x; };
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const v3 xn = u == 3 ? xr : cur[u == 3 ? 0 : u + 1];
+                e -= (double)J(0, u) * bond(cur[u], xn);
+                e -= (double)J(1, u) * bond(cur[u], yn[u]);
+                e -= (double)J(2, u) * bond(cur[u], nxt[u]);
+            }
+            if (H != nullptr) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t hj = (int64_t)((u & 1) ? 1 - p0 : p0) * 3 * Nh + jj + (u >> 1);
+                    e -= (double)H[hj] * cur[u].x + (double)H[Nh + hj] * cur[u].y + (double)H[2 * Nh + hj] * cur[u].z;
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cur[u] = nxt[u];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = (int)(blockDim.x >> 6);
+    const double v = wave_sum(e);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < n_waves; ++w) t += red[w];
+        a.partials[rep * a.n_pb + band] = t;
+    }
+}
+
+int64_t energy_partials(int L, int64_t n_pb_site)
+{
+    const int rows = kmode_rows(L);
+    return rows > 0 ? L / rows : n_pb_site;
+}
+
 hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s)
 {
+    const int rows = kmode_rows(a.L);
+    if (rows > 0) {
+        if (a.n_pb != a.L / rows) return hipErrorInvalidValue;  // one partial per band
+        const int64_t blocks = a.n_rep * (a.L / rows);
+        if (blocks == 0) return hipSuccess;
+        const unsigned threads = (unsigned)((rows * (a.L / 4) + 63) / 64 * 64);
+        const size_t lds = (size_t)2 * 3 * (rows + 1) * a.L * sizeof(float);
+        switch (storage) {
+        case 0: hipLaunchKernelGGL(k_energy_stream<0>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+        case 1: hipLaunchKernelGGL(k_energy_stream<1>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+        case 2: hipLaunchKernelGGL(k_energy_stream<2>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+        case 3: hipLaunchKernelGGL(k_energy_stream<3>, dim3((unsigned)blocks), dim3(threads), lds, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const int64_t blocks = a.n_rep * a.n_pb;
     if (blocks == 0) return hipSuccess;
     switch (storage) {

@@ -289,6 +289,33 @@ def test_kmodes_against_oracle(hsg, oracle_lib, storage):
         off += n
 
 
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16", "qangle"])
+def test_energy_against_oracle_all_lattice_forms(hsg, oracle_lib, storage):
+    """The full energy recomputation (hsg_measure_energy) against the oracle on
+    the GPU's configuration after a few sweeps with tempering: L = 6 on the
+    gathering kernel; L = 4, 8 and 20 on the z-march over whole planes; L = 36,
+    48 and 64 on bands of rows with the row above staged; with and without a
+    random field."""
+    rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 48))
+    groups, uid = [], 0
+    for L, D, field in ((6, 2, None), (4, 1, ("gaussian", 0.2)), (8, 1, None), (20, 1, ("gaussian", 0.1)),
+                        (36, 1, None), (48, 1, ("gaussian", 0.1)), (64, 1, None)):
+        groups.append(inputs.make_group(rng, L, D, 2, inputs.geometric_ladder(0.1, 0.5, 3), field=field,
+                                        sample_uid_base=uid))
+        uid += D
+    seed = inputs.PHILOX_KEY_BASE + 48
+    lat = _lat(hsg, groups, seed, storage=storage)
+    lat.sweep(3)
+    Em = lat.measure_energy()
+    for k, g in enumerate(groups):
+        o = _oracle_on_gpu_state(oracle_lib, lat, k, g, seed, storage)
+        want = o.compute_energies()
+        got = _energies(Em, lat, k)
+        err = np.abs(got - want).max()
+        print(f"L={g.L}: max |dE| {err:.2e}, max |E| {np.abs(want).max():.2e}", flush=True)
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-10), g.L
+
+
 def test_kmodes_full_size_sampled(hsg, oracle_lib):
     """The batched workload at full size (64 samples, 32 rungs) after one sweep:
     every output of two samples against the oracle on the GPU's configurations."""
