@@ -1398,7 +1398,7 @@ hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t s
 {
     if (h == nullptr || d_E == nullptr) return fail(HSG_E_INVALID, "handle and d_E are required");
     for (const Group &g : h->lay.g) {
-        const uint64_t need = (uint64_t)g.n_rep * g.n_pb_site * sizeof(double);
+        const uint64_t need = (uint64_t)g.n_rep * hsg::energy_partials(g.L, g.n_pb_site) * sizeof(double);
         if (need > kStaticScratchBytes)
             return fail(HSG_E_SIZE, "group of L = %d needs %llu bytes of energy partials, the fixed scratch holds %zu",
                         g.L, (unsigned long long)need, kStaticScratchBytes);
