@@ -291,11 +291,10 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > n_pb_stream ? g.n_pb_sweep : n_pb_stream) * 8;
         const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
-        // k modes: the overlap's blocks, or one partial per band of the z-marches
-        const int k_rows = hsg::kmode_rows(g.L);
-        const int64_t k_pb = k_rows > 0 ? g.L / k_rows : g.q_pb;
+        // k modes and copy pairs: the overlap's blocks, or one partial per band of the z-marches
+        const int64_t k_pb = hsg::march_partials(g.L, g.q_pb);
         const uint64_t k_full = (uint64_t)g.D * g.T * k_pb * 84 * 8;
-        const uint64_t p_full = (uint64_t)g.D * g.T * g.q_pb * 7 * (g.O * (g.O - 1) / 2) * 8;  // copy pairs
+        const uint64_t p_full = (uint64_t)g.D * g.T * k_pb * 7 * (g.O * (g.O - 1) / 2) * 8;
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
         // the per-sweep series stages the overlap [D][T][10] after its partials
         g.o_scr_q = g.o_scr + align_up(q_full);
@@ -1485,8 +1484,7 @@ hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        const int rows = hsg::kmode_rows(g.L);
-        a.n_pb = rows > 0 ? g.L / rows : g.q_pb;
+        a.n_pb = (int32_t)hsg::march_partials(g.L, g.q_pb);
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_kmodes(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_kmodes");
@@ -1514,7 +1512,7 @@ hsg_status hsg_measure_pair_overlaps(hsg_lattice *h, double *d_q, hsg_stream_t s
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = g.q_pb;
+        a.n_pb = (int32_t)hsg::march_partials(g.L, g.q_pb);
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_pair_overlaps(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_pair_overlaps");
@@ -1543,7 +1541,7 @@ hsg_status hsg_measure_chi(hsg_lattice *h, double *d_chi, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = g.q_pb;
+        a.n_pb = (int32_t)hsg::march_partials(g.L, g.q_pb);
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_pair_overlaps(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_chi");

@@ -262,6 +262,10 @@ struct SeriesArgs {
 };
 hipError_t launch_series(const SeriesArgs &a, hipStream_t s);
 hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s);
+// The partials per (sample, rung) that launch_kmodes and launch_pair_overlaps
+// expect (n_pb): one per band of the z-marches where kmode_rows(L) > 0, else
+// the overlap's work-groups (q_pb).
+int64_t march_partials(int L, int64_t q_pb);
 
 hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
                                      int32_t T, hipStream_t s);

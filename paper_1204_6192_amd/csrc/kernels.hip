@@ -1396,19 +1396,146 @@ __global__ __launch_bounds__(256) void k_pair_overlaps_finish(PairOvArgs a)
     out[4] = N2 * (m02 * r13 - r02 * m13);
 }
 
+// The copy-pair sums as a z-march where kmode_rows(L) > 0: one work-group per
+// (sample, rung, band of kmode_rows(L) rows) and copy pair (grid column y),
+// the thread of row y and quarter q holding the sites x = 4q .. 4q + 3 of
+// plane z as z advances, the next plane's loads issued a step ahead. Per step
+// the thread forms the local overlaps s(a) . s(b) of its four sites in float64
+// and adds them with weights 1, cos kx and sin kx, the first also with cos kz
+// and sin kz; the k_y terms are cos ky and sin ky times the unweighted sum at
+// the end (x and y stay fixed per thread). Every spin is read once. The sums
+// run in another order than k_pair_overlaps', so the two agree to float64
+// rounding. A work-group's sums go to the partial of its band.
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_pair_overlaps_stream(PairOvArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    __shared__ double red[4][7];
+    __shared__ double cph[224], sph[224];
+    const int L = a.L, Lh = L >> 1, Q = L >> 2;
+    const int TY = kmode_rows(L), n_bands = L / TY;
+    for (int r = threadIdx.x; r < L; r += blockDim.x) {
+        double sv, cv;
+        sincospi(2.0 * (double)r / (double)L, &sv, &cv);
+        cph[r] = cv;
+        sph[r] = sv;
+    }
+    const int64_t dk = blockIdx.x / n_bands;  // d * T + k
+    const int band = (int)(blockIdx.x - dk * n_bands);
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int O = a.O, P = O * (O - 1) / 2, pair = (int)blockIdx.y;
+    int ca = 0, cb = 1;  // the copies of this pair, in the order (0, 1), (0, 2), ..., (1, 2), ...
+    for (int i = 0, q = 0; i < O; ++i)
+        for (int j = i + 1; j < O; ++j, ++q)
+            if (q == pair) {
+                ca = i;
+                cb = j;
+            }
+    const int64_t Nh = a.Nh;
+    const int32_t sa = a.slot_at_temp[((int64_t)d * O + ca) * a.T + k];
+    const int32_t sb = a.slot_at_temp[((int64_t)d * O + cb) * a.T + k];
+    const T *R[2] = {(const T *)a.spins + (((int64_t)d * O + ca) * a.T + sa) * 2 * C::kPlanes * Nh,
+                     (const T *)a.spins + (((int64_t)d * O + cb) * a.T + sb) * 2 * C::kPlanes * Nh};
+    const int tid = threadIdx.x;
+    const bool active = tid < TY * Q;
+    const int y = band * TY + (active ? tid / Q : 0), x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    // the four sites of plane zz of copy c: x0 and x0 + 2 on the parity of
+    // y + zz (half-indices x0 / 2, x0 / 2 + 1), x0 + 1 and x0 + 3 on the other
+    auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) {
+        const int p0 = (y + zz) & 1;
+        const uint32_t jj = (uint32_t)((zz * L + y) * Lh + (x0 >> 1));
+        C::load_raw_pair(R[c] + (int64_t)p0 * C::kPlanes * Nh, (uint32_t)Nh, jj, e);
+        C::load_raw_pair(R[c] + (int64_t)(1 - p0) * C::kPlanes * Nh, (uint32_t)Nh, jj, f);
+    };
+    typename C::R ne[2], nf[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) load4(c, 0, ne[c], nf[c]);
+    double A0 = 0.0, Ac = 0.0, As = 0.0, Zc = 0.0, Zs = 0.0;
+    __syncthreads();  // the phase tables
+    double cx[4], sx[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        cx[u] = cph[x0 + u];
+        sx[u] = sph[x0 + u];
+    }
+    for (int z = 0; z < L; ++z) {
+        v3 s[2][4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            C::decode_pair(ne[c], s[c][0], s[c][2]);
+            C::decode_pair(nf[c], s[c][1], s[c][3]);
+            if (z + 1 < L) load4(c, z + 1, ne[c], nf[c]);
+        }
+        if (active) {
+            double t0 = 0.0, tc = 0.0, ts = 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double f = (double)s[0][u].x * s[1][u].x + (double)s[0][u].y * s[1][u].y +
+                                 (double)s[0][u].z * s[1][u].z;
+                t0 += f;
+                tc = fma(f, cx[u], tc);
+                ts = fma(f, sx[u], ts);
+            }
+            A0 += t0;
+            Ac += tc;
+            As += ts;
+            Zc = fma(t0, cph[z], Zc);
+            Zs = fma(t0, sph[z], Zs);
+        }
+    }
+    const double cy = cph[y], sy = sph[y];
+    // the layout of k_pair_overlaps: k = 0, then (cos, sin) of k_x, k_y, k_z
+    const double v[7] = {A0, Ac, As, cy * A0, sy * A0, Zc, Zs};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = (int)(blockDim.x >> 6);
+#pragma unroll
+    for (int m = 0; m < 7; ++m) {
+        const double w = wave_sum(v[m]);
+        if (lane == 0) red[wave][m] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        double t = 0.0;
+        for (int w = 0; w < n_waves; ++w) t += red[w][threadIdx.x];
+        a.partials[(dk * a.n_pb + band) * (int64_t)(7 * P) + 7 * pair + threadIdx.x] = t;
+    }
+}
+
+int64_t march_partials(int L, int64_t q_pb)
+{
+    const int rows = kmode_rows(L);
+    return rows > 0 ? L / rows : q_pb;
+}
+
 hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s)
 {
-    const int64_t blocks = (int64_t)a.D * a.T * a.n_pb;
     const int P = a.O * (a.O - 1) / 2;
-    if (blocks == 0 || P == 0) return hipSuccess;
-    if (a.L > 1024 || blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)blocks, (unsigned)((P + 3) / 4)), block(kBlock);
-    switch (storage) {
-    case 0: hipLaunchKernelGGL(k_pair_overlaps<0>, grid, block, 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_pair_overlaps<1>, grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_pair_overlaps<2>, grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_pair_overlaps<3>, grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
+    const int rows = kmode_rows(a.L);
+    if (rows > 0) {
+        if (a.n_pb != a.L / rows) return hipErrorInvalidValue;  // one partial per band
+        const int64_t blocks = (int64_t)a.D * a.T * (a.L / rows);
+        if (blocks == 0 || P == 0) return hipSuccess;
+        if (blocks > 0x7FFFFFFFll || P > 65535) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)blocks, (unsigned)P), block((unsigned)((rows * (a.L / 4) + 63) / 64 * 64));
+        switch (storage) {
+        case 0: hipLaunchKernelGGL(k_pair_overlaps_stream<0>, grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_pair_overlaps_stream<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_pair_overlaps_stream<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_pair_overlaps_stream<3>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        const int64_t blocks = (int64_t)a.D * a.T * a.n_pb;
+        if (blocks == 0 || P == 0) return hipSuccess;
+        if (a.L > 1024 || blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)blocks, (unsigned)((P + 3) / 4)), block(kBlock);
+        switch (storage) {
+        case 0: hipLaunchKernelGGL(k_pair_overlaps<0>, grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_pair_overlaps<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_pair_overlaps<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_pair_overlaps<3>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -340,13 +340,14 @@ def test_kmodes_full_size_sampled(hsg, oracle_lib):
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
 def test_pair_overlaps_four_copies_against_oracle(hsg, oracle_lib, storage):
-    """Four copies per sample (the four-replica estimators), three lattice sizes in
+    """Four copies per sample (the four-replica estimators), six lattice sizes in
     one handle, a random field, after sweeps with tempering on every copy's
     ladder: A_ab(k) of all six pairs against the oracle on the same
-    configurations."""
+    configurations. L = 6 takes the gathering kernel; L = 8, 12 and 20 the
+    z-march over whole planes; L = 36 and 48 the z-march over bands of rows."""
     rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 48))
     groups, uid = [], 0
-    for L, D in ((6, 1), (8, 2), (12, 1)):
+    for L, D in ((6, 1), (8, 2), (12, 1), (20, 1), (36, 1), (48, 1)):
         groups.append(inputs.make_group(rng, L, D, 4, inputs.geometric_ladder(0.1, 0.5, 3),
                                         field=("gaussian", 0.2), sample_uid_base=uid))
         uid += D
