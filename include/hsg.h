@@ -171,11 +171,12 @@ hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream);
  * call on a device shares that array: calls that overlap on one device (other
  * streams, other handles, other threads) race and must be ordered by the
  * caller. The partials need, per group, n_replicas x 8 bytes times the
- * work-groups per replica: for L % 4 == 0 up to L = 224 the bands of rows of
- * the z-march (1 up to L = 32, 3 at L = 48, 4 at L = 64, 16 at L = 128),
- * else ceil(L^3 / 512);
- * HSG_E_SIZE when the largest exceeds 16 MiB, HSG_E_INVALID for a NULL handle
- * or d_E. */
+ * work-groups per replica: for L % 4 == 0 up to L = 224 the bands of rows
+ * times the z-slabs of the z-march (one band up to L = 32, 3 at L = 48, 4 at
+ * L = 64, 16 at L = 128; slabs until the group makes 2048 work-groups: 1 for
+ * 4096 replicas of L = 32, 2 for 64 replicas of L = 128), else
+ * ceil(L^3 / 512); HSG_E_SIZE when the largest exceeds 16 MiB, HSG_E_INVALID
+ * for a NULL handle or d_E. */
 hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t stream);
 
 /* Copy the energies computed at the end of the last sweep into d_E [n_replicas]. */

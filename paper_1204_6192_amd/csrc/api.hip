@@ -289,12 +289,14 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         g.o_scr = sc;
         const int64_t n_pb_stream = g.stream_ok ? (int64_t)g.s_max_pb : 1;
         const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > n_pb_stream ? g.n_pb_sweep : n_pb_stream) * 8;
-        const uint64_t e_full = (uint64_t)g.n_rep * g.n_pb_site * 8;
+        const int64_t e_pb = hsg::energy_partials(g.L, g.n_rep, g.n_pb_site);
+        const uint64_t e_full = (uint64_t)g.n_rep * (e_pb > g.n_pb_site ? e_pb : g.n_pb_site) * 8;
         const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
         // k modes and copy pairs: the overlap's blocks, or one partial per band of the z-marches
-        const int64_t k_pb = hsg::march_partials(g.L, g.q_pb);
+        const int64_t k_pb = hsg::kmode_partials(g.L, g.q_pb);
+        const int64_t p_pb = hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb);
         const uint64_t k_full = (uint64_t)g.D * g.T * k_pb * 84 * 8;
-        const uint64_t p_full = (uint64_t)g.D * g.T * k_pb * 7 * (g.O * (g.O - 1) / 2) * 8;
+        const uint64_t p_full = (uint64_t)g.D * g.T * p_pb * 7 * (g.O * (g.O - 1) / 2) * 8;
         uint64_t need = e_sweep > e_full ? e_sweep : e_full;
         // the per-sweep series stages the overlap [D][T][10] after its partials
         g.o_scr_q = g.o_scr + align_up(q_full);
@@ -843,7 +845,7 @@ hsg_status run_energy(hsg_lattice *h, hipStream_t s)
         a.L = g.L;
         a.Lh = g.L / 2;
         a.slots_per_sample = g.O * g.T;
-        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_pb_site);
+        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_rep, g.n_pb_site);
         hipError_t e = hsg::launch_energy(a, h->storage, s);
         if (e == hipSuccess)
             e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, reinterpret_cast<double *>(h->state + g.o_E), s);
@@ -1381,7 +1383,7 @@ hsg_status hsg_measure_energy(hsg_lattice *h, double *d_E, hsg_stream_t stream)
         a.L = g.L;
         a.Lh = g.L / 2;
         a.slots_per_sample = g.O * g.T;
-        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_pb_site);
+        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_rep, g.n_pb_site);
         hipError_t e = hsg::launch_energy(a, h->storage, s);
         double *E = reinterpret_cast<double *>(h->state + g.o_E);
         if (e == hipSuccess) e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, E, s);
@@ -1397,7 +1399,7 @@ hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t s
 {
     if (h == nullptr || d_E == nullptr) return fail(HSG_E_INVALID, "handle and d_E are required");
     for (const Group &g : h->lay.g) {
-        const uint64_t need = (uint64_t)g.n_rep * hsg::energy_partials(g.L, g.n_pb_site) * sizeof(double);
+        const uint64_t need = (uint64_t)g.n_rep * hsg::energy_partials(g.L, g.n_rep, g.n_pb_site) * sizeof(double);
         if (need > kStaticScratchBytes)
             return fail(HSG_E_SIZE, "group of L = %d needs %llu bytes of energy partials, the fixed scratch holds %zu",
                         g.L, (unsigned long long)need, kStaticScratchBytes);
@@ -1417,7 +1419,7 @@ hsg_status hsg_measure_energy_static(hsg_lattice *h, double *d_E, hsg_stream_t s
         a.L = g.L;
         a.Lh = g.L / 2;
         a.slots_per_sample = g.O * g.T;
-        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_pb_site);
+        a.n_pb = (int32_t)hsg::energy_partials(g.L, g.n_rep, g.n_pb_site);
         e = hsg::launch_energy(a, h->storage, s);
         double *E = reinterpret_cast<double *>(h->state + g.o_E);
         if (e == hipSuccess) e = hsg::launch_reduce_partials(a.partials, a.n_pb, g.n_rep, E, s);
@@ -1484,7 +1486,7 @@ hsg_status hsg_measure_kmodes(hsg_lattice *h, double *d_q, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = (int32_t)hsg::march_partials(g.L, g.q_pb);
+        a.n_pb = (int32_t)hsg::kmode_partials(g.L, g.q_pb);
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_kmodes(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_kmodes");
@@ -1512,7 +1514,7 @@ hsg_status hsg_measure_pair_overlaps(hsg_lattice *h, double *d_q, hsg_stream_t s
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = (int32_t)hsg::march_partials(g.L, g.q_pb);
+        a.n_pb = (int32_t)hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb);
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_pair_overlaps(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_pair_overlaps");
@@ -1541,7 +1543,7 @@ hsg_status hsg_measure_chi(hsg_lattice *h, double *d_chi, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = (int32_t)hsg::march_partials(g.L, g.q_pb);
+        a.n_pb = (int32_t)hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb);
         a.chunk = 2 * g.q_chunk;
         const hipError_t e = hsg::launch_pair_overlaps(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_chi");

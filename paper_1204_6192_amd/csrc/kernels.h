@@ -187,9 +187,10 @@ struct EnergyArgs {
     int32_t L, Lh, slots_per_sample, n_pb;
 };
 hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s);
-// The partials per replica that launch_energy writes (n_pb): one per band of
-// the z-march where kmode_rows(L) > 0, else one per 256 parity-0 sites.
-int64_t energy_partials(int L, int64_t n_pb_site);
+// The partials per replica that launch_energy writes (n_pb): one per band and
+// z-slab of the z-march where kmode_rows(L) > 0 (march_slabs(L, n_rep)), else
+// one per 256 parity-0 sites.
+int64_t energy_partials(int L, int64_t n_rep, int64_t n_pb_site);
 
 // Overlap of copies 0 and 1 at every rung: partials [d][k][n_pb][9] -> q [d][k][10];
 // work-group pb covers the half-indices [pb * chunk, (pb + 1) * chunk).
@@ -206,7 +207,7 @@ hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s);
 // Wave-vector dependent and chiral overlaps: partials [D T][n_pb][84], q [D T][84].
 // Gathering passes: block pb covers canonical sites [pb chunk, (pb + 1) chunk).
 // z-marches (kmode_rows(L) > 0): partial pb is band pb of kmode_rows(L) rows,
-// and n_pb must be L / kmode_rows(L).
+// and n_pb must be kmode_partials(L, .).
 struct KmodeArgs {
     const void *spins;
     const int32_t *slot_at_temp;
@@ -229,6 +230,20 @@ __host__ __device__ inline int kmode_rows(int L)
     if (ty > L) ty = L;
     while (L % ty != 0) --ty;
     return (int64_t)2 * 2 * 3 * (ty + 2) * L * 4 <= 65536 ? ty : 0;
+}
+
+// z-slabs per band of the z-marches: n_items work items ((sample, rung) pairs,
+// or replicas) with L / kmode_rows(L) bands each are split along z into the
+// fewest slabs (a power of two dividing L, at least 4 planes each) that make
+// 2048 work-groups, so that lattices with few items still fill the device.
+__host__ __device__ inline int march_slabs(int L, int64_t n_items)
+{
+    const int rows = kmode_rows(L);
+    if (rows <= 0) return 1;
+    const int64_t blocks = n_items * (L / rows);
+    int s = 1;
+    while (blocks * s < 2048 && L % (2 * s) == 0 && L / (2 * s) >= 4) s *= 2;
+    return s;
 }
 
 // Copy-pair local-overlap sums: partials [D T][n_pb][7 P], q [D T][P][7],
@@ -262,10 +277,12 @@ struct SeriesArgs {
 };
 hipError_t launch_series(const SeriesArgs &a, hipStream_t s);
 hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s);
-// The partials per (sample, rung) that launch_kmodes and launch_pair_overlaps
-// expect (n_pb): one per band of the z-marches where kmode_rows(L) > 0, else
-// the overlap's work-groups (q_pb).
-int64_t march_partials(int L, int64_t q_pb);
+// The partials per (sample, rung) that launch_pair_overlaps expects (n_pb): one
+// per band and z-slab of the z-march where kmode_rows(L) > 0
+// (march_slabs(L, D T)), else the overlap's work-groups (q_pb).
+int64_t march_partials(int L, int64_t n_items, int64_t q_pb);
+// The same for launch_kmodes, whose marches take whole z: one per band.
+int64_t kmode_partials(int L, int64_t q_pb);
 
 hipError_t launch_fill_identity_maps(int32_t *slot_at_temp, int32_t *temp_of_slot, int64_t n_lad,
                                      int32_t T, hipStream_t s);

@@ -455,7 +455,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
 }
 
 // The same energies as a z-march where kmode_rows(L) > 0: one work-group per
-// (replica, band of TY = kmode_rows(L) rows), the thread of row y and quarter q
+// (replica, band of TY = kmode_rows(L) rows, z-slab of L / march_slabs(L, n_rep)
+// planes), the thread of row y and quarter q
 // holding the sites x = 4q .. 4q + 3 of plane z as z advances (planes z and
 // z + 1 in registers, the next one loaded a step ahead), plane z staged in LDS
 // with the row above the band. Every bond is counted once, as the +x, +y and +z
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_energy(EnergyArgs a)
 // products), times its coupling, as in k_energy; every spin is read once
 // instead of seven times. The sums run in another order than k_energy's, so
 // the two agree to float64 rounding. A work-group's sum goes to the partial of
-// its band.
+// its band and slab.
 template <int STORE>
 __global__ __launch_bounds__(kBlock) void k_energy_stream(EnergyArgs a)
 {
@@ -475,8 +476,10 @@ __global__ __launch_bounds__(kBlock) void k_energy_stream(EnergyArgs a)
     __shared__ double red[4];
     const int L = a.L, Lh = L >> 1, Q = L >> 2;
     const int TY = kmode_rows(L), n_bands = L / TY, RL = (TY + 1) * L;
-    const int64_t rep = blockIdx.x / n_bands;
-    const int band = (int)(blockIdx.x - rep * n_bands), y0 = band * TY;
+    const int S = march_slabs(L, a.n_rep), Z = L / S;
+    const int64_t rep = blockIdx.x / (n_bands * S);
+    const int pb = (int)(blockIdx.x - rep * n_bands * S);  // band * S + slab
+    const int band = pb / S, y0 = band * TY, z0 = (pb - band * S) * Z;
     const int64_t Nh = a.Nh;
     const int64_t d = rep / a.slots_per_sample;
     const T *base = (const T *)a.spins + rep * 2 * C::kPlanes * Nh;
@@ -519,13 +522,13 @@ __global__ __launch_bounds__(kBlock) void k_energy_stream(EnergyArgs a)
     typename C::R ne, nf, he, hf;
     {
         typename C::R e, f;
-        load4(0, y, x0, e, f);
+        load4(z0, y, x0, e, f);
         decode4(e, f, cur);
-        load4(1, y, x0, ne, nf);
-        if (halo) load4(0, hy, hx0, he, hf);
+        load4(z0 + 1 < L ? z0 + 1 : 0, y, x0, ne, nf);
+        if (halo) load4(z0, hy, hx0, he, hf);
     }
     double e = 0.0;
-    for (int z = 0; z < L; ++z) {
+    for (int z = z0; z < z0 + Z; ++z) {
         const int b = z & 1;
         decode4(ne, nf, nxt);
         const int zn = z + 2 < L ? z + 2 : z + 2 - L;
@@ -583,23 +586,25 @@ __global__ __launch_bounds__(kBlock) void k_energy_stream(EnergyArgs a)
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < n_waves; ++w) t += red[w];
-        a.partials[rep * a.n_pb + band] = t;
+        a.partials[rep * a.n_pb + pb] = t;
     }
 }
 
-int64_t energy_partials(int L, int64_t n_pb_site)
+int64_t energy_partials(int L, int64_t n_rep, int64_t n_pb_site)
 {
     const int rows = kmode_rows(L);
-    return rows > 0 ? L / rows : n_pb_site;
+    return rows > 0 ? (int64_t)(L / rows) * march_slabs(L, n_rep) : n_pb_site;
 }
 
 hipError_t launch_energy(const EnergyArgs &a, int storage, hipStream_t s)
 {
     const int rows = kmode_rows(a.L);
     if (rows > 0) {
-        if (a.n_pb != a.L / rows) return hipErrorInvalidValue;  // one partial per band
-        const int64_t blocks = a.n_rep * (a.L / rows);
+        const int64_t parts = (int64_t)(a.L / rows) * march_slabs(a.L, a.n_rep);
+        if (a.n_pb != parts) return hipErrorInvalidValue;  // one partial per band and slab
+        const int64_t blocks = a.n_rep * parts;
         if (blocks == 0) return hipSuccess;
+        if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
         const unsigned threads = (unsigned)((rows * (a.L / 4) + 63) / 64 * 64);
         const size_t lds = (size_t)2 * 3 * (rows + 1) * a.L * sizeof(float);
         switch (storage) {
@@ -914,7 +919,10 @@ __global__ __launch_bounds__(128) void k_kmodes_finish(KmodeArgs a)
 // unweighted sum at the end. 45 float64 accumulators replace the 63 of the two
 // gathering passes, and both copies are read once instead of twice. The sums
 // run in another order than the gathering kernel's, so the two agree to
-// float64 rounding. A work-group's sums go to the partial of its band.
+// float64 rounding. A work-group's sums go to the partial of its band. (Unlike
+// the copy-pair and energy marches these take no z-slabs: their per-work-group
+// start, the phase tables and the reduction of 63 or 21 sums, cost more than
+// the extra work-groups gain, 593 against 631 us on the large workload.)
 template <int STORE>
 __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
 {
@@ -925,6 +933,8 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
     __shared__ double cph[224], sph[224];
     const int L = a.L, Lh = L >> 1, Q = L >> 2;
     const int TY = kmode_rows(L), n_bands = L / TY;
+    constexpr int z0 = 0;
+    const int Z = L;
     for (int r = threadIdx.x; r < L; r += blockDim.x) {
         double sv, cv;
         sincospi(2.0 * (double)r / (double)L, &sv, &cv);
@@ -932,7 +942,7 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
         sph[r] = sv;
     }
     const int64_t dk = blockIdx.x / n_bands;  // d * T + k
-    const int band = (int)(blockIdx.x - dk * n_bands);
+    const int pb = (int)(blockIdx.x - dk * n_bands), band = pb;
     const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
     const int64_t Nh = a.Nh;
     const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
@@ -952,7 +962,7 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
     };
     typename C::R ne[2], nf[2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) load4(c, 0, ne[c], nf[c]);
+    for (int c = 0; c < 2; ++c) load4(c, z0, ne[c], nf[c]);
     double A0[9], Ac[9], As[9], Zc[9], Zs[9];
 #pragma unroll
     for (int m = 0; m < 9; ++m) A0[m] = Ac[m] = As[m] = Zc[m] = Zs[m] = 0.0;
@@ -963,13 +973,13 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
         cx[u] = cph[x0 + u];
         sx[u] = sph[x0 + u];
     }
-    for (int z = 0; z < L; ++z) {
+    for (int z = z0; z < z0 + Z; ++z) {
         v3 s[2][4];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             C::decode_pair(ne[c], s[c][0], s[c][2]);
             C::decode_pair(nf[c], s[c][1], s[c][3]);
-            if (z + 1 < L) load4(c, z + 1, ne[c], nf[c]);
+            if (z + 1 < z0 + Z) load4(c, z + 1, ne[c], nf[c]);
         }
         if (active) {
             const double cz = cph[z], sz = sph[z];
@@ -1024,7 +1034,7 @@ __global__ __launch_bounds__(kBlock) void k_qk_stream(KmodeArgs a)
     for (int m = threadIdx.x; m < K; m += blockDim.x) {
         double v = 0.0;
         for (int w = 0; w < n_waves; ++w) v += red[w][m];
-        a.partials[(dk * a.n_pb + band) * 84 + m] = v;
+        a.partials[(dk * a.n_pb + pb) * 84 + m] = v;
     }
 }
 
@@ -1059,6 +1069,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_chiral_stream(KmodeArgs a)
     __shared__ double cph[224], sph[224];
     const int L = a.L, Lh = L >> 1, Q = L >> 2;
     const int TY = BANDED ? kmode_rows(L) : L, n_bands = L / TY, RL = (TY + 2) * L;
+    constexpr int z0 = 0;
+    const int Z = L;
     constexpr bool banded = BANDED;  // TY < L
     for (int r = threadIdx.x; r < L; r += blockDim.x) {
         double sv, cv;
@@ -1067,7 +1079,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_chiral_stream(KmodeArgs a)
         sph[r] = sv;
     }
     const int64_t dk = blockIdx.x / n_bands;  // d * T + k
-    const int band = (int)(blockIdx.x - dk * n_bands), y0 = band * TY;
+    const int pb = (int)(blockIdx.x - dk * n_bands), band = pb, y0 = band * TY;
     const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
     const int64_t Nh = a.Nh;
     const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
@@ -1108,12 +1120,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_chiral_stream(KmodeArgs a)
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         typename C::R e, f;
-        load4(c, L - 1, e, f);
+        load4(c, z0 == 0 ? L - 1 : z0 - 1, e, f);
         decode4(e, f, prv[c]);
-        load4(c, 0, e, f);
+        load4(c, z0, e, f);
         decode4(e, f, cur[c]);
-        load4(c, 1, ne[c], nf[c]);
-        if (BANDED && halo) load4r(c, 0, hy, hx0, he[c], hf[c]);
+        load4(c, z0 + 1 < L ? z0 + 1 : 0, ne[c], nf[c]);
+        if (BANDED && halo) load4r(c, z0, hy, hx0, he[c], hf[c]);
     }
     double P0[3], Pc[3], Ps[3], Zc[3], Zs[3];
 #pragma unroll
@@ -1135,7 +1147,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_chiral_stream(KmodeArgs a)
         cx[u] = cph[x0 + u];
         sx[u] = sph[x0 + u];
     }
-    for (int z = 0; z < L; ++z) {
+    for (int z = z0; z < z0 + Z; ++z) {
         const int b = z & 1;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -1232,7 +1244,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_chiral_stream(KmodeArgs a)
     for (int m = threadIdx.x; m < K; m += blockDim.x) {
         double v = 0.0;
         for (int w = 0; w < n_waves; ++w) v += red[w][m];
-        a.partials[(dk * a.n_pb + band) * 84 + KGroup<2>::first + m] = v;
+        a.partials[(dk * a.n_pb + pb) * 84 + KGroup<2>::first + m] = v;
     }
 }
 
@@ -1247,10 +1259,12 @@ static hipError_t launch_kmodes_s(const KmodeArgs &a, hipStream_t s)
     // in one pass, the chiral group in another
     const int rows = kmode_rows(a.L);
     if (rows > 0) {
-        if (a.n_pb != a.L / rows) return hipErrorInvalidValue;  // one partial per band
+        const int64_t parts = kmode_partials(a.L, 0);
+        if (a.n_pb != parts) return hipErrorInvalidValue;  // one partial per band
+        if ((int64_t)a.D * a.T * parts > 0x7FFFFFFFll) return hipErrorInvalidValue;
         const unsigned threads = (unsigned)((rows * (a.L / 4) + 63) / 64 * 64);
         const size_t lds = (size_t)2 * 2 * 3 * (rows + 2) * a.L * sizeof(float);
-        const dim3 cols((unsigned)((int64_t)a.D * a.T * (a.L / rows)));
+        const dim3 cols((unsigned)((int64_t)a.D * a.T * parts));
         hipLaunchKernelGGL((k_qk_stream<STORE>), cols, dim3(threads), 0, s, a);
         if (rows < a.L)
             hipLaunchKernelGGL((k_chiral_stream<STORE, true>), cols, dim3(threads), lds, s, a);
@@ -1397,7 +1411,8 @@ __global__ __launch_bounds__(256) void k_pair_overlaps_finish(PairOvArgs a)
 }
 
 // The copy-pair sums as a z-march where kmode_rows(L) > 0: one work-group per
-// (sample, rung, band of kmode_rows(L) rows) and copy pair (grid column y),
+// (sample, rung, band of kmode_rows(L) rows, z-slab of L / march_slabs(L, D T)
+// planes) and copy pair (grid column y),
 // the thread of row y and quarter q holding the sites x = 4q .. 4q + 3 of
 // plane z as z advances, the next plane's loads issued a step ahead. Per step
 // the thread forms the local overlaps s(a) . s(b) of its four sites in float64
@@ -1405,7 +1420,7 @@ __global__ __launch_bounds__(256) void k_pair_overlaps_finish(PairOvArgs a)
 // and sin kz; the k_y terms are cos ky and sin ky times the unweighted sum at
 // the end (x and y stay fixed per thread). Every spin is read once. The sums
 // run in another order than k_pair_overlaps', so the two agree to float64
-// rounding. A work-group's sums go to the partial of its band.
+// rounding. A work-group's sums go to the partial of its band and slab.
 template <int STORE>
 __global__ __launch_bounds__(kBlock) void k_pair_overlaps_stream(PairOvArgs a)
 {
@@ -1415,14 +1430,16 @@ __global__ __launch_bounds__(kBlock) void k_pair_overlaps_stream(PairOvArgs a)
     __shared__ double cph[224], sph[224];
     const int L = a.L, Lh = L >> 1, Q = L >> 2;
     const int TY = kmode_rows(L), n_bands = L / TY;
+    const int S = march_slabs(L, (int64_t)a.D * a.T), Z = L / S;
     for (int r = threadIdx.x; r < L; r += blockDim.x) {
         double sv, cv;
         sincospi(2.0 * (double)r / (double)L, &sv, &cv);
         cph[r] = cv;
         sph[r] = sv;
     }
-    const int64_t dk = blockIdx.x / n_bands;  // d * T + k
-    const int band = (int)(blockIdx.x - dk * n_bands);
+    const int64_t dk = blockIdx.x / (n_bands * S);  // d * T + k
+    const int pb = (int)(blockIdx.x - dk * n_bands * S);  // band * S + slab
+    const int band = pb / S, z0 = (pb - band * S) * Z;
     const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
     const int O = a.O, P = O * (O - 1) / 2, pair = (int)blockIdx.y;
     int ca = 0, cb = 1;  // the copies of this pair, in the order (0, 1), (0, 2), ..., (1, 2), ...
@@ -1450,7 +1467,7 @@ __global__ __launch_bounds__(kBlock) void k_pair_overlaps_stream(PairOvArgs a)
     };
     typename C::R ne[2], nf[2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) load4(c, 0, ne[c], nf[c]);
+    for (int c = 0; c < 2; ++c) load4(c, z0, ne[c], nf[c]);
     double A0 = 0.0, Ac = 0.0, As = 0.0, Zc = 0.0, Zs = 0.0;
     __syncthreads();  // the phase tables
     double cx[4], sx[4];
@@ -1459,13 +1476,13 @@ __global__ __launch_bounds__(kBlock) void k_pair_overlaps_stream(PairOvArgs a)
         cx[u] = cph[x0 + u];
         sx[u] = sph[x0 + u];
     }
-    for (int z = 0; z < L; ++z) {
+    for (int z = z0; z < z0 + Z; ++z) {
         v3 s[2][4];
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             C::decode_pair(ne[c], s[c][0], s[c][2]);
             C::decode_pair(nf[c], s[c][1], s[c][3]);
-            if (z + 1 < L) load4(c, z + 1, ne[c], nf[c]);
+            if (z + 1 < z0 + Z) load4(c, z + 1, ne[c], nf[c]);
         }
         if (active) {
             double t0 = 0.0, tc = 0.0, ts = 0.0;
@@ -1497,11 +1514,17 @@ __global__ __launch_bounds__(kBlock) void k_pair_overlaps_stream(PairOvArgs a)
     if (threadIdx.x < 7) {
         double t = 0.0;
         for (int w = 0; w < n_waves; ++w) t += red[w][threadIdx.x];
-        a.partials[(dk * a.n_pb + band) * (int64_t)(7 * P) + 7 * pair + threadIdx.x] = t;
+        a.partials[(dk * a.n_pb + pb) * (int64_t)(7 * P) + 7 * pair + threadIdx.x] = t;
     }
 }
 
-int64_t march_partials(int L, int64_t q_pb)
+int64_t march_partials(int L, int64_t n_items, int64_t q_pb)
+{
+    const int rows = kmode_rows(L);
+    return rows > 0 ? (int64_t)(L / rows) * march_slabs(L, n_items) : q_pb;
+}
+
+int64_t kmode_partials(int L, int64_t q_pb)
 {
     const int rows = kmode_rows(L);
     return rows > 0 ? L / rows : q_pb;
@@ -1512,8 +1535,9 @@ hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s)
     const int P = a.O * (a.O - 1) / 2;
     const int rows = kmode_rows(a.L);
     if (rows > 0) {
-        if (a.n_pb != a.L / rows) return hipErrorInvalidValue;  // one partial per band
-        const int64_t blocks = (int64_t)a.D * a.T * (a.L / rows);
+        const int64_t parts = march_partials(a.L, (int64_t)a.D * a.T, 0);
+        if (a.n_pb != parts) return hipErrorInvalidValue;  // one partial per band and slab
+        const int64_t blocks = (int64_t)a.D * a.T * parts;
         if (blocks == 0 || P == 0) return hipSuccess;
         if (blocks > 0x7FFFFFFFll || P > 65535) return hipErrorInvalidValue;
         const dim3 grid((unsigned)blocks, (unsigned)P), block((unsigned)((rows * (a.L / 4) + 63) / 64 * 64));
