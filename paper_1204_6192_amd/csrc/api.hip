@@ -291,7 +291,7 @@ hsg_status build_layout(const hsg_desc *desc, Layout &lay)
         const uint64_t e_sweep = (uint64_t)g.n_rep * (g.n_pb_sweep > n_pb_stream ? g.n_pb_sweep : n_pb_stream) * 8;
         const int64_t e_pb = hsg::energy_partials(g.L, g.n_rep, g.n_pb_site);
         const uint64_t e_full = (uint64_t)g.n_rep * (e_pb > g.n_pb_site ? e_pb : g.n_pb_site) * 8;
-        const uint64_t q_full = (uint64_t)g.D * g.T * g.q_pb * 9 * 8;
+        const uint64_t q_full = (uint64_t)g.D * g.T * hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb) * 9 * 8;
         // k modes and copy pairs: the overlap's blocks, or one partial per band of the z-marches
         const int64_t k_pb = hsg::kmode_partials(g.L, g.q_pb);
         const int64_t p_pb = hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb);
@@ -808,7 +808,8 @@ hsg_status run_series(hsg_lattice *h, hipStream_t s)
             a.D = g.D;
             a.O = g.O;
             a.T = g.T;
-            a.n_pb = g.q_pb;
+            a.L = g.L;
+            a.n_pb = (int32_t)hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb);
             a.chunk = g.q_chunk;
             e = hsg::launch_overlap(a, h->storage, s);
         }
@@ -1458,7 +1459,8 @@ hsg_status hsg_measure_overlap(hsg_lattice *h, double *d_q, hsg_stream_t stream)
         a.D = g.D;
         a.O = g.O;
         a.T = g.T;
-        a.n_pb = g.q_pb;
+        a.L = g.L;
+        a.n_pb = (int32_t)hsg::march_partials(g.L, (int64_t)g.D * g.T, g.q_pb);
         a.chunk = g.q_chunk;
         const hipError_t e = hsg::launch_overlap(a, h->storage, S(stream));
         if (e != hipSuccess) return hip_fail(e, "measure_overlap");

@@ -201,7 +201,10 @@ struct OverlapArgs {
     double *q;
     int64_t Nh;
     int32_t D, O, T, n_pb, chunk;
+    int32_t L;
 };
+// Where kmode_rows(L) > 0 a z-march runs instead (k_overlap_stream): partial pb
+// is z-slab pb % S of band pb / S, and n_pb must be march_partials(L, D T, .).
 hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s);
 
 // Wave-vector dependent and chiral overlaps: partials [D T][n_pb][84], q [D T][84].
@@ -277,7 +280,8 @@ struct SeriesArgs {
 };
 hipError_t launch_series(const SeriesArgs &a, hipStream_t s);
 hipError_t launch_pair_overlaps(const PairOvArgs &a, int storage, hipStream_t s);
-// The partials per (sample, rung) that launch_pair_overlaps expects (n_pb): one
+// The partials per (sample, rung) that launch_pair_overlaps and launch_overlap
+// expect (n_pb): one
 // per band and z-slab of the z-march where kmode_rows(L) > 0
 // (march_slabs(L, D T)), else the overlap's work-groups (q_pb).
 int64_t march_partials(int L, int64_t n_items, int64_t q_pb);

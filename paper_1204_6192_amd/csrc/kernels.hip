@@ -672,6 +672,81 @@ __global__ __launch_bounds__(kBlock) void k_overlap(OverlapArgs a)
             (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
 }
 
+// The same sums as a z-march where kmode_rows(L) > 0: one work-group per
+// (sample, rung, band of kmode_rows(L) rows, z-slab of L / march_slabs(L, D T)
+// planes), the thread of row y and quarter q holding the sites x = 4q .. 4q + 3
+// of plane z as z advances, the next plane's loads issued a step ahead; every
+// spin is read once, with 32-bit offsets and no coordinate arithmetic per site.
+// The sums run in another order than k_overlap's, so the two agree to float64
+// rounding. A work-group's sums go to the partial of its band and slab.
+template <int STORE>
+__global__ __launch_bounds__(kBlock) void k_overlap_stream(OverlapArgs a)
+{
+    using C = Codec<STORE>;
+    using T = typename C::T;
+    __shared__ double red[4][9];
+    const int L = a.L, Lh = L >> 1, Q = L >> 2;
+    const int TY = kmode_rows(L), n_bands = L / TY;
+    const int S = march_slabs(L, (int64_t)a.D * a.T), Z = L / S;
+    const int64_t dk = blockIdx.x / (n_bands * S);  // d * T + k
+    const int pb = (int)(blockIdx.x - dk * n_bands * S);  // band * S + slab
+    const int band = pb / S, z0 = (pb - band * S) * Z;
+    const int d = (int)(dk / a.T), k = (int)(dk - (int64_t)d * a.T);
+    const int64_t Nh = a.Nh;
+    const int32_t sa = a.slot_at_temp[((int64_t)d * a.O + 0) * a.T + k];
+    const int32_t sb = a.slot_at_temp[((int64_t)d * a.O + 1) * a.T + k];
+    const T *R[2] = {(const T *)a.spins + (((int64_t)d * a.O + 0) * a.T + sa) * 2 * C::kPlanes * Nh,
+                     (const T *)a.spins + (((int64_t)d * a.O + 1) * a.T + sb) * 2 * C::kPlanes * Nh};
+    const int tid = threadIdx.x;
+    const bool active = tid < TY * Q;
+    const int y = band * TY + (active ? tid / Q : 0), x0 = active ? 4 * (tid - (tid / Q) * Q) : 0;
+    // the four sites of plane zz of copy c: x0 and x0 + 2 on the parity of
+    // y + zz (half-indices x0 / 2, x0 / 2 + 1), x0 + 1 and x0 + 3 on the other
+    auto load4 = [&](int c, int zz, typename C::R &e, typename C::R &f) {
+        const int p0 = (y + zz) & 1;
+        const uint32_t jj = (uint32_t)((zz * L + y) * Lh + (x0 >> 1));
+        C::load_raw_pair(R[c] + (int64_t)p0 * C::kPlanes * Nh, (uint32_t)Nh, jj, e);
+        C::load_raw_pair(R[c] + (int64_t)(1 - p0) * C::kPlanes * Nh, (uint32_t)Nh, jj, f);
+    };
+    typename C::R ne[2], nf[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) load4(c, z0, ne[c], nf[c]);
+    double acc[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) acc[m] = 0.0;
+    for (int z = z0; z < z0 + Z; ++z) {
+        v3 s[2][4];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            C::decode_pair(ne[c], s[c][0], s[c][2]);
+            C::decode_pair(nf[c], s[c][1], s[c][3]);
+            if (z + 1 < z0 + Z) load4(c, z + 1, ne[c], nf[c]);
+        }
+        if (active) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double xa[3] = {s[0][u].x, s[0][u].y, s[0][u].z}, ya[3] = {s[1][u].x, s[1][u].y, s[1][u].z};
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+#pragma unroll
+                    for (int n = 0; n < 3; ++n) acc[3 * m + n] += xa[m] * ya[n];
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, n_waves = (int)(blockDim.x >> 6);
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        const double v = wave_sum(acc[m]);
+        if (lane == 0) red[wave][m] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double t = 0.0;
+        for (int w = 0; w < n_waves; ++w) t += red[w][threadIdx.x];
+        a.partials[(dk * a.n_pb + pb) * 9 + threadIdx.x] = t;
+    }
+}
+
 __global__ __launch_bounds__(64) void k_overlap_finish(OverlapArgs a)
 {
     const int64_t dk = blockIdx.x;
@@ -692,12 +767,26 @@ hipError_t launch_overlap(const OverlapArgs &a, int storage, hipStream_t s)
 {
     const int64_t blocks = (int64_t)a.D * a.T * a.n_pb;
     if (blocks == 0) return hipSuccess;
-    switch (storage) {
-    case 0: hipLaunchKernelGGL(k_overlap<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_overlap<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_overlap<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
-    case 3: hipLaunchKernelGGL(k_overlap<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
-    default: return hipErrorInvalidValue;
+    const int rows = kmode_rows(a.L);
+    if (rows > 0) {
+        if (a.n_pb != march_partials(a.L, (int64_t)a.D * a.T, 0)) return hipErrorInvalidValue;
+        if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)blocks), block((unsigned)((rows * (a.L / 4) + 63) / 64 * 64));
+        switch (storage) {
+        case 0: hipLaunchKernelGGL(k_overlap_stream<0>, grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_overlap_stream<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_overlap_stream<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_overlap_stream<3>, grid, block, 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (storage) {
+        case 0: hipLaunchKernelGGL(k_overlap<0>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+        case 1: hipLaunchKernelGGL(k_overlap<1>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_overlap<2>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_overlap<3>, dim3((unsigned)blocks), dim3(kBlock), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -735,14 +735,19 @@ def test_fused_kernels_full_size_resync(hsg, oracle_lib, storage):
             assert np.allclose(E[d:d + 1], o.compute_energies(), rtol=1e-11, atol=1e-9)
 
 
-@pytest.mark.parametrize("storage", ["f16", "bf16", "qangle"])
+@pytest.mark.parametrize("storage", ["f16", "bf16", "qangle", "f32"])
 def test_overlap_compressed_against_oracle(hsg, oracle_lib, storage):
     """The overlap of Eq. (5) on compressed spins (decoded and renormalised as the
-    kernels read them), two lattice sizes, after sweeps with tempering: equal to
-    the oracle's on the same decoded configurations to 1e-12."""
+    kernels read them) and on float32 spins, five lattice sizes, after sweeps
+    with tempering: equal to the oracle's on the same decoded configurations to
+    1e-12. L = 6 takes the gathering kernel, L = 8 and 12 the z-march over whole
+    planes, L = 36 and 48 the z-march over bands and z-slabs."""
     rng = np.random.Generator(np.random.Philox(inputs.INSTANCE_SEED_BASE + 53))
     groups = [inputs.make_group(rng, 8, 2, 2, inputs.geometric_ladder(0.1, 0.3, 4)),
               inputs.make_group(rng, 12, 1, 2, inputs.geometric_ladder(0.1, 0.3, 3), sample_uid_base=2)]
+    for L in (6, 36, 48):
+        groups.append(inputs.make_group(rng, L, 1, 2, inputs.geometric_ladder(0.1, 0.3, 3),
+                                        sample_uid_base=len(groups) + 2))
     seed = inputs.PHILOX_KEY_BASE + 53
     lat = _lat(hsg, groups, seed, storage=storage)
     lat.sweep(3)
